@@ -1,0 +1,272 @@
+/*
+ * Reference oracle for the exact Gaussian log-likelihood with a Matérn
+ * covariance (ExaGeoStat, arXiv 1708.02835).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product library calls, links or
+ * includes this file; only the test-suite, the smoke check and the CPU
+ * baseline leg of the benchmark load it.  It shares no code, header, table or
+ * helper with the HIP implementation.
+ *
+ * Everything is plain, single-threaded IEEE binary64 C, compiled without
+ * fused multiply-add contraction and without fast-math, written to be checked
+ * against the paper by eye:
+ *
+ *   - Matérn covariance, Sec. 2.2 Eq. (2):
+ *       C(r; θ) = θ1 / (2^(θ3-1) Γ(θ3)) · (r/θ2)^θ3 · K_θ3(r/θ2),  C(0) = θ1.
+ *     The modified Bessel function of the second kind is taken from its
+ *     integral representation K_ν(x) = ∫_0^∞ exp(-x cosh t) cosh(ν t) dt
+ *     (DLMF 10.32.9), evaluated with the trapezoidal rule.  The paper names
+ *     K_ν but gives no algorithm for it.
+ *   - Cholesky factorisation Σ = L Lᵀ (Sec. 5.4, Alg. 2 step "dpotrf"),
+ *     unblocked, row by row (Cholesky–Banachiewicz).
+ *   - Forward substitution L w = Z (Alg. 2, "dtrsm").
+ *   - log|Σ| = 2 Σ_i log L_ii (Sec. 5.1) and the dot product wᵀw (Alg. 2),
+ *     both with Neumaier-compensated summation.
+ *   - l(θ) = -n/2 log(2π) - ½ log|Σ| - ½ wᵀw (Sec. 2 Eq. (1), Alg. 2 last step).
+ *   - Kriging Z1 = Σ12 Σ22⁻¹ Z2 (Sec. 2.3 Eq. (5), Alg. 3).
+ *   - Synthetic field Z = L e (Sec. 5.3, Alg. 1).
+ *
+ * Matrices are dense row-major n×n arrays owned by the caller.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* ---------------------------------------------------------------- K_ν ---- */
+
+/*
+ * e^x K_ν(x) = ∫_0^∞ exp(-x (cosh t - 1)) cosh(ν t) dt.
+ *
+ * The integrand is analytic and decays double-exponentially, so the
+ * trapezoidal rule converges geometrically in 1/h (Trefethen & Weideman,
+ * SIAM Review 56 (2014)).  For large x the integrand is a narrow bump of width
+ * about 1/sqrt(x) around t = 0, so the step shrinks like 1/sqrt(x).  All terms
+ * are positive: no cancellation.  The sum stops once a term is below e^-745
+ * relative to the first one and t is past the bump.
+ */
+double oracle_bessel_k_scaled(double nu, double x)
+{
+    double h = 0.08;
+    if (x > 0.0 && 0.4 / sqrt(x) < h) h = 0.4 / sqrt(x);
+    double sum = 0.5; /* t = 0: exp(0) * cosh(0), trapezoid half weight */
+    for (long k = 1;; ++k) {
+        double t = (double)k * h;
+        double e = -x * (cosh(t) - 1.0);
+        if (e + nu * t < -745.0 && t > 1.0) break;
+        sum += exp(e) * cosh(nu * t);
+    }
+    return h * sum;
+}
+
+double oracle_bessel_k(double nu, double x)
+{
+    return exp(-x) * oracle_bessel_k_scaled(nu, x);
+}
+
+/* Matérn covariance at distance r, Sec. 2.2 Eq. (2). */
+double oracle_matern(double r, double theta1, double theta2, double theta3)
+{
+    if (r == 0.0) return theta1; /* limit of x^ν K_ν(x) as x → 0 is 2^(ν-1) Γ(ν) */
+    double x = r / theta2;
+    double pref = theta1 / (pow(2.0, theta3 - 1.0) * tgamma(theta3));
+    /* (x^ν e^-x) is formed as one exponential so large x underflows cleanly */
+    return pref * exp(theta3 * log(x) - x) * oracle_bessel_k_scaled(theta3, x);
+}
+
+/* Euclidean distance between two points of the plane (Sec. 2, d = 2). */
+static double dist2d(double x1, double y1, double x2, double y2)
+{
+    double dx = x1 - x2, dy = y1 - y2;
+    return sqrt(dx * dx + dy * dy);
+}
+
+/* Dense n1×n2 row-major covariance between point sets 1 and 2
+ * (genDistanceMatrix followed by genCovMatrix in Alg. 1-3). */
+void oracle_cov_matrix(const double *x1, const double *y1, int64_t n1,
+                       const double *x2, const double *y2, int64_t n2,
+                       double theta1, double theta2, double theta3, double *out)
+{
+    for (int64_t i = 0; i < n1; ++i)
+        for (int64_t j = 0; j < n2; ++j)
+            out[i * n2 + j] = oracle_matern(dist2d(x1[i], y1[i], x2[j], y2[j]),
+                                            theta1, theta2, theta3);
+}
+
+/* Symmetric n×n covariance: lower triangle evaluated, mirrored above. */
+void oracle_cov_symmetric(const double *x, const double *y, int64_t n,
+                          double theta1, double theta2, double theta3, double *out)
+{
+    for (int64_t i = 0; i < n; ++i)
+        for (int64_t j = 0; j <= i; ++j) {
+            double v = oracle_matern(dist2d(x[i], y[i], x[j], y[j]), theta1, theta2, theta3);
+            out[i * n + j] = v;
+            out[j * n + i] = v;
+        }
+}
+
+/* ------------------------------------------------------------ Cholesky ---- */
+
+/*
+ * In-place Cholesky–Banachiewicz on a row-major n×n array: on return the lower
+ * triangle holds L with Σ = L Lᵀ; the strict upper triangle is set to zero.
+ * Returns 0, or j+1 when the j-th pivot (0-based) is not positive — the
+ * LAPACK dpotrf "info" convention.
+ */
+int64_t oracle_cholesky(double *a, int64_t n)
+{
+    for (int64_t i = 0; i < n; ++i) {
+        double *li = a + i * n;
+        for (int64_t j = 0; j <= i; ++j) {
+            const double *lj = a + j * n;
+            double s = li[j];
+            for (int64_t k = 0; k < j; ++k) s -= li[k] * lj[k];
+            if (i == j) {
+                if (!(s > 0.0)) return j + 1;
+                li[j] = sqrt(s);
+            } else {
+                li[j] = s / lj[j];
+            }
+        }
+        for (int64_t j = i + 1; j < n; ++j) li[j] = 0.0;
+    }
+    return 0;
+}
+
+/* L w = z, L lower triangular row-major. */
+void oracle_forward(const double *l, int64_t n, const double *z, double *w)
+{
+    for (int64_t i = 0; i < n; ++i) {
+        double s = z[i];
+        for (int64_t k = 0; k < i; ++k) s -= l[i * n + k] * w[k];
+        w[i] = s / l[i * n + i];
+    }
+}
+
+/* Lᵀ v = w, L lower triangular row-major. */
+void oracle_backward(const double *l, int64_t n, const double *w, double *v)
+{
+    for (int64_t i = n - 1; i >= 0; --i) {
+        double s = w[i];
+        for (int64_t k = i + 1; k < n; ++k) s -= l[k * n + i] * v[k];
+        v[i] = s / l[i * n + i];
+    }
+}
+
+/* z = L e, L lower triangular row-major (Alg. 1, "dtrmm"). */
+void oracle_trmv(const double *l, int64_t n, const double *e, double *z)
+{
+    for (int64_t i = 0; i < n; ++i) {
+        double s = 0.0;
+        for (int64_t k = 0; k <= i; ++k) s += l[i * n + k] * e[k];
+        z[i] = s;
+    }
+}
+
+/* Neumaier's compensated sum. */
+static double neumaier_sum(const double *v, int64_t n)
+{
+    double s = 0.0, c = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+        double t = s + v[i];
+        if (fabs(s) >= fabs(v[i])) c += (s - t) + v[i];
+        else c += (v[i] - t) + s;
+        s = t;
+    }
+    return s + c;
+}
+
+/* log|Σ| = 2 Σ log L_ii, summed as logs (Sec. 5.1 reads "product of the
+ * diagonal"; the product itself under/overflows at realistic n). */
+double oracle_logdet(const double *l, int64_t n)
+{
+    double *t = (double *)malloc((size_t)(n > 0 ? n : 1) * sizeof(double));
+    for (int64_t i = 0; i < n; ++i) t[i] = 2.0 * log(l[i * n + i]);
+    double r = neumaier_sum(t, n);
+    free(t);
+    return r;
+}
+
+double oracle_dot(const double *w, int64_t n)
+{
+    double *t = (double *)malloc((size_t)(n > 0 ? n : 1) * sizeof(double));
+    for (int64_t i = 0; i < n; ++i) t[i] = w[i] * w[i];
+    double r = neumaier_sum(t, n);
+    free(t);
+    return r;
+}
+
+/*
+ * l(θ) by Alg. 2: Σ(θ) → L → w = L⁻¹ Z → logdet, wᵀw → l.
+ * out[0] = l, out[1] = log|Σ|, out[2] = Zᵀ Σ⁻¹ Z.  Returns the Cholesky info
+ * (0 on success); on failure out[0] = -inf and out[1], out[2] are NaN.
+ * When l_out is not NULL the factor (row-major n×n) is copied there.
+ */
+int64_t oracle_loglik(const double *x, const double *y, const double *z, int64_t n,
+                      double theta1, double theta2, double theta3, double *out,
+                      double *l_out)
+{
+    double *a = (double *)malloc((size_t)n * (size_t)n * sizeof(double));
+    double *w = (double *)malloc((size_t)n * sizeof(double));
+    oracle_cov_symmetric(x, y, n, theta1, theta2, theta3, a);
+    int64_t info = oracle_cholesky(a, n);
+    if (info != 0) {
+        out[0] = -INFINITY;
+        out[1] = NAN;
+        out[2] = NAN;
+    } else {
+        oracle_forward(a, n, z, w);
+        double logdet = oracle_logdet(a, n);
+        double quad = oracle_dot(w, n);
+        out[0] = -0.5 * quad - 0.5 * logdet - 0.5 * (double)n * log(2.0 * M_PI);
+        out[1] = logdet;
+        out[2] = quad;
+    }
+    if (l_out) memcpy(l_out, a, (size_t)n * (size_t)n * sizeof(double));
+    free(a);
+    free(w);
+    return info;
+}
+
+/*
+ * Kriging, Sec. 2.3 Eq. (5) with Alg. 3: X = Σ22⁻¹ Z2 through the Cholesky
+ * factor (forward then backward substitution), then Z1 = Σ12 X.
+ * Returns the Cholesky info.
+ */
+int64_t oracle_krige(const double *x, const double *y, const double *z, int64_t n,
+                     const double *xn, const double *yn, int64_t m,
+                     double theta1, double theta2, double theta3, double *znew)
+{
+    double *a = (double *)malloc((size_t)n * (size_t)n * sizeof(double));
+    double *w = (double *)malloc((size_t)n * sizeof(double));
+    double *v = (double *)malloc((size_t)n * sizeof(double));
+    oracle_cov_symmetric(x, y, n, theta1, theta2, theta3, a);
+    int64_t info = oracle_cholesky(a, n);
+    if (info == 0) {
+        oracle_forward(a, n, z, w);
+        oracle_backward(a, n, w, v);
+        for (int64_t k = 0; k < m; ++k) {
+            double s = 0.0;
+            for (int64_t j = 0; j < n; ++j)
+                s += oracle_matern(dist2d(xn[k], yn[k], x[j], y[j]), theta1, theta2, theta3) * v[j];
+            znew[k] = s;
+        }
+    }
+    free(a);
+    free(w);
+    free(v);
+    return info;
+}
+
+/* Synthetic measurements, Sec. 5.3 Alg. 1: Σ(θ) = L Lᵀ, Z = L e.
+ * Returns the Cholesky info. */
+int64_t oracle_synth(const double *x, const double *y, const double *e, int64_t n,
+                     double theta1, double theta2, double theta3, double *z)
+{
+    double *a = (double *)malloc((size_t)n * (size_t)n * sizeof(double));
+    oracle_cov_symmetric(x, y, n, theta1, theta2, theta3, a);
+    int64_t info = oracle_cholesky(a, n);
+    if (info == 0) oracle_trmv(a, n, e, z);
+    free(a);
+    return info;
+}

@@ -1,0 +1,126 @@
+"""Planted-mistake check for the oracle's pins.
+
+Each case copies the oracle source, plants one plausible mistake (a dropped
+term, a flipped sign, a wrong index, a transposed operand, a wrong constant),
+compiles the copy to a temporary library on the CPU and runs a few of the
+independent pins against it.  Every mutant must fail at least one pin; the
+unmodified source must pass all of them.  Nothing here touches the GPU.
+"""
+import ctypes
+import math
+import os
+import subprocess
+
+import numpy as np
+import pytest
+import scipy.linalg as sla
+
+import geoinputs
+
+SRC = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "oracle", "oracle.c")
+
+MUTANTS = {
+    "none": None,
+    "cholesky_sign": ("s -= li[k] * lj[k];", "s += li[k] * lj[k];"),
+    "cholesky_index": ("s -= li[k] * lj[k];", "s -= li[k] * li[k];"),
+    "forward_transposed": ("s -= l[i * n + k] * w[k];", "s -= l[k * n + i] * w[k];"),
+    "logdet_factor": ("t[i] = 2.0 * log(l[i * n + i]);", "t[i] = log(l[i * n + i]);"),
+    "loglik_dropped_term": ("out[0] = -0.5 * quad - 0.5 * logdet - 0.5 * (double)n * log(2.0 * M_PI);",
+                            "out[0] = -0.5 * quad - 0.5 * (double)n * log(2.0 * M_PI);"),
+    "matern_gamma": ("tgamma(theta3)", "tgamma(theta3 + 1.0)"),
+    "matern_power": ("pow(2.0, theta3 - 1.0)", "pow(2.0, theta3)"),
+    "bessel_nu": ("cosh(nu * t);", "cosh(0.5 * nu * t);"),
+    "bessel_halfweight": ("double sum = 0.5;", "double sum = 1.0;"),
+    "distance_sign": ("double dx = x1 - x2, dy = y1 - y2;", "double dx = x1 - x2, dy = y1 + y2;"),
+    "krige_backward_skipped": ("oracle_backward(a, n, w, v);", "memcpy(v, w, (size_t)n * sizeof(double));"),
+    "trmv_upper": ("for (int64_t k = 0; k <= i; ++k) s += l[i * n + k] * e[k];",
+                   "for (int64_t k = 0; k <= i; ++k) s += l[k * n + i] * e[k];"),
+}
+
+
+def _build(tmp_path, name, mutation):
+    src = open(SRC).read()
+    if mutation is not None:
+        old, new = mutation
+        assert src.count(old) >= 1, name
+        src = src.replace(old, new, 1)
+    c = tmp_path / f"{name}.c"
+    so = tmp_path / f"{name}.so"
+    c.write_text(src)
+    subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fPIC", "-shared", "-std=c11",
+                           "-D_GNU_SOURCE", str(c), "-o", str(so), "-lm"])
+    lib = ctypes.CDLL(str(so))
+    D, I64, P = ctypes.c_double, ctypes.c_int64, ctypes.c_void_p
+    lib.oracle_matern.restype = D
+    lib.oracle_matern.argtypes = [D, D, D, D]
+    lib.oracle_loglik.restype = I64
+    lib.oracle_loglik.argtypes = [P, P, P, I64, D, D, D, P, P]
+    lib.oracle_krige.restype = I64
+    lib.oracle_krige.argtypes = [P, P, P, I64, P, P, I64, D, D, D, P]
+    lib.oracle_synth.restype = I64
+    lib.oracle_synth.argtypes = [P, P, P, I64, D, D, D, P]
+    return lib
+
+
+def _p(a):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _pins(lib):
+    """Returns the list of failed pin names."""
+    failed = []
+    # Matérn closed forms (Sec. 2.2)
+    for r, t2 in [(0.05, 0.1), (0.3, 0.2)]:
+        x = r / t2
+        if abs(lib.oracle_matern(r, 1.3, t2, 0.5) - 1.3 * math.exp(-x)) > 1e-14:
+            failed.append("matern_exp")
+        if abs(lib.oracle_matern(r, 1.3, t2, 1.5) - 1.3 * (1 + x) * math.exp(-x)) > 1e-14:
+            failed.append("matern_32")
+    # l(θ) vs eigendecomposition on a jittered grid
+    n = 40
+    theta = (1.1, 0.15, 1.5)
+    x, y = geoinputs.jittered_grid(n, 7)
+    z = geoinputs.normal_vector(n, 7)
+    a = np.empty((n, n))
+    for i in range(n):
+        for j in range(n):
+            dx, dy = x[i] - x[j], y[i] - y[j]
+            rr = math.sqrt(dx * dx + dy * dy) / theta[1]
+            a[i, j] = theta[0] * (1 + rr) * math.exp(-rr)
+    lam, u = np.linalg.eigh(a)
+    ref_ld = float(np.sum(np.log(lam)))
+    ref_q = float(np.sum((u.T @ z) ** 2 / lam))
+    ref_l = -0.5 * n * math.log(2 * math.pi) - 0.5 * ref_ld - 0.5 * ref_q
+    out = np.zeros(3)
+    lib.oracle_loglik(_p(x), _p(y), _p(z), n, *theta, _p(out), None)
+    if not abs(out[0] - ref_l) <= 1e-9 * abs(ref_l):
+        failed.append("loglik_eig")
+    # kriging vs dense solve
+    xn, yn = geoinputs.uniform_points(4, 7)
+    zn = np.zeros(4)
+    lib.oracle_krige(_p(x), _p(y), _p(z), n, _p(xn), _p(yn), 4, *theta, _p(zn))
+    s12 = np.empty((4, n))
+    for k in range(4):
+        for j in range(n):
+            dx, dy = xn[k] - x[j], yn[k] - y[j]
+            rr = math.sqrt(dx * dx + dy * dy) / theta[1]
+            s12[k, j] = theta[0] * (1 + rr) * math.exp(-rr)
+    if not np.allclose(zn, s12 @ np.linalg.solve(a, z), rtol=1e-8, atol=1e-10):
+        failed.append("krige_dense")
+    # synth vs LAPACK factor
+    e = geoinputs.normal_vector(n, 8)
+    zs = np.zeros(n)
+    lib.oracle_synth(_p(x), _p(y), _p(e), n, *theta, _p(zs))
+    if not np.allclose(zs, sla.cholesky(a, lower=True) @ e, rtol=1e-9, atol=1e-10):
+        failed.append("synth_lapack")
+    return failed
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_mutant_is_caught(tmp_path, name):
+    lib = _build(tmp_path, name, MUTANTS[name])
+    failed = _pins(lib)
+    if name == "none":
+        assert failed == []
+    else:
+        assert failed, f"planted mistake {name} passed every pin"
