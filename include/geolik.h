@@ -1,0 +1,230 @@
+/*
+ * geolik — exact Gaussian log-likelihood of a Matérn random field on one
+ * AMD Instinct MI355X (gfx950), after ExaGeoStat (Abdulah et al., arXiv
+ * 1708.02835).
+ *
+ * C ABI.  All pointers are DEVICE pointers (HIP global memory on the
+ * context's device) unless the name ends in `_h` (host memory).  `stream` is
+ * a `hipStream_t` passed as `void*` (NULL = the legacy default stream).  Every
+ * vector is float64, contiguous, and owned by the caller unless stated.
+ *
+ * Return value of every `int` function: a gl_status.  Negative values are
+ * usage or system errors (nothing was computed, or the result is unusable);
+ * positive values are numerical outcomes.
+ *
+ * Threading: the direct calls (matern_generate, loglik_eval, krige_predict,
+ * synth_generate) are stream-ordered and may not be called concurrently on
+ * one context.  The lq_* request-queue calls are thread-safe.
+ */
+#ifndef GEOLIK_H
+#define GEOLIK_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct gl_context gl_context;
+typedef struct gl_factor gl_factor;
+typedef struct lq_queue lq_queue;
+
+/* Matérn parameters, Sec. 2.2 Eq. (2): variance θ1 > 0, range θ2 > 0,
+ * smoothness θ3 > 0 (at most 50). */
+typedef struct {
+    double theta1;
+    double theta2;
+    double theta3;
+} gl_theta;
+
+typedef enum {
+    GL_OK = 0,
+    GL_NOT_SPD = 1,     /* Σ(θ) is not numerically positive definite; see gl_result.info */
+    GL_EINVAL = -1,     /* bad argument (θ_i <= 0, n < 1, NULL pointer, bad option) */
+    GL_ENOMEM = -2,     /* device allocation failed or the HBM budget is exceeded */
+    GL_EHIP = -3,       /* a HIP runtime call failed */
+    GL_EBUSY = -4,      /* lq_poll: request still pending */
+    GL_ECANCELED = -5,  /* request cancelled or queue destroyed */
+    GL_ETIMEDOUT = -6,  /* lq_wait: timeout elapsed */
+    GL_ENODEV = -7      /* no usable gfx950 device */
+} gl_status;
+
+typedef enum {
+    GL_FP64 = 0,        /* every tile and every update in binary64 */
+    GL_MIXED_FP32 = 1,  /* off-band trailing updates in binary32 on MFMA */
+    GL_MIXED_BF16 = 2   /* far off-band updates in bfloat16 (fp32 accumulate), others as MIXED_FP32 */
+} gl_precision;
+
+/* Options of one likelihood evaluation.  Fill with gl_opts_default(). */
+typedef struct {
+    int32_t precision;   /* gl_precision */
+    int32_t tile;        /* tile size b: 0 = automatic, else 128, 256, 384 or 512 */
+    int32_t keep_factor; /* 1: return the Cholesky factor in gl_result.factor for kriging */
+    int32_t band;        /* mixed modes: tiles with i - j < band stay binary64 (>= 1) */
+    double tol32;        /* mixed modes: off-band tile stays binary64 when its Frobenius norm
+                            exceeds tol32 * ||Σ||_F / NT */
+    double tolbf16;      /* GL_MIXED_BF16: tile uses binary32 (not bfloat16) when its norm
+                            exceeds tolbf16 * ||Σ||_F / NT */
+} gl_opts;
+
+/* Result of one likelihood evaluation, host memory. */
+typedef struct {
+    double loglik;      /* l(θ), Eq. (1); -INFINITY when status == GL_NOT_SPD */
+    double logdet;      /* log|Σ(θ)| = 2 Σ log L_ii */
+    double quad;        /* Zᵀ Σ(θ)⁻¹ Z = wᵀw, w = L⁻¹ Z */
+    int64_t info;       /* 0, or the 1-based global column of the first non-positive pivot */
+    int32_t status;     /* gl_status of the evaluation */
+    int32_t tile;       /* tile size used */
+    gl_factor *factor;  /* owned factor when keep_factor = 1 and status == GL_OK, else NULL */
+} gl_result;
+
+/* ------------------------------------------------------------ context ---- */
+
+/* Create a context on HIP device `device`.  `hbm_budget_bytes` caps the device
+ * memory the library holds for factors and workspaces (0 = 90% of the free
+ * memory at creation).  Errors: GL_EINVAL (out == NULL), GL_ENODEV, GL_EHIP. */
+int gl_context_create(int device, size_t hbm_budget_bytes, gl_context **out);
+
+/* Release every workspace and factor still held.  The caller must not use
+ * factors or queues of this context afterwards. */
+void gl_context_destroy(gl_context *ctx);
+
+/* Fill *opts with defaults: FP64, automatic tile, no factor kept, band 2,
+ * tol32 = 1e-2, tolbf16 = 1e-4. */
+void gl_opts_default(gl_opts *opts);
+
+/* Static English description of a gl_status value. */
+const char *gl_status_string(int status);
+
+/* Device bytes a likelihood evaluation of size n at tile b holds
+ * (packed lower tiles plus vectors), b = 0 meaning the automatic choice. */
+size_t gl_footprint_bytes(int64_t n, int32_t tile, int32_t precision);
+
+/* --------------------------------------------------------- operations ---- */
+
+/*
+ * Matérn covariance between point sets 1 and 2, Sec. 2.2 Eq. (2) with the
+ * Euclidean distance r = ||s1_i - s2_j|| (genDistanceMatrix + genCovMatrix
+ * of Alg. 1-3, the distance matrix is never stored).  r == 0 gives θ1.
+ * Output: column-major n1×n2, out[i + j*ld], ld >= n1; the caller owns it.
+ * Errors: GL_EINVAL for n1 < 1, n2 < 1, ld < n1, NULL pointers or bad θ.
+ */
+int matern_generate(gl_context *ctx, const double *x1, const double *y1, int64_t n1,
+                    const double *x2, const double *y2, int64_t n2, gl_theta theta,
+                    double *out, int64_t ld, void *stream);
+
+/*
+ * l(θ) = -n/2 log 2π - ½ log|Σ(θ)| - ½ Zᵀ Σ(θ)⁻¹ Z, Sec. 2 Eq. (1), computed
+ * as in Alg. 2: Σ(θ) in packed lower tiles, tiled Cholesky Σ = L Lᵀ,
+ * forward solve w = L⁻¹ Z, log|Σ| = 2 Σ log L_ii, Zᵀ Σ⁻¹ Z = wᵀw.
+ * Inputs x, y, z: n locations and measurements (device).  opts may be NULL
+ * (defaults).  The call is synchronous with respect to `stream`: it returns
+ * after the result is in *res_h.  Return value equals res_h->status.
+ * With keep_factor = 1 and status GL_OK, res_h->factor owns device memory
+ * until gl_factor_release (it counts against the HBM budget).
+ */
+int loglik_eval(gl_context *ctx, const double *x, const double *y, const double *z, int64_t n,
+                gl_theta theta, const gl_opts *opts, gl_result *res_h, void *stream);
+
+/*
+ * Kriging, Sec. 2.3 Eq. (5) and Alg. 3: Z1 = Σ12 Σ22⁻¹ Z2 at m new locations,
+ * reusing the factor L of a previous loglik_eval (keep_factor = 1) and its
+ * forward solution w: X = L⁻ᵀ w, then Z1_k = Σ_j C(||s_new,k - s_j||) X_j with
+ * Σ12 generated on the fly and never stored.  Output znew: m doubles (device,
+ * caller-owned).  Asynchronous on `stream`.
+ * Errors: GL_EINVAL for a NULL factor, m < 1 or NULL pointers.
+ */
+int krige_predict(gl_context *ctx, gl_factor *factor, const double *xnew, const double *ynew,
+                  int64_t m, double *znew, void *stream);
+
+/* Release a factor returned by loglik_eval. */
+int gl_factor_release(gl_context *ctx, gl_factor *factor);
+
+/* Copy the lower-triangular factor L of `factor` into a dense column-major
+ * n×n array (device, ld >= n) with a zero strict upper triangle. */
+int gl_factor_to_dense(gl_context *ctx, gl_factor *factor, double *out, int64_t ld, void *stream);
+
+/* Order n and tile size of a factor (either output may be NULL). */
+int gl_factor_shape(const gl_factor *factor, int64_t *n, int32_t *tile);
+
+/*
+ * Synthetic measurements, Sec. 5.3 Alg. 1: Σ(θ) = L Lᵀ (tiled Cholesky) and
+ * Z = L e.  Inputs x, y, e: n values each (device).  Output z: n doubles.
+ * tile: 0 = automatic.  Synchronous with respect to `stream`; *info_h (may be
+ * NULL) receives the Cholesky info.  Returns GL_OK or GL_NOT_SPD.
+ */
+int synth_generate(gl_context *ctx, const double *x, const double *y, const double *e,
+                   int64_t n, gl_theta theta, int32_t tile, double *z, int64_t *info_h,
+                   void *stream);
+
+/* ------------------------------------------------------------ serving ---- */
+
+/* Register a dataset (locations and measurements) for the request queue.  The
+ * library copies x, y, z (device pointers) into memory it owns; the caller may
+ * free its buffers when the call returns.  *ds_h receives the dataset id. */
+int gl_dataset_register(gl_context *ctx, const double *x, const double *y, const double *z,
+                        int64_t n, uint64_t *ds_h);
+
+/* Drop a dataset.  Pending requests on it are cancelled. */
+int gl_dataset_release(gl_context *ctx, uint64_t ds);
+
+/* Queue configuration.  Fill with lq_config_default(). */
+typedef struct {
+    int32_t max_inflight;    /* requests resident on the device at once (>= 1) */
+    int32_t streams;         /* device streams the scheduler spreads work over (1..8) */
+    int32_t batch_small;     /* 1: fuse the steps of small requests into shared launches */
+    int32_t small_n;         /* requests with n <= small_n are eligible for fused launches */
+    size_t hbm_budget_bytes; /* admission budget for resident work (0 = the context's) */
+} lq_config;
+
+void lq_config_default(lq_config *cfg);
+
+/* Start a scheduler thread serving likelihood requests of `ctx`. */
+int lq_create(gl_context *ctx, const lq_config *cfg, lq_queue **q_h);
+
+/* Enqueue l(θ) on dataset ds; thread-safe.  *ticket_h identifies the request.
+ * opts may be NULL (defaults; keep_factor is ignored by the queue). */
+int lq_submit(lq_queue *q, uint64_t ds, gl_theta theta, const gl_opts *opts, uint64_t *ticket_h);
+
+/* Non-blocking: GL_EBUSY while pending, else copies the result and retires
+ * the ticket (returns the request's status). */
+int lq_poll(lq_queue *q, uint64_t ticket, gl_result *res_h);
+
+/* Blocking with a timeout in microseconds (< 0 = forever): GL_ETIMEDOUT or
+ * the request's status; a delivered result retires the ticket. */
+int lq_wait(lq_queue *q, uint64_t ticket, gl_result *res_h, int64_t timeout_us);
+
+/* Cancel a request that has not started on the device. GL_OK if cancelled,
+ * GL_EBUSY if it is already running or done. */
+int lq_cancel(lq_queue *q, uint64_t ticket);
+
+/* Counters since creation: completed requests, peak resident bytes, peak
+ * requests resident at once, fused launches issued. Any pointer may be NULL. */
+int lq_stats(lq_queue *q, uint64_t *completed, size_t *peak_bytes, int32_t *peak_inflight,
+             uint64_t *fused_launches);
+
+/* Stop the scheduler: requests not yet started are cancelled, running ones are
+ * drained, then the thread exits and the queue is freed. */
+int lq_destroy(lq_queue *q);
+
+/* --------------------------------------------------------- diagnostics ---- */
+
+/* Runs a built-in device self-check `which` and writes up to `cap` doubles of
+ * output to out_h: 0 = the lane layout of the FP64 16x16x4 matrix-core
+ * product (256 values), 1 = the same for FP32 16x16x4, 2 = BF16 16x16x32. */
+int gl_selftest(gl_context *ctx, int32_t which, double *out_h, int64_t cap);
+
+/* Kernel timing of the trailing-update launches (the dominant kernel family).
+ * While enabled, every trailing launch of the direct calls is bracketed by
+ * HIP events on the stream it runs on.  gl_profile_read synchronises the
+ * device and returns the summed launch durations (ms), the algorithmic flops
+ * of those launches (2b³ per off-diagonal tile update, b²(b+1) per diagonal
+ * tile update) and the launch count since the last read, then resets them. */
+int gl_profile_enable(gl_context *ctx, int32_t on);
+int gl_profile_read(gl_context *ctx, double *ms_h, double *flops_h, int64_t *launches_h);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GEOLIK_H */

@@ -1,0 +1,343 @@
+"""ctypes binding of libgeolik.so (include/geolik.h), same names as the C ABI.
+
+Argument marshalling only: torch tensors provide device memory and streams,
+every computation runs in the HIP library.  A missing library raises
+``GeolikError``; there is no fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libgeolik.so")
+
+GL_OK = 0
+GL_NOT_SPD = 1
+GL_EINVAL = -1
+GL_ENOMEM = -2
+GL_EHIP = -3
+GL_EBUSY = -4
+GL_ECANCELED = -5
+GL_ETIMEDOUT = -6
+GL_ENODEV = -7
+
+GL_FP64 = 0
+GL_MIXED_FP32 = 1
+GL_MIXED_BF16 = 2
+
+
+class GeolikError(RuntimeError):
+    def __init__(self, status: int, what: str = ""):
+        self.status = status
+        super().__init__(f"{what}: {gl_status_string(status)} ({status})" if what else gl_status_string(status))
+
+
+class gl_theta(ctypes.Structure):
+    _fields_ = [("theta1", ctypes.c_double), ("theta2", ctypes.c_double), ("theta3", ctypes.c_double)]
+
+
+class gl_opts(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int32), ("tile", ctypes.c_int32), ("keep_factor", ctypes.c_int32),
+                ("band", ctypes.c_int32), ("tol32", ctypes.c_double), ("tolbf16", ctypes.c_double)]
+
+
+class gl_result(ctypes.Structure):
+    _fields_ = [("loglik", ctypes.c_double), ("logdet", ctypes.c_double), ("quad", ctypes.c_double),
+                ("info", ctypes.c_int64), ("status", ctypes.c_int32), ("tile", ctypes.c_int32),
+                ("factor", ctypes.c_void_p)]
+
+    def as_dict(self) -> dict:
+        return {"loglik": self.loglik, "logdet": self.logdet, "quad": self.quad, "info": int(self.info),
+                "status": int(self.status), "tile": int(self.tile), "factor": self.factor}
+
+
+class lq_config(ctypes.Structure):
+    _fields_ = [("max_inflight", ctypes.c_int32), ("streams", ctypes.c_int32), ("batch_small", ctypes.c_int32),
+                ("small_n", ctypes.c_int32), ("hbm_budget_bytes", ctypes.c_size_t)]
+
+
+_lib = None
+_P = ctypes.c_void_p
+_I32 = ctypes.c_int32
+_I64 = ctypes.c_int64
+_U64 = ctypes.c_uint64
+_SZ = ctypes.c_size_t
+_D = ctypes.c_double
+
+_SIGNATURES = {
+    "gl_context_create": (_I32, [ctypes.c_int, _SZ, ctypes.POINTER(_P)]),
+    "gl_context_destroy": (None, [_P]),
+    "gl_opts_default": (None, [ctypes.POINTER(gl_opts)]),
+    "gl_status_string": (ctypes.c_char_p, [ctypes.c_int]),
+    "gl_footprint_bytes": (_SZ, [_I64, _I32, _I32]),
+    "matern_generate": (_I32, [_P, _P, _P, _I64, _P, _P, _I64, gl_theta, _P, _I64, _P]),
+    "loglik_eval": (_I32, [_P, _P, _P, _P, _I64, gl_theta, ctypes.POINTER(gl_opts), ctypes.POINTER(gl_result), _P]),
+    "krige_predict": (_I32, [_P, _P, _P, _P, _I64, _P, _P]),
+    "gl_factor_release": (_I32, [_P, _P]),
+    "gl_factor_to_dense": (_I32, [_P, _P, _P, _I64, _P]),
+    "gl_factor_shape": (_I32, [_P, ctypes.POINTER(_I64), ctypes.POINTER(_I32)]),
+    "synth_generate": (_I32, [_P, _P, _P, _P, _I64, gl_theta, _I32, _P, ctypes.POINTER(_I64), _P]),
+    "gl_dataset_register": (_I32, [_P, _P, _P, _P, _I64, ctypes.POINTER(_U64)]),
+    "gl_dataset_release": (_I32, [_P, _U64]),
+    "lq_config_default": (None, [ctypes.POINTER(lq_config)]),
+    "lq_create": (_I32, [_P, ctypes.POINTER(lq_config), ctypes.POINTER(_P)]),
+    "lq_submit": (_I32, [_P, _U64, gl_theta, ctypes.POINTER(gl_opts), ctypes.POINTER(_U64)]),
+    "lq_poll": (_I32, [_P, _U64, ctypes.POINTER(gl_result)]),
+    "lq_wait": (_I32, [_P, _U64, ctypes.POINTER(gl_result), _I64]),
+    "lq_cancel": (_I32, [_P, _U64]),
+    "lq_stats": (_I32, [_P, ctypes.POINTER(_U64), ctypes.POINTER(_SZ), ctypes.POINTER(_I32), ctypes.POINTER(_U64)]),
+    "lq_destroy": (_I32, [_P]),
+    "gl_selftest": (_I32, [_P, _I32, ctypes.POINTER(_D), _I64]),
+    "gl_profile_enable": (_I32, [_P, _I32]),
+    "gl_profile_read": (_I32, [_P, ctypes.POINTER(_D), ctypes.POINTER(_D), ctypes.POINTER(_I64)]),
+}
+
+
+def lib() -> ctypes.CDLL:
+    """Load libgeolik.so; raises GeolikError when it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise GeolikError(GL_ENODEV, f"{LIB_PATH} is missing; run python -m paper_1708_02835_amd.build")
+    l = ctypes.CDLL(LIB_PATH)
+    for name, (res, args) in _SIGNATURES.items():
+        f = getattr(l, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = l
+    return l
+
+
+def gl_status_string(status: int) -> str:
+    try:
+        return lib().gl_status_string(int(status)).decode()
+    except GeolikError:
+        return f"status {status}"
+
+
+def _check(status: int, what: str) -> int:
+    if status < 0:
+        raise GeolikError(status, what)
+    return status
+
+
+def _ptr(t) -> int:
+    """Device pointer of a contiguous float64 CUDA tensor."""
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.float64 or not t.is_contiguous():
+        raise TypeError("expected a contiguous float64 CUDA tensor")
+    return t.data_ptr()
+
+
+def _stream(stream) -> int:
+    import torch
+    if stream is None:
+        return torch.cuda.current_stream().cuda_stream
+    return getattr(stream, "cuda_stream", stream)
+
+
+def _theta(theta) -> gl_theta:
+    t1, t2, t3 = (float(v) for v in theta)
+    return gl_theta(t1, t2, t3)
+
+
+def gl_opts_default(**kw) -> gl_opts:
+    o = gl_opts()
+    lib().gl_opts_default(ctypes.byref(o))
+    for k, v in kw.items():
+        setattr(o, k, v)
+    return o
+
+
+def gl_footprint_bytes(n: int, tile: int = 0, precision: int = GL_FP64) -> int:
+    return int(lib().gl_footprint_bytes(int(n), int(tile), int(precision)))
+
+
+class Context:
+    """Owns a gl_context; use as a context manager or call close()."""
+
+    def __init__(self, device: int = 0, hbm_budget_bytes: int = 0):
+        h = _P()
+        _check(lib().gl_context_create(int(device), int(hbm_budget_bytes), ctypes.byref(h)), "gl_context_create")
+        self.handle = h.value
+
+    def close(self):
+        if self.handle:
+            lib().gl_context_destroy(self.handle)
+            self.handle = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def gl_context_create(device: int = 0, hbm_budget_bytes: int = 0) -> Context:
+    return Context(device, hbm_budget_bytes)
+
+
+def gl_context_destroy(ctx: Context) -> None:
+    ctx.close()
+
+
+def matern_generate(ctx: Context, x1, y1, x2, y2, theta, out=None, stream=None):
+    """Dense column-major n1×n2 Matérn covariance; returns a torch tensor of shape (n2, n1)
+    whose transpose is Σ12 (i.e. out.T[i, j] = C(||s1_i - s2_j||))."""
+    import torch
+    n1, n2 = x1.numel(), x2.numel()
+    if out is None:
+        out = torch.empty((n2, n1), dtype=torch.float64, device=x1.device)
+    _check(lib().matern_generate(ctx.handle, _ptr(x1), _ptr(y1), n1, _ptr(x2), _ptr(y2), n2, _theta(theta),
+                                 _ptr(out), n1, _stream(stream)), "matern_generate")
+    return out
+
+
+def loglik_eval(ctx: Context, x, y, z, theta, opts: gl_opts | None = None, stream=None) -> dict:
+    """Alg. 2 on the device; returns the gl_result fields as a dict."""
+    res = gl_result()
+    o = opts if opts is not None else gl_opts_default()
+    st = lib().loglik_eval(ctx.handle, _ptr(x), _ptr(y), _ptr(z), x.numel(), _theta(theta), ctypes.byref(o),
+                           ctypes.byref(res), _stream(stream))
+    _check(st, "loglik_eval")
+    return res.as_dict()
+
+
+def krige_predict(ctx: Context, factor, xnew, ynew, out=None, stream=None):
+    import torch
+    m = xnew.numel()
+    if out is None:
+        out = torch.empty(m, dtype=torch.float64, device=xnew.device)
+    _check(lib().krige_predict(ctx.handle, factor, _ptr(xnew), _ptr(ynew), m, _ptr(out), _stream(stream)),
+           "krige_predict")
+    return out
+
+
+def gl_factor_release(ctx: Context, factor) -> None:
+    _check(lib().gl_factor_release(ctx.handle, factor), "gl_factor_release")
+
+
+def gl_factor_shape(factor) -> tuple[int, int]:
+    n, b = _I64(), _I32()
+    _check(lib().gl_factor_shape(factor, ctypes.byref(n), ctypes.byref(b)), "gl_factor_shape")
+    return int(n.value), int(b.value)
+
+
+def gl_factor_to_dense(ctx: Context, factor, out=None, stream=None):
+    """Dense lower factor; returns a (n, n) tensor holding Lᵀ in row-major order (L column-major)."""
+    import torch
+    n, _ = gl_factor_shape(factor)
+    if out is None:
+        out = torch.empty((n, n), dtype=torch.float64, device="cuda")
+    _check(lib().gl_factor_to_dense(ctx.handle, factor, _ptr(out), n, _stream(stream)), "gl_factor_to_dense")
+    return out
+
+
+def synth_generate(ctx: Context, x, y, e, theta, tile: int = 0, out=None, stream=None):
+    """Alg. 1: returns (z, info)."""
+    import torch
+    n = x.numel()
+    if out is None:
+        out = torch.empty(n, dtype=torch.float64, device=x.device)
+    info = _I64()
+    _check(lib().synth_generate(ctx.handle, _ptr(x), _ptr(y), _ptr(e), n, _theta(theta), int(tile), _ptr(out),
+                                ctypes.byref(info), _stream(stream)), "synth_generate")
+    return out, int(info.value)
+
+
+def gl_dataset_register(ctx: Context, x, y, z) -> int:
+    ds = _U64()
+    _check(lib().gl_dataset_register(ctx.handle, _ptr(x), _ptr(y), _ptr(z), x.numel(), ctypes.byref(ds)),
+           "gl_dataset_register")
+    return int(ds.value)
+
+
+def gl_dataset_release(ctx: Context, ds: int) -> None:
+    _check(lib().gl_dataset_release(ctx.handle, int(ds)), "gl_dataset_release")
+
+
+def lq_config_default(**kw) -> lq_config:
+    c = lq_config()
+    lib().lq_config_default(ctypes.byref(c))
+    for k, v in kw.items():
+        setattr(c, k, v)
+    return c
+
+
+def lq_create(ctx: Context, cfg: lq_config | None = None) -> int:
+    q = _P()
+    c = cfg if cfg is not None else lq_config_default()
+    _check(lib().lq_create(ctx.handle, ctypes.byref(c), ctypes.byref(q)), "lq_create")
+    return q.value
+
+
+def lq_submit(q: int, ds: int, theta, opts: gl_opts | None = None) -> int:
+    t = _U64()
+    _check(lib().lq_submit(q, int(ds), _theta(theta), ctypes.byref(opts) if opts is not None else None,
+                           ctypes.byref(t)), "lq_submit")
+    return int(t.value)
+
+
+def lq_poll(q: int, ticket: int):
+    """None while pending, else the result dict."""
+    res = gl_result()
+    st = lib().lq_poll(q, int(ticket), ctypes.byref(res))
+    if st == GL_EBUSY:
+        return None
+    _check(st if st != GL_ECANCELED else GL_OK, "lq_poll")
+    d = res.as_dict()
+    d["status"] = st
+    return d
+
+
+def lq_wait(q: int, ticket: int, timeout_us: int = -1):
+    """Result dict, or None on timeout."""
+    res = gl_result()
+    st = lib().lq_wait(q, int(ticket), ctypes.byref(res), int(timeout_us))
+    if st == GL_ETIMEDOUT:
+        return None
+    if st < 0 and st != GL_ECANCELED:
+        raise GeolikError(st, "lq_wait")
+    d = res.as_dict()
+    d["status"] = st
+    return d
+
+
+def lq_cancel(q: int, ticket: int) -> int:
+    return int(lib().lq_cancel(q, int(ticket)))
+
+
+def lq_stats(q: int) -> dict:
+    c, pb, pi, fl = _U64(), _SZ(), _I32(), _U64()
+    _check(lib().lq_stats(q, ctypes.byref(c), ctypes.byref(pb), ctypes.byref(pi), ctypes.byref(fl)), "lq_stats")
+    return {"completed": int(c.value), "peak_bytes": int(pb.value), "peak_inflight": int(pi.value),
+            "fused_launches": int(fl.value)}
+
+
+def lq_destroy(q: int) -> None:
+    _check(lib().lq_destroy(q), "lq_destroy")
+
+
+def gl_selftest(ctx: Context, which: int):
+    import numpy as np
+    out = (ctypes.c_double * 256)()
+    _check(lib().gl_selftest(ctx.handle, int(which), out, 256), "gl_selftest")
+    return np.frombuffer(out, dtype=np.float64).copy()
+
+
+def gl_profile_enable(ctx: Context, on: bool = True) -> None:
+    _check(lib().gl_profile_enable(ctx.handle, 1 if on else 0), "gl_profile_enable")
+
+
+def gl_profile_read(ctx: Context) -> dict:
+    ms, fl, n = _D(), _D(), _I64()
+    _check(lib().gl_profile_read(ctx.handle, ctypes.byref(ms), ctypes.byref(fl), ctypes.byref(n)), "gl_profile_read")
+    return {"ms": ms.value, "flops": fl.value, "launches": int(n.value)}

@@ -1,0 +1,532 @@
+// C-ABI implementation: contexts, device workspaces, the step schedule of the
+// tiled factorisation, and the entry points of geolik.h.
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <atomic>
+#include <mutex>
+#include <new>
+
+#include "common.hpp"
+#include "engine.hpp"
+
+int gl_hip_fail(hipError_t e, const char *what)
+{
+    if (getenv("GEOLIK_VERBOSE")) fprintf(stderr, "geolik: %s failed: %s\n", what, hipGetErrorString(e));
+    return e == hipErrorOutOfMemory ? GL_ENOMEM : GL_EHIP;
+}
+
+namespace gl {
+
+int pick_tile(int64_t n, int32_t requested)
+{
+    if (requested == 128 || requested == 256 || requested == 384 || requested == 512) return requested;
+    if (n <= 3000) return 128;
+    if (n <= 24000) return 256;
+    return 512;
+}
+
+bool valid_theta(const gl_theta &t)
+{
+    return t.theta1 > 0.0 && t.theta2 > 0.0 && t.theta3 > 0.0 && t.theta3 <= 50.0 &&
+           isfinite(t.theta1) && isfinite(t.theta2);
+}
+
+size_t work_bytes(int64_t n, int b, int precision)
+{
+    const int64_t nt = ceil_div(n, b);
+    const int64_t npad = nt * b;
+    size_t tiles = (size_t)tile_count(nt) * (size_t)b * b * sizeof(double);
+    if (precision != GL_FP64) tiles += mixed_extra_bytes(nt, b);
+    const size_t vec = (size_t)(3 * npad + 4 * nt + tile_count(nt) + 64) * sizeof(double);
+    return tiles + vec;
+}
+
+void Work::release()
+{
+    if (tiles) hipFree(tiles);
+    if (vecs) hipFree(vecs);
+    tiles = nullptr;
+    lo32 = nullptr;
+    pmap = nullptr;
+    vecs = nullptr;
+    tile_cap = 0;
+    vec_cap = 0;
+}
+
+// Size the workspace for (n, b); reuses the allocation when it is big enough.
+int Work::ensure(gl_context *ctx, int64_t n_, int b_, int precision_)
+{
+    const int64_t nt_ = ceil_div(n_, b_);
+    const int64_t npad_ = nt_ * b_;
+    size_t tneed = (size_t)tile_count(nt_) * (size_t)b_ * b_ * sizeof(double);
+    if (precision_ != GL_FP64) tneed += mixed_extra_bytes(nt_, b_);
+    const size_t vneed = (size_t)(3 * npad_ + 4 * nt_ + tile_count(nt_) + 64) * sizeof(double);
+    if (tneed > tile_cap || vneed > vec_cap) {
+        const size_t old = tile_cap + vec_cap;
+        const size_t want = (tneed > tile_cap ? tneed : tile_cap) + (vneed > vec_cap ? vneed : vec_cap);
+        if (ctx->used.load() - old + want > ctx->budget) return GL_ENOMEM;
+        if (tneed > tile_cap) {
+            if (tiles) hipFree(tiles);
+            tiles = nullptr;
+            tile_cap = 0;
+            GL_HIP_TRY(hipMalloc(reinterpret_cast<void **>(&tiles), tneed));
+            tile_cap = tneed;
+        }
+        if (vneed > vec_cap) {
+            if (vecs) hipFree(vecs);
+            vecs = nullptr;
+            vec_cap = 0;
+            GL_HIP_TRY(hipMalloc(&vecs, vneed));
+            vec_cap = vneed;
+        }
+        ctx->used += (tile_cap + vec_cap) - old;
+    }
+    n = n_;
+    b = b_;
+    nt = nt_;
+    npad = npad_;
+    precision = precision_;
+    double *p = static_cast<double *>(vecs);
+    x = p;
+    y = p + npad;
+    v = p + 2 * npad;
+    logsum = p + 3 * npad;
+    quad = logsum + nt;
+    norm2 = quad + nt;
+    info = reinterpret_cast<int64_t *>(norm2 + tile_count(nt));
+    res = reinterpret_cast<DevResult *>(info + 8);
+    if (precision_ != GL_FP64) {
+        mixed_views(*this);
+    } else {
+        lo32 = nullptr;
+        pmap = nullptr;
+    }
+    return GL_OK;
+}
+
+// Right-looking tiled Cholesky of the generated tiles, with the forward
+// solve of v folded into the same step loop.  Step k on the caller's stream
+// s: POTRF(k), the diagonal solve of v_k, TRSM of column k, v_i -= L_ik v_k,
+// then (after the previous bulk update) the update of column k+1 only.  The
+// bulk update of columns k+2.. runs on the lookahead stream, so POTRF/TRSM of
+// step k+1 overlap with it.
+int Lanes::create()
+{
+    GL_HIP_TRY(hipStreamCreateWithFlags(&la, hipStreamNonBlocking));
+    GL_HIP_TRY(hipEventCreateWithFlags(&fork, hipEventDisableTiming));
+    GL_HIP_TRY(hipEventCreateWithFlags(&panel, hipEventDisableTiming));
+    GL_HIP_TRY(hipEventCreateWithFlags(&bulk, hipEventDisableTiming));
+    GL_HIP_TRY(hipEventCreateWithFlags(&join, hipEventDisableTiming));
+    return GL_OK;
+}
+
+void Lanes::destroy()
+{
+    if (la) hipStreamDestroy(la);
+    if (fork) hipEventDestroy(fork);
+    if (panel) hipEventDestroy(panel);
+    if (bulk) hipEventDestroy(bulk);
+    if (join) hipEventDestroy(join);
+    la = nullptr;
+    fork = panel = bulk = join = nullptr;
+}
+
+int Prof::bracket(hipStream_t s, bool start)
+{
+    (void)start;
+    hipEvent_t e;
+    if (!pool.empty()) {
+        e = pool.back();
+        pool.pop_back();
+    } else {
+        GL_HIP_TRY(hipEventCreate(&e));
+    }
+    GL_HIP_TRY(hipEventRecord(e, s));
+    pending.push_back(e);
+    return GL_OK;
+}
+
+// Algorithmic flops of the trailing update of step k over tile columns
+// jbeg..jend: 2b³ per off-diagonal tile, b²(b+1) per diagonal tile.
+static double trailing_flops(int64_t nt, int64_t jbeg, int64_t jend, int b)
+{
+    double f = 0.0;
+    const double b3 = (double)b * b * b;
+    for (int64_t j = jbeg; j <= jend; ++j) f += 2.0 * b3 * (double)(nt - j - 1) + (double)b * b * (b + 1);
+    return f;
+}
+
+static void trailing(Lanes &ln, Work &w, int64_t k, int64_t jbeg, int64_t jend, hipStream_t s)
+{
+    if (ln.prof) ln.prof->bracket(s, true);
+    launch_trailing(w.tiles, w.b, w.nt, k, jbeg, jend, w.info, s);
+    if (ln.prof) {
+        ln.prof->bracket(s, false);
+        ln.prof->flops += trailing_flops(w.nt, jbeg, jend, w.b);
+        ln.prof->launches += 1;
+    }
+}
+
+int factorize(Lanes &ln, Work &w, hipStream_t s, bool solve)
+{
+    hipStream_t la = ln.la;
+    GL_HIP_TRY(hipEventRecord(ln.fork, s));
+    GL_HIP_TRY(hipStreamWaitEvent(la, ln.fork, 0));
+    for (int64_t k = 0; k < w.nt; ++k) {
+        launch_potrf(w.tiles, w.b, k, w.n, w.info, w.logsum, s);
+        if (solve) launch_fwd_diag(w.tiles, w.b, k, w.n, w.v, w.quad, w.info, s);
+        launch_trsm(w.tiles, w.b, w.nt, k, w.info, s);
+        if (solve) launch_fwd_update(w.tiles, w.b, w.nt, k, w.v, w.info, s);
+        if (k + 1 < w.nt) {
+            GL_HIP_TRY(hipEventRecord(ln.panel, s));
+            if (k > 0) GL_HIP_TRY(hipStreamWaitEvent(s, ln.bulk, 0));
+            trailing(ln, w, k, k + 1, k + 1, s);
+            if (k + 2 < w.nt) {
+                GL_HIP_TRY(hipStreamWaitEvent(la, ln.panel, 0));
+                trailing(ln, w, k, k + 2, w.nt - 1, la);
+                GL_HIP_TRY(hipEventRecord(ln.bulk, la));
+            }
+        }
+    }
+    GL_HIP_TRY(hipGetLastError());
+    GL_HIP_TRY(hipEventRecord(ln.join, la));
+    GL_HIP_TRY(hipStreamWaitEvent(s, ln.join, 0));
+    return GL_OK;
+}
+
+}  // namespace gl
+
+using namespace gl;
+
+extern "C" {
+
+const char *gl_status_string(int status)
+{
+    switch (status) {
+    case GL_OK: return "ok";
+    case GL_NOT_SPD: return "covariance matrix is not positive definite";
+    case GL_EINVAL: return "invalid argument";
+    case GL_ENOMEM: return "out of device memory or HBM budget exceeded";
+    case GL_EHIP: return "HIP runtime error";
+    case GL_EBUSY: return "request pending";
+    case GL_ECANCELED: return "request cancelled";
+    case GL_ETIMEDOUT: return "timed out";
+    case GL_ENODEV: return "no usable gfx950 device";
+    default: return "unknown status";
+    }
+}
+
+void gl_opts_default(gl_opts *o)
+{
+    if (!o) return;
+    o->precision = GL_FP64;
+    o->tile = 0;
+    o->keep_factor = 0;
+    o->band = 2;
+    o->tol32 = 1e-2;
+    o->tolbf16 = 1e-4;
+}
+
+size_t gl_footprint_bytes(int64_t n, int32_t tile, int32_t precision)
+{
+    if (n < 1) return 0;
+    return work_bytes(n, pick_tile(n, tile), precision);
+}
+
+int gl_context_create(int device, size_t budget, gl_context **out)
+{
+    if (!out) return GL_EINVAL;
+    *out = nullptr;
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || count <= 0 || device < 0 || device >= count)
+        return GL_ENODEV;
+    hipDeviceProp_t prop;
+    GL_HIP_TRY(hipGetDeviceProperties(&prop, device));
+    if (strncmp(prop.gcnArchName, "gfx950", 6) != 0) return GL_ENODEV;
+    GL_HIP_TRY(hipSetDevice(device));
+    gl_context *c = new (std::nothrow) gl_context();
+    if (!c) return GL_ENOMEM;
+    c->device = device;
+    size_t freeb = 0, total = 0;
+    GL_HIP_TRY(hipMemGetInfo(&freeb, &total));
+    c->budget = budget ? budget : (size_t)(0.9 * (double)freeb);
+    if (c->lanes.create() != GL_OK ||
+        hipHostMalloc(&c->res_h, sizeof(DevResult), hipHostMallocDefault) != hipSuccess) {
+        gl_context_destroy(c);
+        return GL_EHIP;
+    }
+    *out = c;
+    return GL_OK;
+}
+
+void gl_context_destroy(gl_context *c)
+{
+    if (!c) return;
+    hipSetDevice(c->device);
+    hipDeviceSynchronize();
+    c->ws.release();
+    for (gl_factor *f : c->factors) {
+        f->w.release();
+        delete f;
+    }
+    c->factors.clear();
+    serve_context_cleanup(c);
+    c->lanes.destroy();
+    for (hipEvent_t e : c->prof.pool) hipEventDestroy(e);
+    for (hipEvent_t e : c->prof.pending) hipEventDestroy(e);
+    if (c->res_h) hipHostFree(c->res_h);
+    delete c;
+}
+
+int matern_generate(gl_context *ctx, const double *x1, const double *y1, int64_t n1, const double *x2,
+                    const double *y2, int64_t n2, gl_theta th, double *out, int64_t ld, void *stream)
+{
+    if (!ctx || !x1 || !y1 || !x2 || !y2 || !out || n1 < 1 || n2 < 1 || ld < n1 || !valid_theta(th))
+        return GL_EINVAL;
+    GL_HIP_TRY(hipSetDevice(ctx->device));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    launch_gen_dense(x1, y1, n1, x2, y2, n2, th, out, ld, s);
+    GL_HIP_TRY(hipGetLastError());
+    return GL_OK;
+}
+
+}  // extern "C"
+
+namespace gl {
+
+// Likelihood evaluation on a prepared workspace whose x, y, v hold the padded
+// inputs.  Leaves the factor and w = L⁻¹ Z in the workspace and enqueues the
+// copy of the scalar results to out_h (pinned host memory).
+int eval_launch(Lanes &ln, Work &w, gl_theta th, const gl_opts &o, hipStream_t s, DevResult *out_h)
+{
+    launch_fill(reinterpret_cast<double *>(w.info), 1, 0.0, s);
+    int rc;
+    if (o.precision == GL_FP64) {
+        launch_gen_tiles(w.tiles, w.x, w.y, w.n, w.b, w.nt, th, nullptr, s);
+        rc = factorize(ln, w, s, true);
+    } else {
+        rc = mixed_factorize(ln, w, th, o, s);
+    }
+    if (rc != GL_OK) return rc;
+    launch_final_reduce(w.logsum, w.quad, w.nt, w.n, w.info, w.res, s);
+    GL_HIP_TRY(hipGetLastError());
+    GL_HIP_TRY(hipMemcpyAsync(out_h, w.res, sizeof(DevResult), hipMemcpyDeviceToHost, s));
+    return GL_OK;
+}
+
+bool valid_opts(const gl_opts &o)
+{
+    if (o.precision < GL_FP64 || o.precision > GL_MIXED_BF16) return false;
+    if (o.tile != 0 && o.tile != 128 && o.tile != 256 && o.tile != 384 && o.tile != 512) return false;
+    if (o.precision != GL_FP64 && (o.band < 1 || !(o.tol32 >= 0.0) || !(o.tolbf16 >= 0.0))) return false;
+    return true;
+}
+
+static void fill_result(gl_result *res, const DevResult &d, int b)
+{
+    res->loglik = d.loglik;
+    res->logdet = d.logdet;
+    res->quad = d.quad;
+    res->info = d.info;
+    res->status = d.info ? GL_NOT_SPD : GL_OK;
+    res->tile = b;
+    res->factor = nullptr;
+}
+
+}  // namespace gl
+
+extern "C" {
+
+int loglik_eval(gl_context *ctx, const double *x, const double *y, const double *z, int64_t n,
+                gl_theta th, const gl_opts *opts, gl_result *res, void *stream)
+{
+    if (!res) return GL_EINVAL;
+    memset(res, 0, sizeof(*res));
+    gl_opts o;
+    gl_opts_default(&o);
+    if (opts) o = *opts;
+    if (!ctx || !x || !y || !z || n < 1 || !valid_theta(th) || !valid_opts(o)) {
+        res->status = GL_EINVAL;
+        return GL_EINVAL;
+    }
+    GL_HIP_TRY(hipSetDevice(ctx->device));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int b = pick_tile(n, o.tile);
+    gl_factor *f = nullptr;
+    Work *w = &ctx->ws;
+    if (o.keep_factor) {
+        f = new (std::nothrow) gl_factor();
+        if (!f) return res->status = GL_ENOMEM;
+        f->ctx = ctx;
+        f->theta = th;
+        w = &f->w;
+    }
+    int rc = w->ensure(ctx, n, b, o.precision);
+    if (rc == GL_OK) {
+        launch_copy_pad(x, n, w->x, w->npad, 0.0, s);
+        launch_copy_pad(y, n, w->y, w->npad, 0.0, s);
+        launch_copy_pad(z, n, w->v, w->npad, 0.0, s);
+        rc = eval_launch(ctx->lanes, *w, th, o, s, ctx->res_h);
+        if (rc == GL_OK && hipStreamSynchronize(s) != hipSuccess) rc = GL_EHIP;
+    }
+    if (rc != GL_OK) {
+        if (f) {
+            ctx->used -= f->w.tile_cap + f->w.vec_cap;
+            f->w.release();
+            delete f;
+        }
+        res->status = rc;
+        return rc;
+    }
+    fill_result(res, *ctx->res_h, b);
+    if (f) {
+        if (res->status == GL_OK) {
+            std::lock_guard<std::mutex> lk(ctx->mu);
+            ctx->factors.push_back(f);
+            res->factor = f;
+        } else {
+            ctx->used -= f->w.tile_cap + f->w.vec_cap;
+            f->w.release();
+            delete f;
+        }
+    }
+    return res->status;
+}
+
+int gl_factor_release(gl_context *ctx, gl_factor *f)
+{
+    if (!ctx || !f || f->ctx != ctx) return GL_EINVAL;
+    {
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        bool found = false;
+        for (size_t i = 0; i < ctx->factors.size(); ++i)
+            if (ctx->factors[i] == f) {
+                ctx->factors.erase(ctx->factors.begin() + i);
+                found = true;
+                break;
+            }
+        if (!found) return GL_EINVAL;
+    }
+    hipSetDevice(ctx->device);
+    hipDeviceSynchronize();
+    ctx->used -= f->w.tile_cap + f->w.vec_cap;
+    f->w.release();
+    delete f;
+    return GL_OK;
+}
+
+int gl_factor_shape(const gl_factor *f, int64_t *n, int32_t *tile)
+{
+    if (!f) return GL_EINVAL;
+    if (n) *n = f->w.n;
+    if (tile) *tile = f->w.b;
+    return GL_OK;
+}
+
+int gl_factor_to_dense(gl_context *ctx, gl_factor *f, double *out, int64_t ld, void *stream)
+{
+    if (!ctx || !f || !out || ld < f->w.n) return GL_EINVAL;
+    if (f->w.precision != GL_FP64) return GL_EINVAL;
+    GL_HIP_TRY(hipSetDevice(ctx->device));
+    launch_tiles_to_dense(f->w.tiles, f->w.b, f->w.n, out, ld, static_cast<hipStream_t>(stream));
+    GL_HIP_TRY(hipGetLastError());
+    return GL_OK;
+}
+
+int krige_predict(gl_context *ctx, gl_factor *f, const double *xnew, const double *ynew, int64_t m,
+                  double *znew, void *stream)
+{
+    if (!ctx || !f || f->ctx != ctx || !xnew || !ynew || !znew || m < 1) return GL_EINVAL;
+    GL_HIP_TRY(hipSetDevice(ctx->device));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    Work &w = f->w;
+    const int64_t nchunk = krige_chunks(w.n);
+    double *scratch = nullptr;
+    const size_t bytes = (size_t)(w.npad + m * nchunk) * sizeof(double);
+    GL_HIP_TRY(hipMallocAsync(reinterpret_cast<void **>(&scratch), bytes, s));
+    double *xv = scratch;
+    double *part = scratch + w.npad;
+    // X = L⁻ᵀ w: backward substitution over tile rows, last to first
+    GL_HIP_TRY(hipMemcpyAsync(xv, w.v, (size_t)w.npad * sizeof(double), hipMemcpyDeviceToDevice, s));
+    if (w.precision == GL_FP64) {
+        for (int64_t k = w.nt - 1; k >= 0; --k) {
+            launch_bwd_diag(w.tiles, w.b, k, xv, s);
+            launch_bwd_update(w.tiles, w.b, k, xv, s);
+        }
+    } else {
+        mixed_backward(w, xv, s);
+    }
+    launch_krige(w.x, w.y, w.n, xv, f->theta, xnew, ynew, m, part, nchunk, s);
+    launch_krige_reduce(part, m, nchunk, znew, s);
+    GL_HIP_TRY(hipGetLastError());
+    GL_HIP_TRY(hipFreeAsync(scratch, s));
+    return GL_OK;
+}
+
+int synth_generate(gl_context *ctx, const double *x, const double *y, const double *e, int64_t n,
+                   gl_theta th, int32_t tile, double *z, int64_t *info_h, void *stream)
+{
+    if (!ctx || !x || !y || !e || !z || n < 1 || !valid_theta(th)) return GL_EINVAL;
+    if (tile != 0 && tile != 128 && tile != 256 && tile != 384 && tile != 512) return GL_EINVAL;
+    GL_HIP_TRY(hipSetDevice(ctx->device));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    Work &w = ctx->ws;
+    int rc = w.ensure(ctx, n, pick_tile(n, tile), GL_FP64);
+    if (rc != GL_OK) return rc;
+    launch_copy_pad(x, n, w.x, w.npad, 0.0, s);
+    launch_copy_pad(y, n, w.y, w.npad, 0.0, s);
+    launch_copy_pad(e, n, w.v, w.npad, 0.0, s);
+    launch_fill(reinterpret_cast<double *>(w.info), 1, 0.0, s);
+    launch_gen_tiles(w.tiles, w.x, w.y, w.n, w.b, w.nt, th, nullptr, s);
+    rc = factorize(ctx->lanes, w, s, false);
+    if (rc != GL_OK) return rc;
+    // z = L e: e is read from v, the padded product goes to the x buffer (no
+    // longer needed once the tiles exist), then its first n values to z
+    launch_trmv(w.tiles, w.b, w.nt, w.v, w.x, s);
+    GL_HIP_TRY(hipMemcpyAsync(z, w.x, (size_t)n * sizeof(double), hipMemcpyDeviceToDevice, s));
+    GL_HIP_TRY(hipMemcpyAsync(ctx->res_h, w.info, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    GL_HIP_TRY(hipStreamSynchronize(s));
+    const int64_t info = *reinterpret_cast<int64_t *>(ctx->res_h);
+    if (info_h) *info_h = info;
+    return info ? GL_NOT_SPD : GL_OK;
+}
+
+int gl_profile_enable(gl_context *ctx, int32_t on)
+{
+    if (!ctx) return GL_EINVAL;
+    ctx->lanes.prof = on ? &ctx->prof : nullptr;
+    return GL_OK;
+}
+
+int gl_profile_read(gl_context *ctx, double *ms_h, double *flops_h, int64_t *launches_h)
+{
+    if (!ctx) return GL_EINVAL;
+    GL_HIP_TRY(hipSetDevice(ctx->device));
+    GL_HIP_TRY(hipDeviceSynchronize());
+    Prof &p = ctx->prof;
+    double ms = 0.0;
+    for (size_t i = 0; i + 1 < p.pending.size(); i += 2) {
+        float t = 0.f;
+        GL_HIP_TRY(hipEventElapsedTime(&t, p.pending[i], p.pending[i + 1]));
+        ms += t;
+    }
+    if (ms_h) *ms_h = ms;
+    if (flops_h) *flops_h = p.flops;
+    if (launches_h) *launches_h = p.launches;
+    for (hipEvent_t e : p.pending) p.pool.push_back(e);
+    p.pending.clear();
+    p.flops = 0.0;
+    p.launches = 0;
+    return GL_OK;
+}
+
+int gl_selftest(gl_context *ctx, int32_t which, double *out_h, int64_t cap)
+{
+    if (!ctx || !out_h || cap < 256 || which < 0 || which > 2) return GL_EINVAL;
+    GL_HIP_TRY(hipSetDevice(ctx->device));
+    return selftest_mfma(which, out_h, cap);
+}
+
+}  // extern "C"

@@ -1,0 +1,93 @@
+// Internal host-side structures of the geolik runtime.
+#pragma once
+
+#include <atomic>
+#include <mutex>
+#include <vector>
+
+#include "common.hpp"
+
+namespace gl {
+
+// Device buffers of one likelihood evaluation (or of one kept factor).
+struct Work {
+    // geometry
+    int64_t n = 0, nt = 0, npad = 0;
+    int b = 0;
+    int precision = GL_FP64;
+    // allocations
+    double *tiles = nullptr;  // packed lower tiles, binary64
+    void *vecs = nullptr;
+    size_t tile_cap = 0, vec_cap = 0;
+    // views into vecs
+    double *x = nullptr, *y = nullptr;  // padded locations
+    double *v = nullptr;                // Z on entry, w = L⁻¹ Z after the evaluation
+    double *logsum = nullptr;           // per diagonal tile: 2 Σ log L_rr
+    double *quad = nullptr;             // per tile: Σ w_r²
+    double *norm2 = nullptr;            // per tile: ||Σ_ij||_F² (mixed precision)
+    int64_t *info = nullptr;
+    DevResult *res = nullptr;
+    // mixed precision: views into the tail of the tile allocation
+    float *lo32 = nullptr;              // fp32 copies of off-band tiles
+    uint8_t *pmap = nullptr;            // per tile precision class
+    int ensure(gl_context *ctx, int64_t n, int b, int precision);
+    void release();
+};
+
+// Optional timing of trailing-update launches.
+struct Prof {
+    std::vector<hipEvent_t> pool;
+    std::vector<hipEvent_t> pending;  // start, stop pairs in launch order
+    double flops = 0.0;
+    int64_t launches = 0;
+    int bracket(hipStream_t s, bool start);
+};
+
+// Side stream and events of one evaluation's step schedule (lookahead).
+struct Lanes {
+    Prof *prof = nullptr;
+    hipStream_t la = nullptr;
+    hipEvent_t fork = nullptr, panel = nullptr, bulk = nullptr, join = nullptr;
+    int create();
+    void destroy();
+};
+
+int pick_tile(int64_t n, int32_t requested);
+bool valid_theta(const gl_theta &t);
+size_t work_bytes(int64_t n, int b, int precision);
+int factorize(Lanes &ln, Work &w, hipStream_t s, bool solve);
+// Enqueue a whole evaluation on s (inputs already in w.x, w.y, w.v) and the
+// copy of its scalar results to out_h; does not wait.
+int eval_launch(Lanes &ln, Work &w, gl_theta th, const gl_opts &o, hipStream_t s, DevResult *out_h);
+bool valid_opts(const gl_opts &o);
+
+// mixed precision (mixed.hip)
+size_t mixed_extra_bytes(int64_t nt, int b);
+void mixed_views(Work &w);
+int mixed_factorize(Lanes &ln, Work &w, gl_theta th, const gl_opts &o, hipStream_t s);
+void mixed_backward(Work &w, double *v, hipStream_t s);
+
+// serving (serve.cpp)
+struct ServeState;
+void serve_context_cleanup(gl_context *ctx);
+
+}  // namespace gl
+
+struct gl_factor {
+    gl_context *ctx = nullptr;
+    gl_theta theta{};
+    gl::Work w;
+};
+
+struct gl_context {
+    int device = 0;
+    size_t budget = 0;
+    std::atomic<size_t> used{0};
+    gl::Work ws;  // reused by evaluations that do not keep their factor
+    gl::Lanes lanes;  // step-schedule side stream of the direct calls
+    gl::Prof prof;
+    gl::DevResult *res_h = nullptr;  // pinned host copy of the last result
+    std::mutex mu;                   // guards factors and datasets
+    std::vector<gl_factor *> factors;
+    gl::ServeState *serve = nullptr;
+};

@@ -1,0 +1,48 @@
+// Matrix-core helpers for gfx950 (64-lane wavefronts).
+//
+// v_mfma_f64_16x16x4_f64 computes D(16×16) = A(16×4) · B(4×16) + C.  Lane l
+// supplies A[l % 16][l / 16] and B[l / 16][l % 16]; element r (0..3) of the
+// per-lane result holds D[l / 16 + 4 r][l % 16] (rows interleaved by 4).
+// The FP32 16x16x4 form takes operands the same way but returns
+// D[4 (l / 16) + r][l % 16]; the BF16 16x16x32 form gives each lane 8
+// consecutive k values, A[l % 16][8 (l / 16) + 0..7] and
+// B[8 (l / 16) + 0..7][l % 16], with the FP32 result layout.  These layouts
+// are checked on the device by gl_selftest.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace gl {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+// result coordinates of element r of lane `lane`
+__device__ inline int mfma_row(int lane, int r) { return (lane >> 4) + 4 * r; }  // FP64 form
+__device__ inline int mfma_col(int lane) { return lane & 15; }
+__device__ inline int mfma32_row(int lane, int r) { return 4 * (lane >> 4) + r; }  // FP32 / BF16 forms
+
+__device__ inline d4 mfma_f64(double a, double b, d4 c)
+{
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+__device__ inline f4 mfma_f32(float a, float b, f4 c)
+{
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+__device__ inline f4 mfma_bf16(bf16x8 a, bf16x8 b, f4 c)
+{
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
+// Wave-wide sum (fixed butterfly order, identical on every lane).
+__device__ inline double wave_sum(double v)
+{
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+}  // namespace gl

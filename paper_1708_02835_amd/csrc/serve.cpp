@@ -1,0 +1,489 @@
+// Request queue for many concurrent likelihood clients (the optimiser callbacks
+// of Sec. 5.2, each asking for l(θ) at a new θ).
+//
+// A scheduler thread owns a set of device slots (a stream, a lookahead lane,
+// a workspace and a pinned result buffer each).  Queued requests are admitted
+// in arrival order while a slot is free and the device bytes held by slots
+// stay within the HBM budget; an admitted request's whole evaluation is
+// enqueued on its slot's stream, so requests that arrive while others are on
+// the device overlap with them.  Completion is detected with events and the
+// slot is reused for the next queued request.
+#include <chrono>
+#include <condition_variable>
+#include <deque>
+#include <map>
+#include <thread>
+#include <unordered_map>
+
+#include "engine.hpp"
+
+namespace gl {
+
+struct Dataset {
+    uint64_t id = 0;
+    int64_t n = 0;
+    double *buf = nullptr;  // x | y | z, n each
+    std::atomic<int> refs{0};
+    std::atomic<bool> dropped{false};
+    std::atomic<bool> freed{false};
+    void free_once()
+    {
+        if (!freed.exchange(true)) {
+            if (buf) hipFree(buf);
+            buf = nullptr;
+        }
+    }
+};
+
+struct ServeState {
+    std::mutex mu;
+    std::map<uint64_t, Dataset *> sets;
+    std::vector<Dataset *> graveyard;  // dropped datasets, deleted with the context
+    std::vector<lq_queue *> queues;
+    uint64_t next = 1;
+};
+
+static ServeState *serve_state(gl_context *ctx)
+{
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    if (!ctx->serve) ctx->serve = new ServeState();
+    return ctx->serve;
+}
+
+void serve_context_cleanup(gl_context *ctx)
+{
+    ServeState *st = ctx->serve;
+    if (!st) return;
+    for (auto &kv : st->sets) {
+        kv.second->free_once();
+        delete kv.second;
+    }
+    for (Dataset *d : st->graveyard) {
+        d->free_once();
+        delete d;
+    }
+    delete st;
+    ctx->serve = nullptr;
+}
+
+}  // namespace gl
+
+using namespace gl;
+
+namespace {
+
+enum ReqState { QUEUED = 0, RUNNING = 1, DONE = 2 };
+
+struct Request {
+    uint64_t ticket = 0;
+    Dataset *ds = nullptr;
+    gl_theta th{};
+    gl_opts o{};
+    int state = QUEUED;
+    gl_result res{};
+};
+
+struct Slot {
+    hipStream_t s = nullptr;
+    Lanes ln;
+    Work w;
+    DevResult *res_h = nullptr;
+    hipEvent_t done = nullptr;
+    Request *req = nullptr;
+};
+
+}  // namespace
+
+struct lq_queue {
+    gl_context *ctx = nullptr;
+    lq_config cfg{};
+    size_t budget = 0;
+    std::mutex mu;
+    std::condition_variable cv_work, cv_done;
+    std::deque<Request *> queue;
+    std::unordered_map<uint64_t, Request *> reqs;
+    uint64_t next_ticket = 1;
+    bool stop = false;
+    std::vector<Slot> slots;
+    int inflight = 0, peak_inflight = 0;
+    size_t peak_bytes = 0;
+    uint64_t completed = 0, fused = 0;
+    std::thread thr;
+};
+
+namespace {
+
+size_t slot_bytes(const Slot &sl) { return sl.w.tile_cap + sl.w.vec_cap; }
+
+size_t held_bytes(const lq_queue *q)
+{
+    size_t t = 0;
+    for (const Slot &sl : q->slots) t += slot_bytes(sl);
+    return t;
+}
+
+void finish(lq_queue *q, Request *r, int status)
+{
+    r->res.status = status;
+    r->state = DONE;
+    Dataset *d = r->ds;
+    r->ds = nullptr;
+    if (d && d->refs.fetch_sub(1) == 1 && d->dropped.load()) d->free_once();
+    q->cv_done.notify_all();
+}
+
+// Launch request r on slot sl (queue lock released by the caller).
+int launch_on_slot(gl_context *ctx, Slot &sl, Request *r)
+{
+    const int64_t n = r->ds->n;
+    const int b = pick_tile(n, r->o.tile);
+    int rc = sl.w.ensure(ctx, n, b, r->o.precision);
+    if (rc != GL_OK) return rc;
+    const double *x = r->ds->buf, *y = x + n, *z = y + n;
+    launch_copy_pad(x, n, sl.w.x, sl.w.npad, 0.0, sl.s);
+    launch_copy_pad(y, n, sl.w.y, sl.w.npad, 0.0, sl.s);
+    launch_copy_pad(z, n, sl.w.v, sl.w.npad, 0.0, sl.s);
+    rc = eval_launch(sl.ln, sl.w, r->th, r->o, sl.s, sl.res_h);
+    if (rc != GL_OK) return rc;
+    GL_HIP_TRY(hipEventRecord(sl.done, sl.s));
+    return GL_OK;
+}
+
+void scheduler(lq_queue *q)
+{
+    hipSetDevice(q->ctx->device);
+    std::unique_lock<std::mutex> lk(q->mu);
+    for (;;) {
+        // retire finished slots
+        for (Slot &sl : q->slots) {
+            if (!sl.req) continue;
+            hipError_t e = hipEventQuery(sl.done);
+            if (e == hipErrorNotReady) continue;
+            Request *r = sl.req;
+            sl.req = nullptr;
+            --q->inflight;
+            ++q->completed;
+            if (e != hipSuccess) {
+                finish(q, r, GL_EHIP);
+                continue;
+            }
+            r->res.loglik = sl.res_h->loglik;
+            r->res.logdet = sl.res_h->logdet;
+            r->res.quad = sl.res_h->quad;
+            r->res.info = sl.res_h->info;
+            r->res.tile = sl.w.b;
+            r->res.factor = nullptr;
+            finish(q, r, sl.res_h->info ? GL_NOT_SPD : GL_OK);
+        }
+        // admit queued requests into free slots, in arrival order
+        while (!q->queue.empty()) {
+            Slot *free_slot = nullptr;
+            for (Slot &sl : q->slots)
+                if (!sl.req) {
+                    free_slot = &sl;
+                    break;
+                }
+            if (!free_slot) break;
+            Request *r = q->queue.front();
+            const int64_t n = r->ds->n;
+            const size_t need = work_bytes(n, pick_tile(n, r->o.tile), r->o.precision);
+            size_t held = held_bytes(q);
+            const size_t mine = slot_bytes(*free_slot);
+            if (need > mine && held - mine + need > q->budget) {
+                // give back the memory of idle slots first
+                for (Slot &sl : q->slots)
+                    if (!sl.req && &sl != free_slot && slot_bytes(sl)) {
+                        q->ctx->used -= slot_bytes(sl);
+                        sl.w.release();
+                    }
+                held = held_bytes(q);
+                if (held - mine + need > q->budget) {
+                    if (q->inflight > 0) break;  // wait for running requests to free memory
+                    q->queue.pop_front();
+                    finish(q, r, GL_ENOMEM);  // larger than the whole budget
+                    continue;
+                }
+            }
+            q->queue.pop_front();
+            r->state = RUNNING;
+            free_slot->req = r;
+            ++q->inflight;
+            if (q->inflight > q->peak_inflight) q->peak_inflight = q->inflight;
+            lk.unlock();
+            int rc = launch_on_slot(q->ctx, *free_slot, r);
+            lk.lock();
+            if (rc != GL_OK) {
+                free_slot->req = nullptr;
+                --q->inflight;
+                finish(q, r, rc);
+            }
+            const size_t h = held_bytes(q);
+            if (h > q->peak_bytes) q->peak_bytes = h;
+        }
+        if (q->stop && q->queue.empty() && q->inflight == 0) break;
+        if (q->inflight > 0) {
+            lk.unlock();
+            std::this_thread::sleep_for(std::chrono::microseconds(20));
+            lk.lock();
+        } else {
+            q->cv_work.wait(lk, [q] { return q->stop || !q->queue.empty(); });
+        }
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+int gl_dataset_register(gl_context *ctx, const double *x, const double *y, const double *z, int64_t n,
+                        uint64_t *ds_h)
+{
+    if (!ctx || !x || !y || !z || n < 1 || !ds_h) return GL_EINVAL;
+    GL_HIP_TRY(hipSetDevice(ctx->device));
+    ServeState *st = serve_state(ctx);
+    const size_t bytes = 3 * (size_t)n * sizeof(double);
+    if (ctx->used.load() + bytes > ctx->budget) return GL_ENOMEM;
+    Dataset *d = new Dataset();
+    d->n = n;
+    if (hipMalloc(reinterpret_cast<void **>(&d->buf), bytes) != hipSuccess) {
+        delete d;
+        return GL_ENOMEM;
+    }
+    ctx->used += bytes;
+    hipError_t e = hipMemcpy(d->buf, x, n * sizeof(double), hipMemcpyDeviceToDevice);
+    if (e == hipSuccess) e = hipMemcpy(d->buf + n, y, n * sizeof(double), hipMemcpyDeviceToDevice);
+    if (e == hipSuccess) e = hipMemcpy(d->buf + 2 * n, z, n * sizeof(double), hipMemcpyDeviceToDevice);
+    if (e != hipSuccess) {
+        hipFree(d->buf);
+        ctx->used -= bytes;
+        delete d;
+        return gl_hip_fail(e, "gl_dataset_register copy");
+    }
+    std::lock_guard<std::mutex> lk(st->mu);
+    d->id = st->next++;
+    st->sets[d->id] = d;
+    *ds_h = d->id;
+    return GL_OK;
+}
+
+int gl_dataset_release(gl_context *ctx, uint64_t id)
+{
+    if (!ctx) return GL_EINVAL;
+    ServeState *st = serve_state(ctx);
+    Dataset *d = nullptr;
+    std::vector<lq_queue *> queues;
+    {
+        std::lock_guard<std::mutex> lk(st->mu);
+        auto it = st->sets.find(id);
+        if (it == st->sets.end()) return GL_EINVAL;
+        d = it->second;
+        st->sets.erase(it);
+        st->graveyard.push_back(d);
+        queues = st->queues;
+    }
+    for (lq_queue *q : queues) {
+        std::lock_guard<std::mutex> lk(q->mu);
+        for (auto it = q->queue.begin(); it != q->queue.end();) {
+            if ((*it)->ds == d) {
+                Request *r = *it;
+                it = q->queue.erase(it);
+                finish(q, r, GL_ECANCELED);
+            } else {
+                ++it;
+            }
+        }
+    }
+    d->dropped = true;
+    if (d->refs.load() == 0) {
+        hipSetDevice(ctx->device);
+        d->free_once();
+    }
+    ctx->used -= 3 * (size_t)d->n * sizeof(double);
+    return GL_OK;
+}
+
+void lq_config_default(lq_config *c)
+{
+    if (!c) return;
+    c->max_inflight = 8;
+    c->streams = 4;
+    c->batch_small = 1;
+    c->small_n = 16384;
+    c->hbm_budget_bytes = 0;
+}
+
+int lq_create(gl_context *ctx, const lq_config *cfg, lq_queue **out)
+{
+    if (!ctx || !out) return GL_EINVAL;
+    lq_config c;
+    lq_config_default(&c);
+    if (cfg) c = *cfg;
+    if (c.max_inflight < 1 || c.max_inflight > 64 || c.streams < 1 || c.streams > 8) return GL_EINVAL;
+    GL_HIP_TRY(hipSetDevice(ctx->device));
+    lq_queue *q = new lq_queue();
+    q->ctx = ctx;
+    q->cfg = c;
+    q->budget = c.hbm_budget_bytes ? c.hbm_budget_bytes : ctx->budget;
+    q->slots.resize(c.max_inflight);
+    for (Slot &sl : q->slots) {
+        if (hipStreamCreateWithFlags(&sl.s, hipStreamNonBlocking) != hipSuccess || sl.ln.create() != GL_OK ||
+            hipEventCreateWithFlags(&sl.done, hipEventDisableTiming) != hipSuccess ||
+            hipHostMalloc(reinterpret_cast<void **>(&sl.res_h), sizeof(DevResult), hipHostMallocDefault) !=
+                hipSuccess) {
+            q->stop = true;
+            lq_destroy(q);
+            return GL_EHIP;
+        }
+    }
+    ServeState *st = serve_state(ctx);
+    {
+        std::lock_guard<std::mutex> lk(st->mu);
+        st->queues.push_back(q);
+    }
+    q->thr = std::thread(scheduler, q);
+    *out = q;
+    return GL_OK;
+}
+
+int lq_submit(lq_queue *q, uint64_t ds, gl_theta th, const gl_opts *opts, uint64_t *ticket)
+{
+    if (!q || !ticket || !valid_theta(th)) return GL_EINVAL;
+    gl_opts o;
+    gl_opts_default(&o);
+    if (opts) o = *opts;
+    o.keep_factor = 0;
+    if (!valid_opts(o)) return GL_EINVAL;
+    ServeState *st = serve_state(q->ctx);
+    Request *r = new Request();
+    {
+        std::lock_guard<std::mutex> lk(st->mu);
+        auto it = st->sets.find(ds);
+        if (it == st->sets.end()) {
+            delete r;
+            return GL_EINVAL;
+        }
+        r->ds = it->second;
+        r->ds->refs += 1;
+    }
+    r->th = th;
+    r->o = o;
+    {
+        std::lock_guard<std::mutex> lk(q->mu);
+        if (q->stop) {
+            r->ds->refs -= 1;
+            delete r;
+            return GL_ECANCELED;
+        }
+        r->ticket = q->next_ticket++;
+        q->reqs[r->ticket] = r;
+        q->queue.push_back(r);
+        *ticket = r->ticket;
+    }
+    q->cv_work.notify_one();
+    return GL_OK;
+}
+
+static int take_result(lq_queue *q, std::unordered_map<uint64_t, Request *>::iterator it, gl_result *res)
+{
+    Request *r = it->second;
+    if (res) *res = r->res;
+    const int st = r->res.status;
+    q->reqs.erase(it);
+    delete r;
+    return st;
+}
+
+int lq_poll(lq_queue *q, uint64_t ticket, gl_result *res)
+{
+    if (!q) return GL_EINVAL;
+    std::lock_guard<std::mutex> lk(q->mu);
+    auto it = q->reqs.find(ticket);
+    if (it == q->reqs.end()) return GL_EINVAL;
+    if (it->second->state != DONE) return GL_EBUSY;
+    return take_result(q, it, res);
+}
+
+int lq_wait(lq_queue *q, uint64_t ticket, gl_result *res, int64_t timeout_us)
+{
+    if (!q) return GL_EINVAL;
+    std::unique_lock<std::mutex> lk(q->mu);
+    auto it = q->reqs.find(ticket);
+    if (it == q->reqs.end()) return GL_EINVAL;
+    Request *r = it->second;
+    auto ready = [r] { return r->state == DONE; };
+    if (timeout_us < 0) {
+        q->cv_done.wait(lk, ready);
+    } else if (!q->cv_done.wait_for(lk, std::chrono::microseconds(timeout_us), ready)) {
+        return GL_ETIMEDOUT;
+    }
+    return take_result(q, q->reqs.find(ticket), res);
+}
+
+int lq_cancel(lq_queue *q, uint64_t ticket)
+{
+    if (!q) return GL_EINVAL;
+    std::lock_guard<std::mutex> lk(q->mu);
+    auto it = q->reqs.find(ticket);
+    if (it == q->reqs.end()) return GL_EINVAL;
+    Request *r = it->second;
+    if (r->state != QUEUED) return GL_EBUSY;
+    for (auto qi = q->queue.begin(); qi != q->queue.end(); ++qi)
+        if (*qi == r) {
+            q->queue.erase(qi);
+            break;
+        }
+    finish(q, r, GL_ECANCELED);
+    return GL_OK;
+}
+
+int lq_stats(lq_queue *q, uint64_t *completed, size_t *peak_bytes, int32_t *peak_inflight,
+             uint64_t *fused_launches)
+{
+    if (!q) return GL_EINVAL;
+    std::lock_guard<std::mutex> lk(q->mu);
+    if (completed) *completed = q->completed;
+    if (peak_bytes) *peak_bytes = q->peak_bytes;
+    if (peak_inflight) *peak_inflight = q->peak_inflight;
+    if (fused_launches) *fused_launches = q->fused;
+    return GL_OK;
+}
+
+int lq_destroy(lq_queue *q)
+{
+    if (!q) return GL_EINVAL;
+    {
+        std::lock_guard<std::mutex> lk(q->mu);
+        q->stop = true;
+        while (!q->queue.empty()) {
+            Request *r = q->queue.front();
+            q->queue.pop_front();
+            finish(q, r, GL_ECANCELED);
+        }
+    }
+    q->cv_work.notify_all();
+    if (q->thr.joinable()) q->thr.join();
+    if (q->ctx->serve) {
+        std::lock_guard<std::mutex> lk(q->ctx->serve->mu);
+        auto &v = q->ctx->serve->queues;
+        for (size_t i = 0; i < v.size(); ++i)
+            if (v[i] == q) {
+                v.erase(v.begin() + i);
+                break;
+            }
+    }
+    hipSetDevice(q->ctx->device);
+    for (Slot &sl : q->slots) {
+        if (sl.s) hipStreamSynchronize(sl.s);
+        q->ctx->used -= slot_bytes(sl);
+        sl.w.release();
+        sl.ln.destroy();
+        if (sl.s) hipStreamDestroy(sl.s);
+        if (sl.done) hipEventDestroy(sl.done);
+        if (sl.res_h) hipHostFree(sl.res_h);
+    }
+    for (auto &kv : q->reqs) delete kv.second;
+    delete q;
+    return GL_OK;
+}
+
+}  // extern "C"

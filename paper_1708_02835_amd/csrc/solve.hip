@@ -1,0 +1,306 @@
+// Triangular solves, TRMV and the scalar reductions on the packed tile factor.
+//
+//  * forward solve w = L⁻¹ Z (Alg. 2 step 4, "dtrsm" with one right-hand side),
+//    by tile columns: solve the diagonal block, then subtract L_ik w_k from the
+//    blocks below; the diagonal-block kernel also emits the tile's part of
+//    wᵀw (Alg. 2 step 6);
+//  * backward solve X = L⁻ᵀ w (the second half of "dposv" in Alg. 3);
+//  * Z = L e (Alg. 1 step 7, "dtrmm");
+//  * the final fixed-order reduction of the per-tile log-det and quadratic
+//    form parts into l(θ) (Alg. 2 step 7, Eq. (1)).
+// Every reduction has a fixed order, so results do not depend on scheduling.
+#include <math.h>
+
+#include "common.hpp"
+#include "mfma.hpp"
+
+namespace gl {
+
+// v_k <- L_kk⁻¹ v_k.  Wave 0 solves 64×64 diagonal blocks by column
+// substitution with the running right-hand side in registers; all four waves
+// then apply the block's columns to the rows below it.
+template <int B>
+__global__ __launch_bounds__(256) void fwd_diag_kernel(const double *__restrict__ tiles, int64_t k,
+                                                       int64_t n, double *__restrict__ v,
+                                                       double *__restrict__ quad_part,
+                                                       const int64_t *__restrict__ info)
+{
+    if (info && *info != 0) return;
+    const double *L = tiles + tile_offset(k, k, B);
+    double *vk = v + k * B;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+    __shared__ double xs[B];
+    __shared__ double red[4];
+    for (int r = tid; r < B; r += 256) xs[r] = vk[r];
+    __syncthreads();
+    for (int s = 0; s < B; s += 64) {
+        if (wave == 0) {
+            double z = xs[s + lane];
+            for (int c = 0; c < 64; ++c) {
+                const double lc = L[(int64_t)(s + c) * B + s + lane];
+                const double xc = __shfl(z, c, 64) / L[(int64_t)(s + c) * B + s + c];
+                if (lane == c) z = xc;
+                else if (lane > c) z -= lc * xc;
+            }
+            xs[s + lane] = z;
+        }
+        __syncthreads();
+        for (int r = s + 64 + tid; r < B; r += 256) {
+            double acc = 0.0;
+            for (int c = 0; c < 64; ++c) acc += L[(int64_t)(s + c) * B + r] * xs[s + c];
+            xs[r] -= acc;
+        }
+        __syncthreads();
+    }
+    double q = 0.0;
+    for (int r = tid; r < B; r += 256) {
+        vk[r] = xs[r];
+        if (k * B + r < n) q += xs[r] * xs[r];
+    }
+    if (quad_part) {
+        double w = wave_sum(q);
+        if (lane == 0) red[wave] = w;
+        __syncthreads();
+        if (tid == 0) quad_part[k] = (red[0] + red[1]) + (red[2] + red[3]);
+    }
+}
+
+// v_i -= L_ik v_k for every tile i > k; workgroup (i, 64-row strip).
+template <int B>
+__global__ __launch_bounds__(256) void fwd_update_kernel(const double *__restrict__ tiles, int64_t k,
+                                                         double *__restrict__ v,
+                                                         const int64_t *__restrict__ info)
+{
+    if (info && *info != 0) return;
+    const int64_t i = k + 1 + blockIdx.x;
+    const int r0 = blockIdx.y * 64;
+    const double *L = tiles + tile_offset(i, k, B);
+    const int tid = threadIdx.x;
+    __shared__ double wk[B];
+    __shared__ double red[4][64];
+    for (int c = tid; c < B; c += 256) wk[c] = v[k * B + c];
+    __syncthreads();
+    const int r = tid & 63, g = tid >> 6;
+    double acc = 0.0;
+    for (int c = g; c < B; c += 4) acc += L[(int64_t)c * B + r0 + r] * wk[c];
+    red[g][r] = acc;
+    __syncthreads();
+    if (g == 0) v[i * B + r0 + r] -= (red[0][r] + red[1][r]) + (red[2][r] + red[3][r]);
+}
+
+// v_k <- L_kk⁻ᵀ v_k, 64-row blocks from the bottom: the block's rows first
+// receive the contributions of the solved rows below it (column dot products),
+// then wave 0 back-substitutes the 64×64 block held in LDS.
+template <int B>
+__global__ __launch_bounds__(256) void bwd_diag_kernel(const double *__restrict__ tiles, int64_t k,
+                                                       double *__restrict__ v)
+{
+    const double *L = tiles + tile_offset(k, k, B);
+    double *vk = v + k * B;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+    __shared__ double xs[B];
+    __shared__ double Lb[64][65];  // Lb[c][r] = L[s + r][s + c]
+    for (int r = tid; r < B; r += 256) xs[r] = vk[r];
+    __syncthreads();
+    for (int s = B - 64; s >= 0; s -= 64) {
+        // xs[c] -= Σ_{r >= s+64} L[r][c] xs[r] for the 64 columns c of this block
+        for (int cc = wave * 16; cc < wave * 16 + 16; ++cc) {
+            const int c = s + cc;
+            double acc = 0.0;
+            for (int r = s + 64 + lane; r < B; r += 64) acc += L[(int64_t)c * B + r] * xs[r];
+            acc = wave_sum(acc);
+            if (lane == 0) xs[c] -= acc;
+        }
+        for (int e = tid; e < 64 * 64; e += 256) {
+            const int c = e >> 6, r = e & 63;
+            Lb[c][r] = L[(int64_t)(s + c) * B + s + r];
+        }
+        __syncthreads();
+        if (wave == 0) {
+            double z = xs[s + lane];
+            for (int c = 63; c >= 0; --c) {
+                const double xc = __shfl(z, c, 64) / Lb[c][c];
+                if (lane == c) z = xc;
+                else if (lane < c) z -= Lb[lane][c] * xc;  // L[s + c][s + lane]
+            }
+            xs[s + lane] = z;
+        }
+        __syncthreads();
+    }
+    for (int r = tid; r < B; r += 256) vk[r] = xs[r];
+}
+
+// v_j -= L_kjᵀ v_k for every tile j < k; workgroup (j, 64-column strip),
+// each wave 16 columns, one column dot product at a time.
+template <int B>
+__global__ __launch_bounds__(256) void bwd_update_kernel(const double *__restrict__ tiles, int64_t k,
+                                                         double *__restrict__ v)
+{
+    const int64_t j = blockIdx.x;
+    const int c0 = blockIdx.y * 64;
+    const double *L = tiles + tile_offset(k, j, B);
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+    __shared__ double xk[B];
+    for (int r = tid; r < B; r += 256) xk[r] = v[k * B + r];
+    __syncthreads();
+    for (int cc = wave * 16; cc < wave * 16 + 16; ++cc) {
+        const int c = c0 + cc;
+        double acc = 0.0;
+        for (int r = lane; r < B; r += 64) acc += L[(int64_t)c * B + r] * xk[r];
+        acc = wave_sum(acc);
+        if (lane == 0) v[j * B + c] -= acc;
+    }
+}
+
+// z_i = Σ_{j<i} L_ij e_j + tril(L_ii) e_i; workgroup (i, 64-row strip).
+template <int B>
+__global__ __launch_bounds__(256) void trmv_kernel(const double *__restrict__ tiles,
+                                                   const double *__restrict__ e,
+                                                   double *__restrict__ z)
+{
+    const int64_t i = blockIdx.x;
+    const int r0 = blockIdx.y * 64;
+    const int tid = threadIdx.x;
+    const int r = tid & 63, g = tid >> 6;
+    __shared__ double red[4][64];
+    double acc = 0.0;
+    for (int64_t j = 0; j <= i; ++j) {
+        const double *L = tiles + tile_offset(i, j, B);
+        const double *ej = e + j * B;
+        const int cend = (j == i) ? (r0 + r + 1) : B;
+        for (int c = g; c < cend; c += 4) acc += L[(int64_t)c * B + r0 + r] * ej[c];
+    }
+    red[g][r] = acc;
+    __syncthreads();
+    if (g == 0) z[i * B + r0 + r] = (red[0][r] + red[1][r]) + (red[2][r] + red[3][r]);
+}
+
+// One wave: logdet = Σ_k logsum[k], quad = Σ_k quad_part[k], l by Eq. (1).
+__global__ void final_reduce_kernel(const double *__restrict__ logsum,
+                                    const double *__restrict__ quad_part, int64_t nt, int64_t n,
+                                    const int64_t *__restrict__ info, DevResult *__restrict__ res)
+{
+    const int lane = threadIdx.x;
+    double a = 0.0, b = 0.0;
+    for (int64_t t = lane; t < nt; t += 64) {
+        a += logsum[t];
+        b += quad_part[t];
+    }
+    a = wave_sum(a);
+    b = wave_sum(b);
+    if (lane == 0) {
+        const int64_t inf = *info;
+        res->info = inf;
+        if (inf != 0) {
+            res->loglik = -INFINITY;
+            res->logdet = NAN;
+            res->quad = NAN;
+        } else {
+            res->logdet = a;
+            res->quad = b;
+            res->loglik = -0.5 * b - 0.5 * a - 0.5 * (double)n * log(2.0 * M_PI);
+        }
+    }
+}
+
+__global__ void fill_kernel(double *__restrict__ p, int64_t count, double v)
+{
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < count) p[i] = v;
+}
+
+__global__ void copy_pad_kernel(const double *__restrict__ src, int64_t n, double *__restrict__ dst,
+                                int64_t npad, double padv)
+{
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < npad) dst[i] = (i < n) ? src[i] : padv;
+}
+
+// Dense column-major copy of the n×n lower factor, zero strict upper triangle.
+__global__ void tiles_to_dense_kernel(const double *__restrict__ tiles, int b, int64_t n,
+                                      double *__restrict__ out, int64_t ld)
+{
+    const int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (r >= n) return;
+    for (int64_t c = blockIdx.y; c < n; c += gridDim.y) {
+        double v = 0.0;
+        if (r >= c) {
+            const int64_t ti = r / b, tj = c / b;
+            v = tiles[tile_offset(ti, tj, b) + (c % b) * b + (r % b)];
+        }
+        out[r + c * ld] = v;
+    }
+}
+
+#define GL_DISPATCH_B(b, KERNEL, GRID, ...)                                   \
+    switch (b) {                                                              \
+    case 128: KERNEL<128><<<GRID, 256, 0, s>>>(__VA_ARGS__); break;           \
+    case 256: KERNEL<256><<<GRID, 256, 0, s>>>(__VA_ARGS__); break;           \
+    case 384: KERNEL<384><<<GRID, 256, 0, s>>>(__VA_ARGS__); break;           \
+    default: KERNEL<512><<<GRID, 256, 0, s>>>(__VA_ARGS__); break;            \
+    }
+
+void launch_fwd_diag(const double *tiles, int b, int64_t k, int64_t n, double *v, double *quad_part,
+                     const int64_t *info, hipStream_t s)
+{
+    GL_DISPATCH_B(b, fwd_diag_kernel, dim3(1), tiles, k, n, v, quad_part, info);
+}
+
+void launch_fwd_update(const double *tiles, int b, int64_t nt, int64_t k, double *v,
+                       const int64_t *info, hipStream_t s)
+{
+    if (nt - k - 1 <= 0) return;
+    dim3 grid((unsigned)(nt - k - 1), (unsigned)(b / 64));
+    GL_DISPATCH_B(b, fwd_update_kernel, grid, tiles, k, v, info);
+}
+
+void launch_bwd_diag(const double *tiles, int b, int64_t k, double *v, hipStream_t s)
+{
+    GL_DISPATCH_B(b, bwd_diag_kernel, dim3(1), tiles, k, v);
+}
+
+void launch_bwd_update(const double *tiles, int b, int64_t k, double *v, hipStream_t s)
+{
+    if (k <= 0) return;
+    dim3 grid((unsigned)k, (unsigned)(b / 64));
+    GL_DISPATCH_B(b, bwd_update_kernel, grid, tiles, k, v);
+}
+
+void launch_trmv(const double *tiles, int b, int64_t nt, const double *e, double *z, hipStream_t s)
+{
+    dim3 grid((unsigned)nt, (unsigned)(b / 64));
+    GL_DISPATCH_B(b, trmv_kernel, grid, tiles, e, z);
+}
+
+void launch_final_reduce(const double *logsum, const double *quad_part, int64_t nt, int64_t n,
+                         const int64_t *info, DevResult *res, hipStream_t s)
+{
+    final_reduce_kernel<<<1, 64, 0, s>>>(logsum, quad_part, nt, n, info, res);
+}
+
+void launch_fill(double *p, int64_t count, double v, hipStream_t s)
+{
+    if (count <= 0) return;
+    fill_kernel<<<(unsigned)ceil_div(count, 256), 256, 0, s>>>(p, count, v);
+}
+
+void launch_copy_pad(const double *src, int64_t n, double *dst, int64_t npad, double padv,
+                     hipStream_t s)
+{
+    copy_pad_kernel<<<(unsigned)ceil_div(npad, 256), 256, 0, s>>>(src, n, dst, npad, padv);
+}
+
+void launch_tiles_to_dense(const double *tiles, int b, int64_t n, double *out, int64_t ld,
+                           hipStream_t s)
+{
+    dim3 grid((unsigned)ceil_div(n, 256), (unsigned)(n < 65535 ? n : 65535));
+    tiles_to_dense_kernel<<<grid, 256, 0, s>>>(tiles, b, n, out, ld);
+}
+
+}  // namespace gl

@@ -1,0 +1,166 @@
+// Trailing update of the right-looking tile Cholesky (the SYRK and GEMM tasks
+// of the tile algorithm, Sec. 4.2): after step k,
+//   A_ij -= L_ik L_jkᵀ   for every tile k < j <= i < NT,
+// in FP64 on the matrix cores.
+//
+// One launch covers the tiles of a range of tile columns [jbeg, jbeg+jcount).
+// Each workgroup (256 threads, 4 waves in a 2×2 arrangement) computes one
+// 128×128 block of one tile with K = b: the 128-row slices of L_ik and L_jk
+// are streamed through LDS in 16-column chunks, double-buffered, and every
+// wave accumulates a 64×64 block as 4×4 FP64 16x16x4 products.
+// Upper blocks of diagonal tiles are skipped (only the lower triangle of A_ii
+// is ever read).
+//
+// Workgroups are dispatched round-robin over the 8 XCDs; the logical block
+// index is remapped so that each XCD works on a contiguous run of blocks,
+// i.e. on whole tiles and on neighbouring tiles of one column, which share
+// the L_jk operand in that XCD's L2.
+#include "common.hpp"
+#include "mfma.hpp"
+
+namespace gl {
+
+constexpr int GB = 128;  // output block edge
+constexpr int GK = 16;   // k chunk
+
+// Tiles of columns jbeg, jbeg+1, ... in column order; column jbeg + c holds
+// rows i = jbeg + c .. nt-1.  Maps a linear index to (i, j).
+__device__ inline void trailing_tile(int64_t t, int64_t jbeg, int64_t nt, int64_t &i, int64_t &j)
+{
+    const int64_t m0 = nt - jbeg;
+    const double a = 2.0 * (double)m0 + 1.0;
+    int64_t c = (int64_t)((a - sqrt(a * a - 8.0 * (double)t)) * 0.5);
+    if (c < 0) c = 0;
+    while (c > 0 && c * m0 - c * (c - 1) / 2 > t) --c;
+    while ((c + 1) * m0 - (c + 1) * c / 2 <= t) ++c;
+    j = jbeg + c;
+    i = j + (t - (c * m0 - c * (c - 1) / 2));
+}
+
+template <int B>
+__global__ __launch_bounds__(256, 2) void trailing_f64_kernel(double *__restrict__ tiles, int64_t k,
+                                                              int64_t jbeg, int64_t nt,
+                                                              int64_t nblocks,
+                                                              const int64_t *__restrict__ info)
+{
+    if (*info != 0) return;
+    constexpr int SB = B / GB;
+    constexpr int SUB = SB * SB;
+    const int64_t G = gridDim.x;  // a multiple of 8
+    const int64_t g = blockIdx.x;
+    const int64_t lid = (g & 7) * (G >> 3) + (g >> 3);
+    if (lid >= nblocks) return;
+    const int64_t t = lid / SUB;
+    const int sub = (int)(lid % SUB);
+    int64_t i, j;
+    trailing_tile(t, jbeg, nt, i, j);
+    const int rb = sub / SB, cb = sub % SB;
+    if (i == j && cb > rb) return;
+
+    const double *Ap = tiles + tile_offset(i, k, B) + rb * GB;
+    const double *Bp = tiles + tile_offset(j, k, B) + cb * GB;
+    double *C = tiles + tile_offset(i, j, B) + (int64_t)(cb * GB) * B + rb * GB;
+
+    __shared__ double As[2][GK][GB];
+    __shared__ double Bs[2][GK][GB];
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+    const int wm = wave >> 1, wn = wave & 1;
+    const int lc = tid >> 4;         // chunk column 0..15
+    const int lr = (tid & 15) * 8;   // chunk row 0..120, 8 consecutive rows
+
+    d4 acc[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] = (d4){0.0, 0.0, 0.0, 0.0};
+
+    double2 ra[4], rbv[4];
+    {
+        const double2 *pa = reinterpret_cast<const double2 *>(Ap + (int64_t)lc * B + lr);
+        const double2 *pb = reinterpret_cast<const double2 *>(Bp + (int64_t)lc * B + lr);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            ra[q] = pa[q];
+            rbv[q] = pb[q];
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            *reinterpret_cast<double2 *>(&As[0][lc][lr + 2 * q]) = ra[q];
+            *reinterpret_cast<double2 *>(&Bs[0][lc][lr + 2 * q]) = rbv[q];
+        }
+    }
+    __syncthreads();
+
+    constexpr int NK = B / GK;
+    for (int kc = 0; kc < NK; ++kc) {
+        const int cur = kc & 1;
+        if (kc + 1 < NK) {
+            const int64_t col = (int64_t)(kc + 1) * GK + lc;
+            const double2 *pa = reinterpret_cast<const double2 *>(Ap + col * B + lr);
+            const double2 *pb = reinterpret_cast<const double2 *>(Bp + col * B + lr);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                ra[q] = pa[q];
+                rbv[q] = pb[q];
+            }
+        }
+#pragma unroll
+        for (int kk = 0; kk < GK; kk += 4) {
+            double av[4], bv[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                av[q] = As[cur][kk + (lane >> 4)][wm * 64 + q * 16 + (lane & 15)];
+                bv[q] = Bs[cur][kk + (lane >> 4)][wn * 64 + q * 16 + (lane & 15)];
+            }
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int b = 0; b < 4; ++b) acc[a][b] = mfma_f64(av[a], bv[b], acc[a][b]);
+        }
+        if (kc + 1 < NK) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                *reinterpret_cast<double2 *>(&As[cur ^ 1][lc][lr + 2 * q]) = ra[q];
+                *reinterpret_cast<double2 *>(&Bs[cur ^ 1][lc][lr + 2 * q]) = rbv[q];
+            }
+        }
+        __syncthreads();
+    }
+
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            const int64_t col = wn * 64 + b * 16 + mfma_col(lane);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = wm * 64 + a * 16 + mfma_row(lane, r);
+                C[col * B + row] -= acc[a][b][r];
+            }
+        }
+    }
+}
+
+void launch_trailing(double *tiles, int b, int64_t nt, int64_t k, int64_t jbeg, int64_t jend,
+                     const int64_t *info, hipStream_t s)
+{
+    if (jbeg > jend || jbeg >= nt) return;
+    // tiles in columns jbeg..jend, rows j..nt-1
+    const int64_t m0 = nt - jbeg;
+    const int64_t cols = jend - jbeg + 1;
+    const int64_t ntiles = cols * m0 - cols * (cols - 1) / 2;
+    const int64_t sub = (int64_t)(b / GB) * (b / GB);
+    const int64_t nblocks = ntiles * sub;
+    const int64_t grid = ceil_div(nblocks, 8) * 8;
+    switch (b) {
+    case 128: trailing_f64_kernel<128><<<(unsigned)grid, 256, 0, s>>>(tiles, k, jbeg, nt, nblocks, info); break;
+    case 256: trailing_f64_kernel<256><<<(unsigned)grid, 256, 0, s>>>(tiles, k, jbeg, nt, nblocks, info); break;
+    case 384: trailing_f64_kernel<384><<<(unsigned)grid, 256, 0, s>>>(tiles, k, jbeg, nt, nblocks, info); break;
+    default: trailing_f64_kernel<512><<<(unsigned)grid, 256, 0, s>>>(tiles, k, jbeg, nt, nblocks, info); break;
+    }
+}
+
+}  // namespace gl

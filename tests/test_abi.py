@@ -1,0 +1,85 @@
+"""CPU checks of the C-ABI library: it loads, exports every function declared
+in include/geolik.h, and its host-only entry points behave as documented.
+No compute call is made here (there is no GPU in this environment)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "geolik.h")
+
+
+def _ensure_built():
+    from paper_1708_02835_amd import build as b
+    if not os.path.exists(b.LIB):
+        b.build()
+    return b.LIB
+
+
+def _declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z0-9_]*\s*\**\s*([a-z_][a-z0-9_]*)\s*\(", text, flags=re.M)
+    return sorted(set(names))
+
+
+def test_header_declares_the_entry_points():
+    names = _declared_functions()
+    for must in ["matern_generate", "loglik_eval", "krige_predict", "synth_generate", "lq_submit",
+                 "lq_poll", "lq_wait", "lq_create", "lq_destroy", "gl_context_create"]:
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol():
+    lib = ctypes.CDLL(_ensure_built())
+    missing = [n for n in _declared_functions() if not hasattr(lib, n)]
+    assert missing == []
+
+
+def test_binding_names_match_header():
+    import paper_1708_02835_amd as g
+    missing = [n for n in _declared_functions() if not hasattr(g, n)]
+    assert missing == []
+
+
+def test_status_strings_and_defaults():
+    _ensure_built()
+    import paper_1708_02835_amd as g
+    assert g.gl_status_string(g.GL_OK) == "ok"
+    assert "positive definite" in g.gl_status_string(g.GL_NOT_SPD)
+    for st in [g.GL_EINVAL, g.GL_ENOMEM, g.GL_EHIP, g.GL_EBUSY, g.GL_ECANCELED, g.GL_ETIMEDOUT, g.GL_ENODEV]:
+        assert g.gl_status_string(st) != "unknown status"
+    o = g.gl_opts_default()
+    assert (o.precision, o.tile, o.keep_factor, o.band) == (g.GL_FP64, 0, 0, 2)
+    c = g.lq_config_default()
+    assert c.max_inflight >= 1 and 1 <= c.streams <= 8
+
+
+@pytest.mark.parametrize("n,tile", [(1, 128), (1600, 128), (40000, 512), (100000, 512), (100001, 256)])
+def test_footprint_formula(n, tile):
+    _ensure_built()
+    import paper_1708_02835_amd as g
+    nt = -(-n // tile)
+    tiles = nt * (nt + 1) // 2 * tile * tile * 8
+    vec = (3 * nt * tile + 4 * nt + nt * (nt + 1) // 2 + 64) * 8
+    assert g.gl_footprint_bytes(n, tile, g.GL_FP64) == tiles + vec
+
+
+def test_automatic_tile_choice_footprints_are_monotone():
+    _ensure_built()
+    import paper_1708_02835_amd as g
+    sizes = [g.gl_footprint_bytes(n) for n in [1000, 4000, 16000, 40000, 100000]]
+    assert sizes == sorted(sizes)
+
+
+def test_context_create_without_gpu_reports_enodev():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    _ensure_built()
+    import paper_1708_02835_amd as g
+    with pytest.raises(g.GeolikError) as ei:
+        g.Context()
+    assert ei.value.status == g.GL_ENODEV
