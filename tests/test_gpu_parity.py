@@ -9,9 +9,11 @@ cases (n = 1, n below one tile, a singular Σ).  Tolerances:
   each carries up to ~745 ulp of relative rounding there; elsewhere they agree
   to a few ulp.
 * l(θ): 1e-10 relative (the stated FP64 bound) when Σ is well conditioned;
-  for ill-conditioned θ the bound is 4 × the oracle's own permutation noise
-  floor (the largest change of the oracle's l over three reorderings of the
-  locations, which exact arithmetic leaves unchanged), floored at 1e-10.
+  for ill-conditioned θ the bound is 4 × the noise floor of binary64 itself:
+  the largest distance from the oracle of other correct FP64 evaluations of
+  the same l (the oracle on reordered locations, LAPACK's Cholesky, the tiled
+  right-looking order, and LAPACK on Σ with ±1 ulp moved into each entry,
+  i.e. a different correctly rounded Eq. (2)), floored at 1e-10.
 """
 import math
 
@@ -48,15 +50,58 @@ def rel(a, b):
     return abs(a - b) / max(abs(b), 1e-300)
 
 
+def _tiled_loglik(S, z, b):
+    """Right-looking tile Cholesky with LAPACK tile kernels (the same blocking
+    as the device path), then the Alg. 2 scalars — one more correct FP64
+    evaluation order of the same l."""
+    import scipy.linalg as sla
+    n = S.shape[0]
+    nt = -(-n // b)
+    A = np.eye(nt * b)
+    A[:n, :n] = S
+    for k in range(nt):
+        ks = slice(k * b, (k + 1) * b)
+        A[ks, ks] = np.linalg.cholesky(A[ks, ks])
+        for i in range(k + 1, nt):
+            isl = slice(i * b, (i + 1) * b)
+            A[isl, ks] = sla.solve_triangular(A[ks, ks], A[isl, ks].T, lower=True).T
+        for j in range(k + 1, nt):
+            js = slice(j * b, (j + 1) * b)
+            A[j * b:, js] -= A[j * b:, ks] @ A[js, ks].T
+    L = np.tril(A)[:n, :n]
+    w = sla.solve_triangular(L, z, lower=True)
+    return -0.5 * w @ w - np.sum(np.log(np.diag(L))) - 0.5 * n * math.log(2 * math.pi)
+
+
 def noise_floor(x, y, z, theta, reps=3):
-    """Largest relative change of the oracle's own l under reordering of the
-    locations (exact arithmetic gives the same l) over `reps` permutations."""
+    """Spread of correct binary64 evaluations of one l: the largest relative
+    distance from the oracle's value of (a) the oracle on reordered locations
+    (exact arithmetic leaves l unchanged), (b) LAPACK's Cholesky on the
+    oracle's Σ, (c) the tiled right-looking order at tiles 128, 256, 512,
+    (d) LAPACK on Σ with every entry moved by a random -1/0/+1 ulp, which is
+    how far two correctly rounded evaluations of Eq. (2) may differ."""
+    import scipy.linalg as sla
     a = oracle.loglik(x, y, z, theta)[0]
     worst = 0.0
     for seed in range(reps):
         perm = np.random.default_rng(seed).permutation(x.size)
-        b = oracle.loglik(x[perm], y[perm], z[perm], theta)[0]
-        worst = max(worst, rel(b, a))
+        worst = max(worst, rel(oracle.loglik(x[perm], y[perm], z[perm], theta)[0], a))
+    S = oracle.cov_symmetric(x, y, theta)
+    L = np.linalg.cholesky(S)
+    w = sla.solve_triangular(L, z, lower=True)
+    lap = -0.5 * w @ w - np.sum(np.log(np.diag(L))) - 0.5 * x.size * math.log(2 * math.pi)
+    worst = max(worst, rel(lap, a))
+    for b in (128, 256, 512):
+        worst = max(worst, rel(_tiled_loglik(S, z, b), a))
+    rng = np.random.default_rng(1)
+    for _ in range(reps):
+        p = np.triu(rng.integers(-1, 2, size=S.shape), 1)
+        p = p + p.T
+        Sp = np.where(p > 0, np.nextafter(S, np.inf), np.where(p < 0, np.nextafter(S, -np.inf), S))
+        Lp = np.linalg.cholesky(Sp)
+        wp = sla.solve_triangular(Lp, z, lower=True)
+        lp = -0.5 * wp @ wp - np.sum(np.log(np.diag(Lp))) - 0.5 * x.size * math.log(2 * math.pi)
+        worst = max(worst, rel(lp, a))
     return worst
 
 
