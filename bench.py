@@ -39,7 +39,23 @@ def parse():
     p.add_argument("--theta", type=float, nargs=3, default=(1.0, 0.1, 0.5))
     p.add_argument("--seed", type=int, default=3000)
     p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                   help="only run device-to-device copies of MIB mebibytes (HBM counter calibration)")
     return p.parse_args()
+
+
+def calibrate_copy(mib: int) -> None:
+    """Plain device copies of a known size, for scaling the FETCH_SIZE and
+    WRITE_SIZE counters of the benchmark kernels (read: mib MiB, write: mib MiB
+    per copy)."""
+    import torch
+    n = mib * (1 << 20) // 8
+    a = torch.ones(n, dtype=torch.float64, device="cuda:0")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"calibrate_copy_mib": mib, "copies": 3}), flush=True)
 
 
 def cpu_baseline(n_target: int, theta) -> dict:
@@ -70,6 +86,9 @@ def cpu_baseline(n_target: int, theta) -> dict:
 
 def main():
     args = parse()
+    if args.calibrate_copy:
+        calibrate_copy(args.calibrate_copy)
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; multi-GPU runs are not part of this build",
                           "n_gpus": args.gpus}))

@@ -45,14 +45,18 @@ void launch_gen_dense(const double *x1, const double *y1, int64_t n1, const doub
                       const double *y2, int64_t n2, gl_theta th, double *out, int64_t ld,
                       hipStream_t s);
 // Cholesky steps (FP64)
+// POTRF leaves the inverses of the b/64 diagonal 64×64 blocks of L_kk in dinv
+// (64·b doubles, column-major blocks); TRSM and the forward solve of the same
+// step read them.
 void launch_potrf(double *tiles, int b, int64_t k, int64_t n, int64_t *info, double *diag_logsum,
-                  hipStream_t s);
-void launch_trsm(double *tiles, int b, int64_t nt, int64_t k, const int64_t *info, hipStream_t s);
+                  double *dinv, hipStream_t s);
+void launch_trsm(double *tiles, int b, int64_t nt, int64_t k, const double *dinv, const int64_t *info,
+                 hipStream_t s);
 void launch_trailing(double *tiles, int b, int64_t nt, int64_t k, int64_t jbeg, int64_t jend,
-                     const int64_t *info, hipStream_t s);
+                     const int64_t *info, bool critical, hipStream_t s);
 // Solves and reductions
 void launch_fwd_diag(const double *tiles, int b, int64_t k, int64_t n, double *v, double *quad_part,
-                     const int64_t *info, hipStream_t s);
+                     const double *dinv, const int64_t *info, hipStream_t s);
 void launch_fwd_update(const double *tiles, int b, int64_t nt, int64_t k, double *v,
                        const int64_t *info, hipStream_t s);
 void launch_bwd_diag(const double *tiles, int b, int64_t k, double *v, hipStream_t s);

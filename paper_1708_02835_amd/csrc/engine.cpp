@@ -7,6 +7,7 @@
 #include <atomic>
 #include <mutex>
 #include <new>
+#include <vector>
 
 #include "common.hpp"
 #include "engine.hpp"
@@ -39,7 +40,7 @@ size_t work_bytes(int64_t n, int b, int precision)
     const int64_t npad = nt * b;
     size_t tiles = (size_t)tile_count(nt) * (size_t)b * b * sizeof(double);
     if (precision != GL_FP64) tiles += mixed_extra_bytes(nt, b);
-    const size_t vec = (size_t)(3 * npad + 4 * nt + tile_count(nt) + 64) * sizeof(double);
+    const size_t vec = (size_t)(3 * npad + 4 * nt + tile_count(nt) + 64 * b + 64) * sizeof(double);
     return tiles + vec;
 }
 
@@ -62,7 +63,7 @@ int Work::ensure(gl_context *ctx, int64_t n_, int b_, int precision_)
     const int64_t npad_ = nt_ * b_;
     size_t tneed = (size_t)tile_count(nt_) * (size_t)b_ * b_ * sizeof(double);
     if (precision_ != GL_FP64) tneed += mixed_extra_bytes(nt_, b_);
-    const size_t vneed = (size_t)(3 * npad_ + 4 * nt_ + tile_count(nt_) + 64) * sizeof(double);
+    const size_t vneed = (size_t)(3 * npad_ + 4 * nt_ + tile_count(nt_) + 64 * b_ + 64) * sizeof(double);
     if (tneed > tile_cap || vneed > vec_cap) {
         const size_t old = tile_cap + vec_cap;
         const size_t want = (tneed > tile_cap ? tneed : tile_cap) + (vneed > vec_cap ? vneed : vec_cap);
@@ -95,7 +96,8 @@ int Work::ensure(gl_context *ctx, int64_t n_, int b_, int precision_)
     logsum = p + 3 * npad;
     quad = logsum + nt;
     norm2 = quad + nt;
-    info = reinterpret_cast<int64_t *>(norm2 + tile_count(nt));
+    dinv = norm2 + tile_count(nt);
+    info = reinterpret_cast<int64_t *>(dinv + 64 * b);
     res = reinterpret_cast<DevResult *>(info + 8);
     if (precision_ != GL_FP64) {
         mixed_views(*this);
@@ -158,10 +160,10 @@ static double trailing_flops(int64_t nt, int64_t jbeg, int64_t jend, int b)
     return f;
 }
 
-static void trailing(Lanes &ln, Work &w, int64_t k, int64_t jbeg, int64_t jend, hipStream_t s)
+static void trailing(Lanes &ln, Work &w, int64_t k, int64_t jbeg, int64_t jend, hipStream_t s, bool critical)
 {
     if (ln.prof) ln.prof->bracket(s, true);
-    launch_trailing(w.tiles, w.b, w.nt, k, jbeg, jend, w.info, s);
+    launch_trailing(w.tiles, w.b, w.nt, k, jbeg, jend, w.info, critical, s);
     if (ln.prof) {
         ln.prof->bracket(s, false);
         ln.prof->flops += trailing_flops(w.nt, jbeg, jend, w.b);
@@ -175,17 +177,17 @@ int factorize(Lanes &ln, Work &w, hipStream_t s, bool solve)
     GL_HIP_TRY(hipEventRecord(ln.fork, s));
     GL_HIP_TRY(hipStreamWaitEvent(la, ln.fork, 0));
     for (int64_t k = 0; k < w.nt; ++k) {
-        launch_potrf(w.tiles, w.b, k, w.n, w.info, w.logsum, s);
-        if (solve) launch_fwd_diag(w.tiles, w.b, k, w.n, w.v, w.quad, w.info, s);
-        launch_trsm(w.tiles, w.b, w.nt, k, w.info, s);
+        launch_potrf(w.tiles, w.b, k, w.n, w.info, w.logsum, w.dinv, s);
+        if (solve) launch_fwd_diag(w.tiles, w.b, k, w.n, w.v, w.quad, w.dinv, w.info, s);
+        launch_trsm(w.tiles, w.b, w.nt, k, w.dinv, w.info, s);
         if (solve) launch_fwd_update(w.tiles, w.b, w.nt, k, w.v, w.info, s);
         if (k + 1 < w.nt) {
             GL_HIP_TRY(hipEventRecord(ln.panel, s));
             if (k > 0) GL_HIP_TRY(hipStreamWaitEvent(s, ln.bulk, 0));
-            trailing(ln, w, k, k + 1, k + 1, s);
+            trailing(ln, w, k, k + 1, k + 1, s, true);
             if (k + 2 < w.nt) {
                 GL_HIP_TRY(hipStreamWaitEvent(la, ln.panel, 0));
-                trailing(ln, w, k, k + 2, w.nt - 1, la);
+                trailing(ln, w, k, k + 2, w.nt - 1, la, false);
                 GL_HIP_TRY(hipEventRecord(ln.bulk, la));
             }
         }

@@ -25,6 +25,7 @@ struct Work {
     double *logsum = nullptr;           // per diagonal tile: 2 Σ log L_rr
     double *quad = nullptr;             // per tile: Σ w_r²
     double *norm2 = nullptr;            // per tile: ||Σ_ij||_F² (mixed precision)
+    double *dinv = nullptr;             // inverses of the 64×64 diagonal blocks of the current L_kk
     int64_t *info = nullptr;
     DevResult *res = nullptr;
     // mixed precision: views into the tail of the tile allocation

@@ -15,6 +15,7 @@
 namespace gl {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
+typedef double d2 __attribute__((ext_vector_type(2)));  // 16-byte vector loads and stores
 typedef float f4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
@@ -36,6 +37,15 @@ __device__ inline f4 mfma_f32(float a, float b, f4 c)
 __device__ inline f4 mfma_bf16(bf16x8 a, bf16x8 b, f4 c)
 {
     return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
+// Value of v in lane l (l uniform across the wave), as two 32-bit readlanes.
+__device__ inline double readlane_f64(double v, int l)
+{
+    const long long bits = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)(bits & 0xffffffffll), l);
+    const int hi = __builtin_amdgcn_readlane((int)(bits >> 32), l);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
 // Wave-wide sum (fixed butterfly order, identical on every lane).

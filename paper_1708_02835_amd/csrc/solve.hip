@@ -16,48 +16,50 @@
 
 namespace gl {
 
-// v_k <- L_kk⁻¹ v_k.  Wave 0 solves 64×64 diagonal blocks by column
-// substitution with the running right-hand side in registers; all four waves
-// then apply the block's columns to the rows below it.
+// v_k <- L_kk⁻¹ v_k by 64-row blocks J, using the inverted diagonal blocks
+// D_J⁻¹ that POTRF left in `dinv`:  t = v_J - L[J, 0:J] w[0:J],  w_J = D_J⁻¹ t.
+// Both products are split over four thread groups with fixed-order partial
+// sums.  The tile's part of wᵀw (rows < n) goes to quad_part[k].
 template <int B>
 __global__ __launch_bounds__(256) void fwd_diag_kernel(const double *__restrict__ tiles, int64_t k,
                                                        int64_t n, double *__restrict__ v,
                                                        double *__restrict__ quad_part,
+                                                       const double *__restrict__ dinv,
                                                        const int64_t *__restrict__ info)
 {
     if (info && *info != 0) return;
+    __builtin_amdgcn_s_setprio(3);  // critical path of the step schedule
     const double *L = tiles + tile_offset(k, k, B);
     double *vk = v + k * B;
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = tid >> 6;
+    const int r = tid & 63, g = tid >> 6;
     __shared__ double xs[B];
+    __shared__ double t[64];
+    __shared__ double part[4][64];
     __shared__ double red[4];
-    for (int r = tid; r < B; r += 256) xs[r] = vk[r];
+    for (int q = tid; q < B; q += 256) xs[q] = vk[q];
     __syncthreads();
-    for (int s = 0; s < B; s += 64) {
-        if (wave == 0) {
-            double z = xs[s + lane];
-            for (int c = 0; c < 64; ++c) {
-                const double lc = L[(int64_t)(s + c) * B + s + lane];
-                const double xc = __shfl(z, c, 64) / L[(int64_t)(s + c) * B + s + c];
-                if (lane == c) z = xc;
-                else if (lane > c) z -= lc * xc;
-            }
-            xs[s + lane] = z;
-        }
+    for (int J = 0; J < B; J += 64) {
+        double acc = 0.0;
+        for (int c = g; c < J; c += 4) acc += L[(int64_t)c * B + J + r] * xs[c];
+        part[g][r] = acc;
         __syncthreads();
-        for (int r = s + 64 + tid; r < B; r += 256) {
-            double acc = 0.0;
-            for (int c = 0; c < 64; ++c) acc += L[(int64_t)(s + c) * B + r] * xs[s + c];
-            xs[r] -= acc;
-        }
+        if (tid < 64) t[r] = xs[J + r] - ((part[0][r] + part[1][r]) + (part[2][r] + part[3][r]));
+        __syncthreads();
+        const double *dv = dinv + (int64_t)(J / 64) * 64 * 64;
+        acc = 0.0;
+        for (int m = g; m < 64; m += 4) acc += dv[m * 64 + r] * t[m];
+        part[g][r] = acc;
+        __syncthreads();
+        if (tid < 64) xs[J + r] = (part[0][r] + part[1][r]) + (part[2][r] + part[3][r]);
         __syncthreads();
     }
     double q = 0.0;
-    for (int r = tid; r < B; r += 256) {
-        vk[r] = xs[r];
-        if (k * B + r < n) q += xs[r] * xs[r];
+    for (int rr = tid; rr < B; rr += 256) {
+        vk[rr] = xs[rr];
+        if (k * B + rr < n) q += xs[rr] * xs[rr];
     }
     if (quad_part) {
         double w = wave_sum(q);
@@ -74,6 +76,7 @@ __global__ __launch_bounds__(256) void fwd_update_kernel(const double *__restric
                                                          const int64_t *__restrict__ info)
 {
     if (info && *info != 0) return;
+    __builtin_amdgcn_s_setprio(3);
     const int64_t i = k + 1 + blockIdx.x;
     const int r0 = blockIdx.y * 64;
     const double *L = tiles + tile_offset(i, k, B);
@@ -247,9 +250,9 @@ __global__ void tiles_to_dense_kernel(const double *__restrict__ tiles, int b, i
     }
 
 void launch_fwd_diag(const double *tiles, int b, int64_t k, int64_t n, double *v, double *quad_part,
-                     const int64_t *info, hipStream_t s)
+                     const double *dinv, const int64_t *info, hipStream_t s)
 {
-    GL_DISPATCH_B(b, fwd_diag_kernel, dim3(1), tiles, k, n, v, quad_part, info);
+    GL_DISPATCH_B(b, fwd_diag_kernel, dim3(1), tiles, k, n, v, quad_part, dinv, info);
 }
 
 void launch_fwd_update(const double *tiles, int b, int64_t nt, int64_t k, double *v,

@@ -41,9 +41,11 @@ template <int B>
 __global__ __launch_bounds__(256, 2) void trailing_f64_kernel(double *__restrict__ tiles, int64_t k,
                                                               int64_t jbeg, int64_t nt,
                                                               int64_t nblocks,
-                                                              const int64_t *__restrict__ info)
+                                                              const int64_t *__restrict__ info,
+                                                              int critical)
 {
     if (*info != 0) return;
+    if (critical) __builtin_amdgcn_s_setprio(3);
     constexpr int SB = B / GB;
     constexpr int SUB = SB * SB;
     const int64_t G = gridDim.x;  // a multiple of 8
@@ -77,10 +79,10 @@ __global__ __launch_bounds__(256, 2) void trailing_f64_kernel(double *__restrict
 #pragma unroll
         for (int b = 0; b < 4; ++b) acc[a][b] = (d4){0.0, 0.0, 0.0, 0.0};
 
-    double2 ra[4], rbv[4];
+    d2 ra[4], rbv[4];
     {
-        const double2 *pa = reinterpret_cast<const double2 *>(Ap + (int64_t)lc * B + lr);
-        const double2 *pb = reinterpret_cast<const double2 *>(Bp + (int64_t)lc * B + lr);
+        const d2 *pa = reinterpret_cast<const d2 *>(Ap + (int64_t)lc * B + lr);
+        const d2 *pb = reinterpret_cast<const d2 *>(Bp + (int64_t)lc * B + lr);
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             ra[q] = pa[q];
@@ -88,8 +90,8 @@ __global__ __launch_bounds__(256, 2) void trailing_f64_kernel(double *__restrict
         }
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            *reinterpret_cast<double2 *>(&As[0][lc][lr + 2 * q]) = ra[q];
-            *reinterpret_cast<double2 *>(&Bs[0][lc][lr + 2 * q]) = rbv[q];
+            *reinterpret_cast<d2 *>(&As[0][lc][lr + 2 * q]) = ra[q];
+            *reinterpret_cast<d2 *>(&Bs[0][lc][lr + 2 * q]) = rbv[q];
         }
     }
     __syncthreads();
@@ -99,8 +101,8 @@ __global__ __launch_bounds__(256, 2) void trailing_f64_kernel(double *__restrict
         const int cur = kc & 1;
         if (kc + 1 < NK) {
             const int64_t col = (int64_t)(kc + 1) * GK + lc;
-            const double2 *pa = reinterpret_cast<const double2 *>(Ap + col * B + lr);
-            const double2 *pb = reinterpret_cast<const double2 *>(Bp + col * B + lr);
+            const d2 *pa = reinterpret_cast<const d2 *>(Ap + col * B + lr);
+            const d2 *pb = reinterpret_cast<const d2 *>(Bp + col * B + lr);
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 ra[q] = pa[q];
@@ -115,16 +117,18 @@ __global__ __launch_bounds__(256, 2) void trailing_f64_kernel(double *__restrict
                 av[q] = As[cur][kk + (lane >> 4)][wm * 64 + q * 16 + (lane & 15)];
                 bv[q] = Bs[cur][kk + (lane >> 4)][wn * 64 + q * 16 + (lane & 15)];
             }
+            // operands swapped: the product is the transpose of the C block, so
+            // result row r of lane l is C column, lane % 16 is C row (coalesced)
 #pragma unroll
             for (int a = 0; a < 4; ++a)
 #pragma unroll
-                for (int b = 0; b < 4; ++b) acc[a][b] = mfma_f64(av[a], bv[b], acc[a][b]);
+                for (int b = 0; b < 4; ++b) acc[a][b] = mfma_f64(bv[b], av[a], acc[a][b]);
         }
         if (kc + 1 < NK) {
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                *reinterpret_cast<double2 *>(&As[cur ^ 1][lc][lr + 2 * q]) = ra[q];
-                *reinterpret_cast<double2 *>(&Bs[cur ^ 1][lc][lr + 2 * q]) = rbv[q];
+                *reinterpret_cast<d2 *>(&As[cur ^ 1][lc][lr + 2 * q]) = ra[q];
+                *reinterpret_cast<d2 *>(&Bs[cur ^ 1][lc][lr + 2 * q]) = rbv[q];
             }
         }
         __syncthreads();
@@ -134,10 +138,10 @@ __global__ __launch_bounds__(256, 2) void trailing_f64_kernel(double *__restrict
     for (int a = 0; a < 4; ++a) {
 #pragma unroll
         for (int b = 0; b < 4; ++b) {
-            const int64_t col = wn * 64 + b * 16 + mfma_col(lane);
+            const int row = wm * 64 + a * 16 + mfma_col(lane);
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int row = wm * 64 + a * 16 + mfma_row(lane, r);
+                const int64_t col = wn * 64 + b * 16 + mfma_row(lane, r);
                 C[col * B + row] -= acc[a][b][r];
             }
         }
@@ -145,7 +149,7 @@ __global__ __launch_bounds__(256, 2) void trailing_f64_kernel(double *__restrict
 }
 
 void launch_trailing(double *tiles, int b, int64_t nt, int64_t k, int64_t jbeg, int64_t jend,
-                     const int64_t *info, hipStream_t s)
+                     const int64_t *info, bool critical, hipStream_t s)
 {
     if (jbeg > jend || jbeg >= nt) return;
     // tiles in columns jbeg..jend, rows j..nt-1
@@ -156,10 +160,10 @@ void launch_trailing(double *tiles, int b, int64_t nt, int64_t k, int64_t jbeg, 
     const int64_t nblocks = ntiles * sub;
     const int64_t grid = ceil_div(nblocks, 8) * 8;
     switch (b) {
-    case 128: trailing_f64_kernel<128><<<(unsigned)grid, 256, 0, s>>>(tiles, k, jbeg, nt, nblocks, info); break;
-    case 256: trailing_f64_kernel<256><<<(unsigned)grid, 256, 0, s>>>(tiles, k, jbeg, nt, nblocks, info); break;
-    case 384: trailing_f64_kernel<384><<<(unsigned)grid, 256, 0, s>>>(tiles, k, jbeg, nt, nblocks, info); break;
-    default: trailing_f64_kernel<512><<<(unsigned)grid, 256, 0, s>>>(tiles, k, jbeg, nt, nblocks, info); break;
+    case 128: trailing_f64_kernel<128><<<(unsigned)grid, 256, 0, s>>>(tiles, k, jbeg, nt, nblocks, info, critical ? 1 : 0); break;
+    case 256: trailing_f64_kernel<256><<<(unsigned)grid, 256, 0, s>>>(tiles, k, jbeg, nt, nblocks, info, critical ? 1 : 0); break;
+    case 384: trailing_f64_kernel<384><<<(unsigned)grid, 256, 0, s>>>(tiles, k, jbeg, nt, nblocks, info, critical ? 1 : 0); break;
+    default: trailing_f64_kernel<512><<<(unsigned)grid, 256, 0, s>>>(tiles, k, jbeg, nt, nblocks, info, critical ? 1 : 0); break;
     }
 }
 

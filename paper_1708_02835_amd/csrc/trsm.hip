@@ -1,87 +1,140 @@
 // Panel triangular solve (the TRSM task of the tile algorithm, Sec. 4.2):
 // L_ik = A_ik L_kk⁻ᵀ for every tile i > k of column k.
 //
-// Workgroup (i, strip) owns 64 rows of tile (i, k), so it is the only writer
-// of those rows and solves them in place.  The strip X (64 × b) is computed in
-// 32-column blocks J:
-//   T = A[:, J] - X[:, 0:J] · L_kk[J, 0:J]ᵀ        (FP64 matrix-core product)
-//   X[:, J] = T · L_kk[J, J]⁻ᵀ                      (forward substitution per row)
-// Columns 0:J of the strip were written by this workgroup in earlier blocks.
+// Workgroup (i, strip) owns 64 rows of tile (i, k), the only writer of those
+// rows, and solves them in place in 64-column blocks J, all on the matrix
+// cores:
+//   T      = A[:, J] - X[:, 0:J] · L_kk[J, 0:J]ᵀ
+//   X[:, J] = T · D_J⁻ᵀ
+// where D_J⁻¹ is the inverse of the J-th 64×64 diagonal block of L_kk, left in
+// `dinv` by the POTRF of the same step.  The product streams 16-column chunks
+// of X and L_kk through LDS, double-buffered; X[:, 0:J] was written by this
+// workgroup in earlier blocks (visible after the block barrier).
 #include "common.hpp"
 #include "mfma.hpp"
 
 namespace gl {
 
-constexpr int TNB = 32;  // column block
-constexpr int TSH = 64;  // strip height
+constexpr int TB = 64;  // column block and strip height
+constexpr int TC = 16;  // k chunk
+constexpr int TP = TB + 16;  // LDS row pitch (bank spread of the 16-lane groups)
 
 template <int B>
 __global__ __launch_bounds__(256) void trsm_kernel(double *__restrict__ tiles, int64_t k,
+                                                   const double *__restrict__ dinv,
                                                    const int64_t *__restrict__ info)
 {
     if (*info != 0) return;
+    __builtin_amdgcn_s_setprio(3);  // critical path of the step schedule
     const int64_t i = k + 1 + blockIdx.x;
-    const int r0 = blockIdx.y * TSH;
+    const int r0 = blockIdx.y * TB;
     const double *L = tiles + tile_offset(k, k, B);
     double *X = tiles + tile_offset(i, k, B);
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = tid >> 6;
-    __shared__ double T[TSH][TNB + 1];
-    __shared__ double Ld[TNB][TNB + 1];
+    // chunk buffers during the product (Xs[b][kc][r] = X[r0 + r][k0 + kc],
+    // Ls[b][kc][j] = L[J + j][k0 + kc]); D_J⁻¹ reuses them afterwards
+    __shared__ double buf[2 * TC * TP * 2];
+    __shared__ double Tt[TB][TP];  // Tt[c][r] = T[r][c]
+    auto Xs = reinterpret_cast<double(*)[TC][TP]>(buf);
+    auto Ls = reinterpret_cast<double(*)[TC][TP]>(buf + 2 * TC * TP);
+    double *Di = buf;  // Di[c * TP + r] = (D_J⁻¹)[r][c]
 
-    for (int J = 0; J < B; J += TNB) {
-        // wave w owns rows r0 + 16w .. +15 of the strip, two 16-column halves
-        d4 acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
-        for (int kk = 0; kk < J; kk += 4) {
-            const int64_t col = kk + (lane >> 4);
-            const double a = X[col * B + r0 + wave * 16 + (lane & 15)];
-            const double b0 = L[col * B + J + (lane & 15)];
-            const double b1 = L[col * B + J + 16 + (lane & 15)];
-            acc0 = mfma_f64(a, b0, acc0);
-            acc1 = mfma_f64(a, b1, acc1);
-        }
+    const int lkc = tid >> 4, lr = (tid & 15) * 4;  // loader: column lkc, rows lr..lr+3
+
+    for (int J = 0; J < B; J += TB) {
+        const int nch = J / TC;
+        d4 acc[4];
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int row = wave * 16 + mfma_row(lane, r);
-            const int c0 = mfma_col(lane);
-            T[row][c0] = X[(int64_t)(J + c0) * B + r0 + row] - acc0[r];
-            T[row][16 + c0] = X[(int64_t)(J + 16 + c0) * B + r0 + row] - acc1[r];
-        }
-        for (int e = tid; e < TNB * TNB; e += 256) {
-            const int c = e / TNB, r = e % TNB;  // column c, row r of the diagonal block
-            Ld[r][c] = L[(int64_t)(J + c) * B + J + r];
+        for (int rb = 0; rb < 4; ++rb) acc[rb] = (d4){0.0, 0.0, 0.0, 0.0};
+        d2 rx[2], rl[2];
+        if (nch > 0) {
+            const d2 *px = reinterpret_cast<const d2 *>(X + (int64_t)lkc * B + r0 + lr);
+            const d2 *pl = reinterpret_cast<const d2 *>(L + (int64_t)lkc * B + J + lr);
+            rx[0] = px[0];
+            rx[1] = px[1];
+            rl[0] = pl[0];
+            rl[1] = pl[1];
+            *reinterpret_cast<d2 *>(&Xs[0][lkc][lr]) = rx[0];
+            *reinterpret_cast<d2 *>(&Xs[0][lkc][lr + 2]) = rx[1];
+            *reinterpret_cast<d2 *>(&Ls[0][lkc][lr]) = rl[0];
+            *reinterpret_cast<d2 *>(&Ls[0][lkc][lr + 2]) = rl[1];
         }
         __syncthreads();
-        if (tid < TSH) {
-            // row tid: x_c = (t_c - Σ_{d<c} x_d L[c][d]) / L[c][c]
-#pragma unroll
-            for (int c = 0; c < TNB; ++c) {
-                double v = T[tid][c];
-#pragma unroll
-                for (int d = 0; d < c; ++d) v -= T[tid][d] * Ld[c][d];
-                T[tid][c] = v / Ld[c][c];
+        for (int ch = 0; ch < nch; ++ch) {
+            const int cur = ch & 1;
+            if (ch + 1 < nch) {
+                const int64_t col = (int64_t)(ch + 1) * TC + lkc;
+                const d2 *px = reinterpret_cast<const d2 *>(X + col * B + r0 + lr);
+                const d2 *pl = reinterpret_cast<const d2 *>(L + col * B + J + lr);
+                rx[0] = px[0];
+                rx[1] = px[1];
+                rl[0] = pl[0];
+                rl[1] = pl[1];
             }
+            // wave w: columns w*16.. of the block; four 16-row groups of the strip
+#pragma unroll
+            for (int kk = 0; kk < TC; kk += 4) {
+                const double xl = Ls[cur][kk + (lane >> 4)][wave * 16 + (lane & 15)];
+#pragma unroll
+                for (int rb = 0; rb < 4; ++rb)
+                    acc[rb] = mfma_f64(xl, Xs[cur][kk + (lane >> 4)][rb * 16 + (lane & 15)], acc[rb]);
+            }
+            if (ch + 1 < nch) {
+                *reinterpret_cast<d2 *>(&Xs[cur ^ 1][lkc][lr]) = rx[0];
+                *reinterpret_cast<d2 *>(&Xs[cur ^ 1][lkc][lr + 2]) = rx[1];
+                *reinterpret_cast<d2 *>(&Ls[cur ^ 1][lkc][lr]) = rl[0];
+                *reinterpret_cast<d2 *>(&Ls[cur ^ 1][lkc][lr + 2]) = rl[1];
+            }
+            __syncthreads();
         }
+        // T = A[:, J] - product (result row q of lane l: block column w*16 + l/16 + 4q,
+        // lane % 16: strip row), and D_J⁻¹ into LDS
+#pragma unroll
+        for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int c = wave * 16 + mfma_row(lane, q);
+                const int r = rb * 16 + mfma_col(lane);
+                Tt[c][r] = X[(int64_t)(J + c) * B + r0 + r] - acc[rb][q];
+            }
+        const double *dv = dinv + (int64_t)(J / TB) * TB * TB;
+        for (int e = tid; e < TB * TB; e += 256) Di[(e >> 6) * TP + (e & 63)] = dv[e];
         __syncthreads();
-        for (int e = tid; e < TSH * TNB; e += 256) {
-            const int c = e / TSH, r = e % TSH;
-            X[(int64_t)(J + c) * B + r0 + r] = T[r][c];
+        // X[:, J] = T · D_J⁻ᵀ: X[r][c] = Σ_m T[r][m] D⁻¹[c][m]
+#pragma unroll
+        for (int rb = 0; rb < 4; ++rb) acc[rb] = (d4){0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int kk = 0; kk < TB; kk += 4) {
+            const int m = kk + (lane >> 4);
+            const double xd = Di[m * TP + wave * 16 + (lane & 15)];
+#pragma unroll
+            for (int rb = 0; rb < 4; ++rb) acc[rb] = mfma_f64(xd, Tt[m][rb * 16 + (lane & 15)], acc[rb]);
         }
+#pragma unroll
+        for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int c = wave * 16 + mfma_row(lane, q);
+                const int r = rb * 16 + mfma_col(lane);
+                X[(int64_t)(J + c) * B + r0 + r] = acc[rb][q];
+            }
         __syncthreads();
     }
 }
 
-void launch_trsm(double *tiles, int b, int64_t nt, int64_t k, const int64_t *info, hipStream_t s)
+void launch_trsm(double *tiles, int b, int64_t nt, int64_t k, const double *dinv, const int64_t *info,
+                 hipStream_t s)
 {
     const int64_t m = nt - k - 1;
     if (m <= 0) return;
-    dim3 grid((unsigned)m, (unsigned)(b / TSH));
+    dim3 grid((unsigned)m, (unsigned)(b / TB));
     switch (b) {
-    case 128: trsm_kernel<128><<<grid, 256, 0, s>>>(tiles, k, info); break;
-    case 256: trsm_kernel<256><<<grid, 256, 0, s>>>(tiles, k, info); break;
-    case 384: trsm_kernel<384><<<grid, 256, 0, s>>>(tiles, k, info); break;
-    default: trsm_kernel<512><<<grid, 256, 0, s>>>(tiles, k, info); break;
+    case 128: trsm_kernel<128><<<grid, 256, 0, s>>>(tiles, k, dinv, info); break;
+    case 256: trsm_kernel<256><<<grid, 256, 0, s>>>(tiles, k, dinv, info); break;
+    case 384: trsm_kernel<384><<<grid, 256, 0, s>>>(tiles, k, dinv, info); break;
+    default: trsm_kernel<512><<<grid, 256, 0, s>>>(tiles, k, dinv, info); break;
     }
 }
 

@@ -63,7 +63,7 @@ def test_footprint_formula(n, tile):
     import paper_1708_02835_amd as g
     nt = -(-n // tile)
     tiles = nt * (nt + 1) // 2 * tile * tile * 8
-    vec = (3 * nt * tile + 4 * nt + nt * (nt + 1) // 2 + 64) * 8
+    vec = (3 * nt * tile + 4 * nt + nt * (nt + 1) // 2 + 64 * tile + 64) * 8
     assert g.gl_footprint_bytes(n, tile, g.GL_FP64) == tiles + vec
 
 
