@@ -39,6 +39,9 @@ def parse():
     p.add_argument("--theta", type=float, nargs=3, default=(1.0, 0.1, 0.5))
     p.add_argument("--seed", type=int, default=3000)
     p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision legs")
+    p.add_argument("--theta-b", type=float, nargs=3, default=(1.0, 0.3, 1.0),
+                   help="second parameter vector of the mixed-precision comparison")
     p.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                    help="only run device-to-device copies of MIB mebibytes (HBM counter calibration)")
     return p.parse_args()
@@ -82,6 +85,47 @@ def cpu_baseline(n_target: int, theta) -> dict:
             "sample": (f"oracle l(theta) timed at n={n1} ({t1:.2f} s) and n={n2} ({t2:.2f} s) on one host core, "
                        f"extrapolated to n={n_target} with t = a n^2 + b n^3 (t={t_target:.3g} s)"),
             "seconds_timed": t1 + t2}
+
+
+def mixed_legs(g, ctx, xd, yd, ed, zd, theta, theta_b, args, res64, t64, log):
+    """Time-to-l(θ) of the mixed-precision modes against FP64 at the same
+    size, with the relative error of l and log|Σ| against the FP64 result,
+    for θ (Z simulated at θ) and θ_b (Z simulated at θ_b)."""
+    import torch
+    out = {}
+
+    def run(z, th, prec, steps):
+        opts = g.gl_opts_default(precision=prec, tile=args.tile)
+        r = g.loglik_eval(ctx, xd, yd, z, th, opts)  # warm-up (also builds the precision map)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            r = g.loglik_eval(ctx, xd, yd, z, th, opts)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / steps
+        stats = g.gl_precision_stats(ctx) if prec != g.GL_FP64 else None
+        return r, dt, stats
+
+    for label, th, z, steps in (("theta_a", theta, zd, args.steps), ("theta_b", theta_b, None, 1)):
+        if z is None:
+            z, info = g.synth_generate(ctx, xd, yd, ed, th, args.tile)
+            if info != 0:
+                out[label] = {"theta": list(th), "error": f"field generation failed, info={info}"}
+                continue
+            r64, t64b, _ = run(z, th, g.GL_FP64, 1)
+        else:
+            r64, t64b = res64, t64
+        leg = {"theta": list(th), "fp64_ms": t64b * 1e3, "loglik_fp64": r64["loglik"]}
+        for name, prec in (("bf16", g.GL_MIXED_BF16), ("fp32", g.GL_MIXED_FP32)):
+            r, dt, stats = run(z, th, prec, steps if name == "bf16" else 1)
+            leg[name] = {"ms": dt * 1e3, "speedup_vs_fp64": t64b / dt,
+                         "rel_err_loglik": abs(r["loglik"] - r64["loglik"]) / abs(r64["loglik"]),
+                         "rel_err_logdet": abs(r["logdet"] - r64["logdet"]) / abs(r64["logdet"]),
+                         "status": r["status"],
+                         "work_frac": {k: round(v["work_frac"], 4) for k, v in stats.items()}}
+            log(f"mixed {label} {name}: {dt:.3f} s, x{t64b / dt:.2f}, rel err {leg[name]['rel_err_loglik']:.2e}")
+        out[label] = leg
+    return out
 
 
 def main():
@@ -168,6 +212,8 @@ def main():
                      "launches": prof["launches"], "avg_launch_ms": avg_ms,
                      "flops_per_launch": avg_flops},
     }
+    if not args.no_mixed:
+        out["mixed"] = mixed_legs(g, ctx, xd, yd, ed, zd, theta, tuple(args.theta_b), args, res, step_s, log)
     ctx.close()
     if not args.no_cpu_baseline:
         log("timing the oracle on the host")

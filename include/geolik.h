@@ -56,16 +56,30 @@ typedef enum {
     GL_MIXED_BF16 = 2   /* far off-band updates in bfloat16 (fp32 accumulate), others as MIXED_FP32 */
 } gl_precision;
 
-/* Options of one likelihood evaluation.  Fill with gl_opts_default(). */
+/* Options of one likelihood evaluation.  Fill with gl_opts_default().
+ *
+ * Mixed precision (not in the paper): every tile stays stored in binary64 and
+ * the diagonal tiles, POTRF, TRSM, the solve and log|Σ| stay binary64; the
+ * trailing products of off-band tiles (i, j) run at a precision chosen from
+ * the normalised tile norm ν_ij = ||Σ_ij||_F / sqrt(||Σ_ii||_F ||Σ_jj||_F):
+ *   GL_MIXED_FP32: FP32 products, or binary64 when ν_ij > tol_hi
+ *                  (tol_hi < 0: +infinity, i.e. every off-band tile FP32);
+ *   GL_MIXED_BF16: bfloat16 products with FP32 accumulation, operands split
+ *                  in three parts (about FP32 accuracy) when ν_ij > tol_hi,
+ *                  two parts when tol_lo < ν_ij <= tol_hi, one part below
+ *                  (tol_hi < 0: 1e-2, tol_lo < 0: 1e-4).
+ * Tiles with i - j < band stay binary64. */
 typedef struct {
     int32_t precision;   /* gl_precision */
     int32_t tile;        /* tile size b: 0 = automatic, else 128, 256, 384 or 512 */
     int32_t keep_factor; /* 1: return the Cholesky factor in gl_result.factor for kriging */
     int32_t band;        /* mixed modes: tiles with i - j < band stay binary64 (>= 1) */
-    double tol32;        /* mixed modes: off-band tile stays binary64 when its Frobenius norm
-                            exceeds tol32 * ||Σ||_F / NT */
-    double tolbf16;      /* GL_MIXED_BF16: tile uses binary32 (not bfloat16) when its norm
-                            exceeds tolbf16 * ||Σ||_F / NT */
+    int32_t reorder;     /* -1: automatic (Morton order for the mixed modes, input order for
+                            GL_FP64); 0: input order; 1: Morton order.  l(θ) does not depend
+                            on the order; kept factors are in the order used. */
+    int32_t reserved;    /* 0 */
+    double tol_hi;       /* mixed modes: see above (negative: mode default) */
+    double tol_lo;       /* GL_MIXED_BF16: see above (negative: mode default) */
 } gl_opts;
 
 /* Result of one likelihood evaluation, host memory. */
@@ -91,7 +105,7 @@ int gl_context_create(int device, size_t hbm_budget_bytes, gl_context **out);
 void gl_context_destroy(gl_context *ctx);
 
 /* Fill *opts with defaults: FP64, automatic tile, no factor kept, band 2,
- * tol32 = 1e-2, tolbf16 = 1e-4. */
+ * automatic order, mode-default thresholds (-1). */
 void gl_opts_default(gl_opts *opts);
 
 /* Static English description of a gl_status value. */
@@ -142,7 +156,8 @@ int krige_predict(gl_context *ctx, gl_factor *factor, const double *xnew, const 
 int gl_factor_release(gl_context *ctx, gl_factor *factor);
 
 /* Copy the lower-triangular factor L of `factor` into a dense column-major
- * n×n array (device, ld >= n) with a zero strict upper triangle. */
+ * n×n array (device, ld >= n) with a zero strict upper triangle, in the
+ * order the factorisation used (input order unless reordering was on). */
 int gl_factor_to_dense(gl_context *ctx, gl_factor *factor, double *out, int64_t ld, void *stream);
 
 /* Order n and tile size of a factor (either output may be NULL). */
@@ -171,10 +186,13 @@ int gl_dataset_release(gl_context *ctx, uint64_t ds);
 
 /* Queue configuration.  Fill with lq_config_default(). */
 typedef struct {
-    int32_t max_inflight;    /* requests resident on the device at once (>= 1) */
-    int32_t streams;         /* device streams the scheduler spreads work over (1..8) */
-    int32_t batch_small;     /* 1: fuse the steps of small requests into shared launches */
-    int32_t small_n;         /* requests with n <= small_n are eligible for fused launches */
+    int32_t max_inflight;    /* requests resident on the device at once (1..64) */
+    int32_t streams;         /* requests run one at a time per stream outside the fused
+                                launches; this many such streams (1..8) */
+    int32_t batch_small;     /* 1: FP64 requests with n <= small_n (tile 0 or 256, no
+                                reordering) advance together through fused launches,
+                                one factorisation step per launch, tile 256 */
+    int32_t small_n;         /* size limit of the fused path */
     size_t hbm_budget_bytes; /* admission budget for resident work (0 = the context's) */
 } lq_config;
 
@@ -208,7 +226,20 @@ int lq_stats(lq_queue *q, uint64_t *completed, size_t *peak_bytes, int32_t *peak
  * drained, then the thread exits and the queue is freed. */
 int lq_destroy(lq_queue *q);
 
+/* Morton (Z-order) permutation of n locations: perm[i] (device, n int64) is
+ * the input index of position i.  Coordinates are quantised to 16 bits over
+ * their bounding box; ties are broken by the input index, so the permutation
+ * is unique.  This is the order the mixed modes factor in. */
+int gl_morton_order(gl_context *ctx, const double *x, const double *y, int64_t n, int64_t *perm,
+                    void *stream);
+
 /* --------------------------------------------------------- diagnostics ---- */
+
+/* Precision map of the last mixed-precision loglik_eval on this context:
+ * tiles per class and work per class (Σ over tiles of the trailing updates
+ * they receive), classes 0 FP64, 1 FP32, 2 BF16x6, 3 BF16x3, 4 BF16.  Either
+ * pointer may be NULL; each receives 5 values. */
+int gl_precision_stats(gl_context *ctx, int64_t *tiles_h, double *work_h);
 
 /* Runs a built-in device self-check `which` and writes up to `cap` doubles of
  * output to out_h: 0 = the lane layout of the FP64 16x16x4 matrix-core

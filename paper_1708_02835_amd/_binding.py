@@ -39,7 +39,8 @@ class gl_theta(ctypes.Structure):
 
 class gl_opts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("tile", ctypes.c_int32), ("keep_factor", ctypes.c_int32),
-                ("band", ctypes.c_int32), ("tol32", ctypes.c_double), ("tolbf16", ctypes.c_double)]
+                ("band", ctypes.c_int32), ("reorder", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("tol_hi", ctypes.c_double), ("tol_lo", ctypes.c_double)]
 
 
 class gl_result(ctypes.Structure):
@@ -90,6 +91,8 @@ _SIGNATURES = {
     "lq_destroy": (_I32, [_P]),
     "gl_selftest": (_I32, [_P, _I32, ctypes.POINTER(_D), _I64]),
     "gl_profile_enable": (_I32, [_P, _I32]),
+    "gl_morton_order": (_I32, [_P, _P, _P, _I64, _P, _P]),
+    "gl_precision_stats": (_I32, [_P, ctypes.POINTER(_I64), ctypes.POINTER(_D)]),
     "gl_profile_read": (_I32, [_P, ctypes.POINTER(_D), ctypes.POINTER(_D), ctypes.POINTER(_I64)]),
 }
 
@@ -287,24 +290,27 @@ def lq_submit(q: int, ds: int, theta, opts: gl_opts | None = None) -> int:
 
 
 def lq_poll(q: int, ticket: int):
-    """None while pending, else the result dict."""
+    """None while pending, else the result dict; its "status" is the request's
+    (GL_OK, GL_NOT_SPD, GL_ENOMEM, GL_ECANCELED, GL_EHIP).  An unknown ticket
+    raises."""
     res = gl_result()
     st = lib().lq_poll(q, int(ticket), ctypes.byref(res))
     if st == GL_EBUSY:
         return None
-    _check(st if st != GL_ECANCELED else GL_OK, "lq_poll")
+    if st == GL_EINVAL:
+        _check(st, "lq_poll")
     d = res.as_dict()
     d["status"] = st
     return d
 
 
 def lq_wait(q: int, ticket: int, timeout_us: int = -1):
-    """Result dict, or None on timeout."""
+    """Result dict (status as for lq_poll), or None on timeout."""
     res = gl_result()
     st = lib().lq_wait(q, int(ticket), ctypes.byref(res), int(timeout_us))
     if st == GL_ETIMEDOUT:
         return None
-    if st < 0 and st != GL_ECANCELED:
+    if st == GL_EINVAL:
         raise GeolikError(st, "lq_wait")
     d = res.as_dict()
     d["status"] = st
@@ -341,3 +347,25 @@ def gl_profile_read(ctx: Context) -> dict:
     ms, fl, n = _D(), _D(), _I64()
     _check(lib().gl_profile_read(ctx.handle, ctypes.byref(ms), ctypes.byref(fl), ctypes.byref(n)), "gl_profile_read")
     return {"ms": ms.value, "flops": fl.value, "launches": int(n.value)}
+
+
+def gl_morton_order(ctx: Context, x, y, stream=None):
+    """Morton permutation of the locations (int64 CUDA tensor, input index per position)."""
+    import torch
+    n = x.numel()
+    perm = torch.empty(n, dtype=torch.int64, device=x.device)
+    _check(lib().gl_morton_order(ctx.handle, _ptr(x), _ptr(y), n, perm.data_ptr(), _stream(stream)),
+           "gl_morton_order")
+    return perm
+
+
+PRECISION_CLASSES = ("fp64", "fp32", "bf16x6", "bf16x3", "bf16")
+
+
+def gl_precision_stats(ctx: Context) -> dict:
+    """Tiles and trailing-update work per precision class of the last mixed evaluation."""
+    tiles = (_I64 * 5)()
+    work = (_D * 5)()
+    _check(lib().gl_precision_stats(ctx.handle, tiles, work), "gl_precision_stats")
+    tot = sum(work) or 1.0
+    return {c: {"tiles": int(tiles[i]), "work_frac": work[i] / tot} for i, c in enumerate(PRECISION_CLASSES)}

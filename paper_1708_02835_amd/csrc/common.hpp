@@ -25,7 +25,7 @@ __host__ __device__ inline int64_t tile_offset(int64_t i, int64_t j, int b)
     return tile_index(i, j) * (int64_t)b * b;
 }
 inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
-inline int64_t tile_count(int64_t nt) { return nt * (nt + 1) / 2; }
+__host__ __device__ inline int64_t tile_count(int64_t nt) { return nt * (nt + 1) / 2; }
 
 // Per-evaluation scalars reduced on the device.
 struct DevResult {

@@ -34,60 +34,67 @@ bool valid_theta(const gl_theta &t)
            isfinite(t.theta1) && isfinite(t.theta2);
 }
 
-size_t work_bytes(int64_t n, int b, int precision)
+// Sizes of the three device allocations of a workspace.
+static void work_sizes(int64_t n, int b, int precision, size_t &tiles, size_t &vec, size_t &mix)
 {
     const int64_t nt = ceil_div(n, b);
     const int64_t npad = nt * b;
-    size_t tiles = (size_t)tile_count(nt) * (size_t)b * b * sizeof(double);
-    if (precision != GL_FP64) tiles += mixed_extra_bytes(nt, b);
-    const size_t vec = (size_t)(3 * npad + 4 * nt + tile_count(nt) + 64 * b + 64) * sizeof(double);
-    return tiles + vec;
+    tiles = (size_t)tile_count(nt) * (size_t)b * b * sizeof(double);
+    // x, y, v | logsum, quad | norm2 | dinv | info + result | Morton keys
+    vec = (size_t)(3 * npad + 2 * nt + tile_count(nt) + 64 * b + 16 + npow2_of(n) + 4) * sizeof(double);
+    mix = mixed_extra_bytes(nt, b, precision);
+}
+
+size_t work_bytes(int64_t n, int b, int precision)
+{
+    size_t t, v, m;
+    work_sizes(n, b, precision, t, v, m);
+    return t + v + m;
 }
 
 void Work::release()
 {
     if (tiles) hipFree(tiles);
     if (vecs) hipFree(vecs);
+    if (mix) hipFree(mix);
     tiles = nullptr;
-    lo32 = nullptr;
-    pmap = nullptr;
     vecs = nullptr;
-    tile_cap = 0;
-    vec_cap = 0;
+    mix = nullptr;
+    tile_cap = vec_cap = mix_cap = 0;
+    mv = MixedViews{};
 }
 
-// Size the workspace for (n, b); reuses the allocation when it is big enough.
+static int grow(void *&p, size_t &cap, size_t need)
+{
+    if (need <= cap) return GL_OK;
+    if (p) hipFree(p);
+    p = nullptr;
+    cap = 0;
+    GL_HIP_TRY(hipMalloc(&p, need));
+    cap = need;
+    return GL_OK;
+}
+
+// Size the workspace for (n, b); reuses the allocations when they are big enough.
 int Work::ensure(gl_context *ctx, int64_t n_, int b_, int precision_)
 {
-    const int64_t nt_ = ceil_div(n_, b_);
-    const int64_t npad_ = nt_ * b_;
-    size_t tneed = (size_t)tile_count(nt_) * (size_t)b_ * b_ * sizeof(double);
-    if (precision_ != GL_FP64) tneed += mixed_extra_bytes(nt_, b_);
-    const size_t vneed = (size_t)(3 * npad_ + 4 * nt_ + tile_count(nt_) + 64 * b_ + 64) * sizeof(double);
-    if (tneed > tile_cap || vneed > vec_cap) {
-        const size_t old = tile_cap + vec_cap;
-        const size_t want = (tneed > tile_cap ? tneed : tile_cap) + (vneed > vec_cap ? vneed : vec_cap);
-        if (ctx->used.load() - old + want > ctx->budget) return GL_ENOMEM;
-        if (tneed > tile_cap) {
-            if (tiles) hipFree(tiles);
-            tiles = nullptr;
-            tile_cap = 0;
-            GL_HIP_TRY(hipMalloc(reinterpret_cast<void **>(&tiles), tneed));
-            tile_cap = tneed;
-        }
-        if (vneed > vec_cap) {
-            if (vecs) hipFree(vecs);
-            vecs = nullptr;
-            vec_cap = 0;
-            GL_HIP_TRY(hipMalloc(&vecs, vneed));
-            vec_cap = vneed;
-        }
-        ctx->used += (tile_cap + vec_cap) - old;
-    }
+    size_t tneed, vneed, mneed;
+    work_sizes(n_, b_, precision_, tneed, vneed, mneed);
+    const size_t old = bytes();
+    const size_t want = (tneed > tile_cap ? tneed : tile_cap) + (vneed > vec_cap ? vneed : vec_cap) +
+                        (mneed > mix_cap ? mneed : mix_cap);
+    if (want > old && ctx->used.load() - old + want > ctx->budget) return GL_ENOMEM;
+    void *tp = tiles;
+    int rc = grow(tp, tile_cap, tneed);
+    tiles = static_cast<double *>(tp);
+    if (rc == GL_OK) rc = grow(vecs, vec_cap, vneed);
+    if (rc == GL_OK && mneed) rc = grow(mix, mix_cap, mneed);
+    ctx->used += bytes() - old;
+    if (rc != GL_OK) return rc;
     n = n_;
     b = b_;
-    nt = nt_;
-    npad = npad_;
+    nt = ceil_div(n_, b_);
+    npad = nt * b_;
     precision = precision_;
     double *p = static_cast<double *>(vecs);
     x = p;
@@ -99,21 +106,11 @@ int Work::ensure(gl_context *ctx, int64_t n_, int b_, int precision_)
     dinv = norm2 + tile_count(nt);
     info = reinterpret_cast<int64_t *>(dinv + 64 * b);
     res = reinterpret_cast<DevResult *>(info + 8);
-    if (precision_ != GL_FP64) {
-        mixed_views(*this);
-    } else {
-        lo32 = nullptr;
-        pmap = nullptr;
-    }
+    keys = reinterpret_cast<uint64_t *>(info + 16);
+    mixed_views(*this);
     return GL_OK;
 }
 
-// Right-looking tiled Cholesky of the generated tiles, with the forward
-// solve of v folded into the same step loop.  Step k on the caller's stream
-// s: POTRF(k), the diagonal solve of v_k, TRSM of column k, v_i -= L_ik v_k,
-// then (after the previous bulk update) the update of column k+1 only.  The
-// bulk update of columns k+2.. runs on the lookahead stream, so POTRF/TRSM of
-// step k+1 overlap with it.
 int Lanes::create()
 {
     GL_HIP_TRY(hipStreamCreateWithFlags(&la, hipStreamNonBlocking));
@@ -227,8 +224,10 @@ void gl_opts_default(gl_opts *o)
     o->tile = 0;
     o->keep_factor = 0;
     o->band = 2;
-    o->tol32 = 1e-2;
-    o->tolbf16 = 1e-4;
+    o->reorder = -1;
+    o->reserved = 0;
+    o->tol_hi = -1.0;
+    o->tol_lo = -1.0;
 }
 
 size_t gl_footprint_bytes(int64_t n, int32_t tile, int32_t precision)
@@ -301,7 +300,8 @@ namespace gl {
 // Likelihood evaluation on a prepared workspace whose x, y, v hold the padded
 // inputs.  Leaves the factor and w = L⁻¹ Z in the workspace and enqueues the
 // copy of the scalar results to out_h (pinned host memory).
-int eval_launch(Lanes &ln, Work &w, gl_theta th, const gl_opts &o, hipStream_t s, DevResult *out_h)
+int eval_launch(Lanes &ln, Work &w, gl_theta th, const gl_opts &o, hipStream_t s, DevResult *out_h,
+                MixedPlan *plan_out)
 {
     launch_fill(reinterpret_cast<double *>(w.info), 1, 0.0, s);
     int rc;
@@ -309,7 +309,7 @@ int eval_launch(Lanes &ln, Work &w, gl_theta th, const gl_opts &o, hipStream_t s
         launch_gen_tiles(w.tiles, w.x, w.y, w.n, w.b, w.nt, th, nullptr, s);
         rc = factorize(ln, w, s, true);
     } else {
-        rc = mixed_factorize(ln, w, th, o, s);
+        rc = mixed_factorize(ln, w, th, o, s, plan_out);
     }
     if (rc != GL_OK) return rc;
     launch_final_reduce(w.logsum, w.quad, w.nt, w.n, w.info, w.res, s);
@@ -322,8 +322,37 @@ bool valid_opts(const gl_opts &o)
 {
     if (o.precision < GL_FP64 || o.precision > GL_MIXED_BF16) return false;
     if (o.tile != 0 && o.tile != 128 && o.tile != 256 && o.tile != 384 && o.tile != 512) return false;
-    if (o.precision != GL_FP64 && (o.band < 1 || !(o.tol32 >= 0.0) || !(o.tolbf16 >= 0.0))) return false;
+    if (o.reorder < -1 || o.reorder > 1) return false;
+    if (o.precision != GL_FP64 && o.band < 1) return false;
+    if (isnan(o.tol_hi) || isnan(o.tol_lo)) return false;
     return true;
+}
+
+void stage_inputs(Work &w, const double *x, const double *y, const double *z, int reorder, hipStream_t s)
+{
+    if (reorder) {
+        launch_morton_order(x, y, z, w.n, w.npad, w.keys, w.x, w.y, w.v, nullptr, s);
+    } else {
+        launch_copy_pad(x, w.n, w.x, w.npad, 0.0, s);
+        launch_copy_pad(y, w.n, w.y, w.npad, 0.0, s);
+        launch_copy_pad(z, w.n, w.v, w.npad, 0.0, s);
+    }
+}
+
+// Mode defaults for negative thresholds: FP32 mode keeps every off-band tile
+// in FP32; BF16 mode uses the three-part split above 1e-2, two parts above
+// 1e-4 and one part below.
+gl_opts resolved_opts(const gl_opts &in)
+{
+    gl_opts o = in;
+    if (o.precision == GL_MIXED_FP32) {
+        if (o.tol_hi < 0) o.tol_hi = INFINITY;
+    } else if (o.precision == GL_MIXED_BF16) {
+        if (o.tol_hi < 0) o.tol_hi = 1e-2;
+        if (o.tol_lo < 0) o.tol_lo = 1e-4;
+    }
+    if (o.reorder < 0) o.reorder = (o.precision == GL_FP64) ? 0 : 1;
+    return o;
 }
 
 static void fill_result(gl_result *res, const DevResult &d, int b)
@@ -353,6 +382,7 @@ int loglik_eval(gl_context *ctx, const double *x, const double *y, const double 
         res->status = GL_EINVAL;
         return GL_EINVAL;
     }
+    o = resolved_opts(o);
     GL_HIP_TRY(hipSetDevice(ctx->device));
     hipStream_t s = static_cast<hipStream_t>(stream);
     const int b = pick_tile(n, o.tile);
@@ -367,15 +397,13 @@ int loglik_eval(gl_context *ctx, const double *x, const double *y, const double 
     }
     int rc = w->ensure(ctx, n, b, o.precision);
     if (rc == GL_OK) {
-        launch_copy_pad(x, n, w->x, w->npad, 0.0, s);
-        launch_copy_pad(y, n, w->y, w->npad, 0.0, s);
-        launch_copy_pad(z, n, w->v, w->npad, 0.0, s);
-        rc = eval_launch(ctx->lanes, *w, th, o, s, ctx->res_h);
+        stage_inputs(*w, x, y, z, o.reorder, s);
+        rc = eval_launch(ctx->lanes, *w, th, o, s, ctx->res_h, &ctx->last_plan);
         if (rc == GL_OK && hipStreamSynchronize(s) != hipSuccess) rc = GL_EHIP;
     }
     if (rc != GL_OK) {
         if (f) {
-            ctx->used -= f->w.tile_cap + f->w.vec_cap;
+            ctx->used -= f->w.bytes();
             f->w.release();
             delete f;
         }
@@ -389,7 +417,7 @@ int loglik_eval(gl_context *ctx, const double *x, const double *y, const double 
             ctx->factors.push_back(f);
             res->factor = f;
         } else {
-            ctx->used -= f->w.tile_cap + f->w.vec_cap;
+            ctx->used -= f->w.bytes();
             f->w.release();
             delete f;
         }
@@ -413,7 +441,7 @@ int gl_factor_release(gl_context *ctx, gl_factor *f)
     }
     hipSetDevice(ctx->device);
     hipDeviceSynchronize();
-    ctx->used -= f->w.tile_cap + f->w.vec_cap;
+    ctx->used -= f->w.bytes();
     f->w.release();
     delete f;
     return GL_OK;
@@ -430,7 +458,6 @@ int gl_factor_shape(const gl_factor *f, int64_t *n, int32_t *tile)
 int gl_factor_to_dense(gl_context *ctx, gl_factor *f, double *out, int64_t ld, void *stream)
 {
     if (!ctx || !f || !out || ld < f->w.n) return GL_EINVAL;
-    if (f->w.precision != GL_FP64) return GL_EINVAL;
     GL_HIP_TRY(hipSetDevice(ctx->device));
     launch_tiles_to_dense(f->w.tiles, f->w.b, f->w.n, out, ld, static_cast<hipStream_t>(stream));
     GL_HIP_TRY(hipGetLastError());
@@ -452,13 +479,9 @@ int krige_predict(gl_context *ctx, gl_factor *f, const double *xnew, const doubl
     double *part = scratch + w.npad;
     // X = L⁻ᵀ w: backward substitution over tile rows, last to first
     GL_HIP_TRY(hipMemcpyAsync(xv, w.v, (size_t)w.npad * sizeof(double), hipMemcpyDeviceToDevice, s));
-    if (w.precision == GL_FP64) {
-        for (int64_t k = w.nt - 1; k >= 0; --k) {
-            launch_bwd_diag(w.tiles, w.b, k, xv, s);
-            launch_bwd_update(w.tiles, w.b, k, xv, s);
-        }
-    } else {
-        mixed_backward(w, xv, s);
+    for (int64_t k = w.nt - 1; k >= 0; --k) {
+        launch_bwd_diag(w.tiles, w.b, k, xv, s);
+        launch_bwd_update(w.tiles, w.b, k, xv, s);
     }
     launch_krige(w.x, w.y, w.n, xv, f->theta, xnew, ynew, m, part, nchunk, s);
     launch_krige_reduce(part, m, nchunk, znew, s);
@@ -521,6 +544,29 @@ int gl_profile_read(gl_context *ctx, double *ms_h, double *flops_h, int64_t *lau
     p.pending.clear();
     p.flops = 0.0;
     p.launches = 0;
+    return GL_OK;
+}
+
+int gl_morton_order(gl_context *ctx, const double *x, const double *y, int64_t n, int64_t *perm, void *stream)
+{
+    if (!ctx || !x || !y || !perm || n < 1 || n > 0xffffffffll) return GL_EINVAL;
+    GL_HIP_TRY(hipSetDevice(ctx->device));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    uint64_t *keys = nullptr;
+    GL_HIP_TRY(hipMallocAsync(reinterpret_cast<void **>(&keys), (size_t)(npow2_of(n) + 4) * sizeof(uint64_t), s));
+    launch_morton_order(x, y, nullptr, n, n, keys, nullptr, nullptr, nullptr, perm, s);
+    GL_HIP_TRY(hipGetLastError());
+    GL_HIP_TRY(hipFreeAsync(keys, s));
+    return GL_OK;
+}
+
+int gl_precision_stats(gl_context *ctx, int64_t *tiles_h, double *work_h)
+{
+    if (!ctx) return GL_EINVAL;
+    for (int c = 0; c < 5; ++c) {
+        if (tiles_h) tiles_h[c] = ctx->last_plan.tiles[c];
+        if (work_h) work_h[c] = ctx->last_plan.work[c];
+    }
     return GL_OK;
 }
 

@@ -9,6 +9,25 @@
 
 namespace gl {
 
+// Views into the mixed-precision side buffer of a workspace.
+struct MixedViews {
+    float *p32[2] = {nullptr, nullptr};          // FP32 panel copies, by parity of k
+    uint16_t *planes[2] = {nullptr, nullptr};    // bfloat16 parts (3 planes each), by parity of k
+    int64_t plane_stride = 0;                    // elements between the parts of one parity
+    int np = 0;                                  // parts written per panel element
+    int2 *lists = nullptr;                       // per-class tile lists (device)
+    uint8_t *map = nullptr;                      // per-tile precision class (device)
+};
+
+// Host-side plan of one mixed evaluation: per class, the offset of its list
+// and, per tile column j, the list position where column j starts.
+struct MixedPlan {
+    int64_t base[5] = {0, 0, 0, 0, 0};
+    int64_t tiles[5] = {0, 0, 0, 0, 0};
+    double work[5] = {0, 0, 0, 0, 0};  // Σ over tiles of the number of trailing updates they receive
+    std::vector<std::vector<int64_t>> start;
+};
+
 // Device buffers of one likelihood evaluation (or of one kept factor).
 struct Work {
     // geometry
@@ -18,7 +37,8 @@ struct Work {
     // allocations
     double *tiles = nullptr;  // packed lower tiles, binary64
     void *vecs = nullptr;
-    size_t tile_cap = 0, vec_cap = 0;
+    void *mix = nullptr;  // mixed-precision side buffer
+    size_t tile_cap = 0, vec_cap = 0, mix_cap = 0;
     // views into vecs
     double *x = nullptr, *y = nullptr;  // padded locations
     double *v = nullptr;                // Z on entry, w = L⁻¹ Z after the evaluation
@@ -28,10 +48,10 @@ struct Work {
     double *dinv = nullptr;             // inverses of the 64×64 diagonal blocks of the current L_kk
     int64_t *info = nullptr;
     DevResult *res = nullptr;
-    // mixed precision: views into the tail of the tile allocation
-    float *lo32 = nullptr;              // fp32 copies of off-band tiles
-    uint8_t *pmap = nullptr;            // per tile precision class
+    uint64_t *keys = nullptr;           // Morton sort keys (+ bounding box)
+    MixedViews mv;
     int ensure(gl_context *ctx, int64_t n, int b, int precision);
+    size_t bytes() const { return tile_cap + vec_cap + mix_cap; }
     void release();
 };
 
@@ -59,14 +79,25 @@ size_t work_bytes(int64_t n, int b, int precision);
 int factorize(Lanes &ln, Work &w, hipStream_t s, bool solve);
 // Enqueue a whole evaluation on s (inputs already in w.x, w.y, w.v) and the
 // copy of its scalar results to out_h; does not wait.
-int eval_launch(Lanes &ln, Work &w, gl_theta th, const gl_opts &o, hipStream_t s, DevResult *out_h);
+int eval_launch(Lanes &ln, Work &w, gl_theta th, const gl_opts &o, hipStream_t s, DevResult *out_h,
+                MixedPlan *plan_out = nullptr);
+// Copy n inputs into the padded workspace vectors, in Morton order when
+// `reorder` is set.
+void stage_inputs(Work &w, const double *x, const double *y, const double *z, int reorder, hipStream_t s);
+gl_opts resolved_opts(const gl_opts &in);
 bool valid_opts(const gl_opts &o);
 
 // mixed precision (mixed.hip)
-size_t mixed_extra_bytes(int64_t nt, int b);
+size_t mixed_extra_bytes(int64_t nt, int b, int precision);
 void mixed_views(Work &w);
-int mixed_factorize(Lanes &ln, Work &w, gl_theta th, const gl_opts &o, hipStream_t s);
-void mixed_backward(Work &w, double *v, hipStream_t s);
+int mixed_factorize(Lanes &ln, Work &w, gl_theta th, const gl_opts &o, hipStream_t s, MixedPlan *plan_out);
+void launch_trailing_list(double *tiles, int b, int64_t k, const int2 *list, int64_t count,
+                          const int64_t *info, bool critical, hipStream_t s);
+// Morton reordering (reorder.hip); keys holds npow2(n) + 4 words
+int64_t npow2_of(int64_t n);
+void launch_morton_order(const double *x, const double *y, const double *z, int64_t n, int64_t npad,
+                         uint64_t *keys, double *xo, double *yo, double *zo, int64_t *perm,
+                         hipStream_t s);
 
 // serving (serve.cpp)
 struct ServeState;
@@ -87,6 +118,7 @@ struct gl_context {
     gl::Work ws;  // reused by evaluations that do not keep their factor
     gl::Lanes lanes;  // step-schedule side stream of the direct calls
     gl::Prof prof;
+    gl::MixedPlan last_plan;  // precision map summary of the last mixed evaluation
     gl::DevResult *res_h = nullptr;  // pinned host copy of the last result
     std::mutex mu;                   // guards factors and datasets
     std::vector<gl_factor *> factors;

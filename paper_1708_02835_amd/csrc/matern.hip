@@ -1,6 +1,7 @@
 // Σ(θ) generation kernels (Alg. 1 steps 3-4, Alg. 2 step 2, Alg. 3 steps 3-6):
 // the distance matrix is never stored; each element is evaluated from the two
 // locations and written once.
+#include "batch.hpp"
 #include "common.hpp"
 #include "matern_device.hpp"
 #include "mfma.hpp"
@@ -26,12 +27,10 @@ __device__ inline void tile_from_index(int64_t t, int64_t &i, int64_t &j)
 // NULL, the tile's squared Frobenius norm is written to norm2[t] by a
 // fixed-order block reduction.
 template <int B>
-__global__ __launch_bounds__(256) void gen_tiles_kernel(double *__restrict__ tiles,
-                                                        const double *__restrict__ x,
-                                                        const double *__restrict__ y, int64_t n,
-                                                        gl_theta th, double *__restrict__ norm2)
+__device__ __forceinline__ void gen_tiles_body(double *__restrict__ tiles, const double *__restrict__ x,
+                                               const double *__restrict__ y, int64_t n, gl_theta th,
+                                               double *__restrict__ norm2, int64_t t)
 {
-    const int64_t t = blockIdx.x;
     int64_t ti, tj;
     tile_from_index(t, ti, tj);
     const MaternSetup ms = matern_setup(th.theta1, th.theta2, th.theta3);
@@ -73,6 +72,15 @@ __global__ __launch_bounds__(256) void gen_tiles_kernel(double *__restrict__ til
     }
 }
 
+template <int B>
+__global__ __launch_bounds__(256) void gen_tiles_kernel(double *__restrict__ tiles,
+                                                        const double *__restrict__ x,
+                                                        const double *__restrict__ y, int64_t n,
+                                                        gl_theta th, double *__restrict__ norm2)
+{
+    gen_tiles_body<B>(tiles, x, y, n, th, norm2, blockIdx.x);
+}
+
 void launch_gen_tiles(double *tiles, const double *x, const double *y, int64_t n, int b, int64_t nt,
                       gl_theta th, double *norm2, hipStream_t s)
 {
@@ -83,6 +91,22 @@ void launch_gen_tiles(double *tiles, const double *x, const double *y, int64_t n
     case 384: gen_tiles_kernel<384><<<grid, 256, 0, s>>>(tiles, x, y, n, th, norm2); break;
     default: gen_tiles_kernel<512><<<grid, 256, 0, s>>>(tiles, x, y, n, th, norm2); break;
     }
+}
+
+template <int B>
+__global__ __launch_bounds__(256) void gen_batched_kernel(const BatchReq *__restrict__ d, int count)
+{
+    const int64_t g = blockIdx.x;
+    const int r = GL_BATCH_FIND(d, count, g, o_gen);
+    const BatchReq &q = d[r];
+    gen_tiles_body<B>(q.tiles, q.x, q.y, q.n, q.th, nullptr, g - q.o_gen);
+}
+
+void launch_gen_batched(int b, const BatchReq *d, int count, int64_t tiles, hipStream_t s)
+{
+    if (tiles <= 0) return;
+    if (b == 128) gen_batched_kernel<128><<<(unsigned)tiles, 256, 0, s>>>(d, count);
+    else gen_batched_kernel<256><<<(unsigned)tiles, 256, 0, s>>>(d, count);
 }
 
 // Dense column-major n1×n2 covariance between two point sets: out[i + j*ld].

@@ -1,15 +1,521 @@
-// Mixed-precision factorisation (placeholder until the precision map lands).
+// Mixed-precision tiled Cholesky: per-tile precision of the trailing update.
+//
+// Every tile is stored in binary64 and the diagonal tiles, POTRF, TRSM, the
+// solve and the log-determinant stay binary64.  What changes is the precision
+// of the trailing products A_ij -= L_ik L_jkᵀ of off-band tiles, chosen per
+// tile (i, j) from the normalised tile norm
+//     ν_ij = ||Σ_ij||_F / sqrt(||Σ_ii||_F ||Σ_jj||_F)
+// measured when Σ is generated:
+//   class 0  FP64    diagonal tiles, tiles with i - j < band, and (FP32 mode)
+//                    tiles with ν_ij > tol_hi;
+//   class 1  FP32    FP32 matrix-core products (GL_MIXED_FP32);
+//   class 2  BF16x6  operands split into three bfloat16 parts a = h + m + l,
+//                    products hh + hm + mh + hl + lh + mm: about FP32 accuracy
+//                    (GL_MIXED_BF16, ν_ij > tol_hi);
+//   class 3  BF16x3  two parts, products hh + hm + mh (tol_lo < ν_ij <= tol_hi);
+//   class 4  BF16    one part (ν_ij <= tol_lo).
+// Low-precision products accumulate in FP32 over the whole K = b of one tile
+// update and are then subtracted from the binary64 tile.
+// The split-bfloat16 products follow Henry, Tang and Heinecke, "Leveraging the
+// bfloat16 artificial intelligence datatype for higher-precision
+// computations" (ARITH 2019).
+//
+// After the TRSM of step k, the panel column L_ik (i > k) is copied into the
+// formats the classes need: FP32 column-major, or bfloat16 parts stored
+// row-major (k contiguous, the operand layout of the BF16 matrix-core
+// product).  Copies are double-buffered by the parity of k, so the bulk
+// update of step k can still read them while step k+1 writes its own.
+#include <vector>
+
 #include "engine.hpp"
+#include "mfma.hpp"
 
 namespace gl {
 
-size_t mixed_extra_bytes(int64_t, int) { return 0; }
+enum { C64 = 0, C32 = 1, CB6 = 2, CB3 = 3, CB1 = 4, NCLASS = 5 };
+
+// ------------------------------------------------------------ precision map --
+
+__global__ void classify_kernel(const double *__restrict__ norm2, int64_t nt, int band, int mode,
+                                double tol_hi, double tol_lo, uint8_t *__restrict__ map)
+{
+    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (t >= tile_count(nt)) return;
+    int64_t i = (int64_t)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
+    while (i * (i + 1) / 2 > t) --i;
+    while ((i + 1) * (i + 2) / 2 <= t) ++i;
+    const int64_t j = t - i * (i + 1) / 2;
+    uint8_t c;
+    if (i - j < band) {
+        c = C64;
+    } else {
+        const double nij = sqrt(norm2[t]);
+        const double nii = sqrt(norm2[tile_index(i, i)]);
+        const double njj = sqrt(norm2[tile_index(j, j)]);
+        const double v = nij / sqrt(nii * njj);
+        if (mode == GL_MIXED_FP32) c = (v > tol_hi) ? C64 : C32;
+        else c = (v > tol_hi) ? CB6 : (v > tol_lo) ? CB3 : CB1;
+    }
+    map[t] = c;
+}
+
+// --------------------------------------------------------------- bfloat16 --
+
+// Round to nearest even (finite inputs).
+__device__ inline uint16_t bf16_bits(float f)
+{
+    const uint32_t u = __float_as_uint(f);
+    return (uint16_t)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
+}
+__device__ inline float bf16_value(uint16_t h) { return __uint_as_float(((uint32_t)h) << 16); }
+
+// Panel copies of step k.  Workgroup (tile i, 64×64 block): reads the binary64
+// block of L_ik and writes the FP32 copy (column-major) or np bfloat16 parts
+// (row-major, via an LDS transpose).
+template <int B>
+__global__ __launch_bounds__(256) void panel_convert_kernel(const double *__restrict__ tiles, int64_t k,
+                                                            float *__restrict__ p32,
+                                                            uint16_t *__restrict__ planes,
+                                                            int64_t plane_stride, int np,
+                                                            const int64_t *__restrict__ info)
+{
+    if (*info != 0) return;
+    const int64_t i = k + 1 + blockIdx.x;
+    const int bi = blockIdx.y / (B / 64), bj = blockIdx.y % (B / 64);  // row block, column block
+    const double *L = tiles + tile_offset(i, k, B);
+    const int tid = threadIdx.x;
+    if (p32) {
+        float *P = p32 + i * (int64_t)B * B;
+        for (int e = tid; e < 64 * 64; e += 256) {
+            const int c = e >> 6, r = e & 63;
+            const int64_t off = (int64_t)(bj * 64 + c) * B + bi * 64 + r;
+            P[off] = (float)L[off];
+        }
+    }
+    if (planes) {
+        __shared__ float T[64][65];  // T[r][c]
+        for (int e = tid; e < 64 * 64; e += 256) {
+            const int c = e >> 6, r = e & 63;
+            T[r][c] = (float)L[(int64_t)(bj * 64 + c) * B + bi * 64 + r];
+        }
+        __syncthreads();
+        for (int e = tid; e < 64 * 64; e += 256) {
+            const int r = e >> 6, c = e & 63;  // write row-major: consecutive threads, consecutive c
+            const int64_t off = i * (int64_t)B * B + (int64_t)(bi * 64 + r) * B + bj * 64 + c;
+            float v = T[r][c];
+            for (int p = 0; p < np; ++p) {
+                const uint16_t h = bf16_bits(v);
+                planes[p * plane_stride + off] = h;
+                v = v - bf16_value(h);
+            }
+        }
+    }
+}
+
+// ------------------------------------------------- FP32 trailing update --
+
+constexpr int FB = 128;  // output block
+constexpr int FK = 32;   // k chunk (eight 16x16x4 steps)
+
+__device__ inline void list_tile(const int2 *__restrict__ list, int64_t G, int64_t nblocks, int sub_per_tile,
+                                 int64_t &t, int &sub, bool &valid)
+{
+    const int64_t g = blockIdx.x;
+    const int64_t lid = (g & 7) * (G >> 3) + (g >> 3);  // XCD-contiguous logical order
+    valid = lid < nblocks;
+    t = lid / sub_per_tile;
+    sub = (int)(lid % sub_per_tile);
+}
+
+template <int B>
+__global__ __launch_bounds__(256, 2) void trailing_f32_kernel(double *__restrict__ tiles,
+                                                              const float *__restrict__ p32,
+                                                              const int2 *__restrict__ list,
+                                                              int64_t nblocks,
+                                                              const int64_t *__restrict__ info,
+                                                              int critical)
+{
+    if (*info != 0) return;
+    if (critical) __builtin_amdgcn_s_setprio(3);
+    constexpr int SB = B / FB;
+    int64_t t;
+    int sub;
+    bool valid;
+    list_tile(list, gridDim.x, nblocks, SB * SB, t, sub, valid);
+    if (!valid) return;
+    const int2 ij = list[t];
+    const int rb = sub / SB, cb = sub % SB;
+    const float *Ap = p32 + (int64_t)ij.x * B * B + rb * FB;
+    const float *Bp = p32 + (int64_t)ij.y * B * B + cb * FB;
+    double *C = tiles + tile_offset(ij.x, ij.y, B) + (int64_t)(cb * FB) * B + rb * FB;
+
+    __shared__ float As[2][FK][FB];
+    __shared__ float Bs[2][FK][FB];
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+    const int wm = wave >> 1, wn = wave & 1;
+    const int lc = tid >> 3;          // chunk column 0..31
+    const int lr = (tid & 7) * 16;    // 16 consecutive rows
+    typedef float f4v __attribute__((ext_vector_type(4)));
+
+    f4 acc[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] = (f4){0.f, 0.f, 0.f, 0.f};
+
+    f4v ra[4], rbv[4];
+    {
+        const f4v *pa = reinterpret_cast<const f4v *>(Ap + (int64_t)lc * B + lr);
+        const f4v *pb = reinterpret_cast<const f4v *>(Bp + (int64_t)lc * B + lr);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            ra[q] = pa[q];
+            rbv[q] = pb[q];
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            *reinterpret_cast<f4v *>(&As[0][lc][lr + 4 * q]) = ra[q];
+            *reinterpret_cast<f4v *>(&Bs[0][lc][lr + 4 * q]) = rbv[q];
+        }
+    }
+    __syncthreads();
+    constexpr int NK = B / FK;
+    for (int kc = 0; kc < NK; ++kc) {
+        const int cur = kc & 1;
+        if (kc + 1 < NK) {
+            const int64_t col = (int64_t)(kc + 1) * FK + lc;
+            const f4v *pa = reinterpret_cast<const f4v *>(Ap + col * B + lr);
+            const f4v *pb = reinterpret_cast<const f4v *>(Bp + col * B + lr);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                ra[q] = pa[q];
+                rbv[q] = pb[q];
+            }
+        }
+#pragma unroll
+        for (int kk = 0; kk < FK; kk += 4) {
+            float av[4], bv[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                av[q] = As[cur][kk + (lane >> 4)][wm * 64 + q * 16 + (lane & 15)];
+                bv[q] = Bs[cur][kk + (lane >> 4)][wn * 64 + q * 16 + (lane & 15)];
+            }
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int b = 0; b < 4; ++b) acc[a][b] = mfma_f32(bv[b], av[a], acc[a][b]);
+        }
+        if (kc + 1 < NK) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                *reinterpret_cast<f4v *>(&As[cur ^ 1][lc][lr + 4 * q]) = ra[q];
+                *reinterpret_cast<f4v *>(&Bs[cur ^ 1][lc][lr + 4 * q]) = rbv[q];
+            }
+        }
+        __syncthreads();
+    }
+    // result element r of lane l: C row = lane % 16, C column = 4 (l / 16) + r
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            const int row = wm * 64 + a * 16 + mfma_col(lane);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int64_t col = wn * 64 + b * 16 + mfma32_row(lane, r);
+                C[col * B + row] -= (double)acc[a][b][r];
+            }
+        }
+}
+
+// ----------------------------------------------- BF16 trailing update ----
+
+constexpr int HK = 32;        // k chunk = one 16x16x32 product
+constexpr int HP = HK + 8;    // LDS row pitch in bf16 (80 bytes: conflict-free 16-byte reads)
+
+template <int B, int NP>
+__global__ __launch_bounds__(256, 2) void trailing_bf16_kernel(double *__restrict__ tiles,
+                                                               const uint16_t *__restrict__ planes,
+                                                               int64_t plane_stride,
+                                                               const int2 *__restrict__ list,
+                                                               int64_t nblocks,
+                                                               const int64_t *__restrict__ info,
+                                                               int critical)
+{
+    if (*info != 0) return;
+    if (critical) __builtin_amdgcn_s_setprio(3);
+    constexpr int SB = B / FB;
+    int64_t t;
+    int sub;
+    bool valid;
+    list_tile(list, gridDim.x, nblocks, SB * SB, t, sub, valid);
+    if (!valid) return;
+    const int2 ij = list[t];
+    const int rb = sub / SB, cb = sub % SB;
+    // row-major parts: element (r, kk) of tile slot s at s*B*B + r*B + kk
+    const uint16_t *Ap = planes + (int64_t)ij.x * B * B + (int64_t)(rb * FB) * B;
+    const uint16_t *Bp = planes + (int64_t)ij.y * B * B + (int64_t)(cb * FB) * B;
+    double *C = tiles + tile_offset(ij.x, ij.y, B) + (int64_t)(cb * FB) * B + rb * FB;
+
+    __shared__ uint16_t As[NP][FB][HP];
+    __shared__ uint16_t Bs[NP][FB][HP];
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+    const int wm = wave >> 1, wn = wave & 1;
+    typedef uint32_t u4 __attribute__((ext_vector_type(4)));
+
+    f4 acc[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] = (f4){0.f, 0.f, 0.f, 0.f};
+
+    // loader: 128 rows × 32 bf16 per part and operand = 512 16-byte pieces, two per thread
+    u4 ra[NP][2], rbv[NP][2];
+    auto load = [&](int k0) {
+#pragma unroll
+        for (int p = 0; p < NP; ++p)
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int piece = tid + 256 * h;
+                const int row = piece >> 2, part = piece & 3;
+                ra[p][h] = *reinterpret_cast<const u4 *>(Ap + p * plane_stride + (int64_t)row * B + k0 + part * 8);
+                rbv[p][h] = *reinterpret_cast<const u4 *>(Bp + p * plane_stride + (int64_t)row * B + k0 + part * 8);
+            }
+    };
+    auto store = [&]() {
+#pragma unroll
+        for (int p = 0; p < NP; ++p)
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int piece = tid + 256 * h;
+                const int row = piece >> 2, part = piece & 3;
+                *reinterpret_cast<u4 *>(&As[p][row][part * 8]) = ra[p][h];
+                *reinterpret_cast<u4 *>(&Bs[p][row][part * 8]) = rbv[p][h];
+            }
+    };
+    load(0);
+    constexpr int NK = B / HK;
+    for (int kc = 0; kc < NK; ++kc) {
+        store();
+        __syncthreads();
+        if (kc + 1 < NK) load((kc + 1) * HK);
+        // fragments: 8 consecutive k of one row per lane
+        bf16x8 af[NP][4], bfr[NP][4];
+#pragma unroll
+        for (int p = 0; p < NP; ++p)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                af[p][q] = *reinterpret_cast<const bf16x8 *>(&As[p][wm * 64 + q * 16 + (lane & 15)][8 * (lane >> 4)]);
+                bfr[p][q] = *reinterpret_cast<const bf16x8 *>(&Bs[p][wn * 64 + q * 16 + (lane & 15)][8 * (lane >> 4)]);
+            }
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+                // operands swapped (B-part first): result row = C column, lane % 16 = C row
+                acc[a][b] = mfma_bf16(bfr[0][b], af[0][a], acc[a][b]);
+                if (NP >= 2) {
+                    acc[a][b] = mfma_bf16(bfr[1][b], af[0][a], acc[a][b]);
+                    acc[a][b] = mfma_bf16(bfr[0][b], af[1][a], acc[a][b]);
+                }
+                if (NP >= 3) {
+                    acc[a][b] = mfma_bf16(bfr[2][b], af[0][a], acc[a][b]);
+                    acc[a][b] = mfma_bf16(bfr[0][b], af[2][a], acc[a][b]);
+                    acc[a][b] = mfma_bf16(bfr[1][b], af[1][a], acc[a][b]);
+                }
+            }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            const int row = wm * 64 + a * 16 + mfma_col(lane);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int64_t col = wn * 64 + b * 16 + mfma32_row(lane, r);
+                C[col * B + row] -= (double)acc[a][b][r];
+            }
+        }
+}
+
+// ------------------------------------------------------------- launchers --
+
+template <int B>
+static void launch_class(int cls, double *tiles, int64_t k, const MixedViews &mv, const int2 *list,
+                         int64_t count, const int64_t *info, bool critical, hipStream_t s)
+{
+    if (count <= 0) return;
+    const int64_t sub = (int64_t)(B / FB) * (B / FB);
+    const int64_t nblocks = count * sub;
+    const unsigned grid = (unsigned)(ceil_div(nblocks, 8) * 8);
+    const int crit = critical ? 1 : 0;
+    const int par = (int)(k & 1);
+    switch (cls) {
+    case C64:
+        launch_trailing_list(tiles, B, k, list, count, info, critical, s);
+        break;
+    case C32:
+        trailing_f32_kernel<B><<<grid, 256, 0, s>>>(tiles, mv.p32[par], list, nblocks, info, crit);
+        break;
+    case CB6:
+        trailing_bf16_kernel<B, 3><<<grid, 256, 0, s>>>(tiles, mv.planes[par], mv.plane_stride, list, nblocks, info, crit);
+        break;
+    case CB3:
+        trailing_bf16_kernel<B, 2><<<grid, 256, 0, s>>>(tiles, mv.planes[par], mv.plane_stride, list, nblocks, info, crit);
+        break;
+    default:
+        trailing_bf16_kernel<B, 1><<<grid, 256, 0, s>>>(tiles, mv.planes[par], mv.plane_stride, list, nblocks, info, crit);
+        break;
+    }
+}
+
+static void launch_class_any(int b, int cls, double *tiles, int64_t k, const MixedViews &mv, const int2 *list,
+                             int64_t count, const int64_t *info, bool critical, hipStream_t s)
+{
+    switch (b) {
+    case 128: launch_class<128>(cls, tiles, k, mv, list, count, info, critical, s); break;
+    case 256: launch_class<256>(cls, tiles, k, mv, list, count, info, critical, s); break;
+    case 384: launch_class<384>(cls, tiles, k, mv, list, count, info, critical, s); break;
+    default: launch_class<512>(cls, tiles, k, mv, list, count, info, critical, s); break;
+    }
+}
+
+static void launch_panel_convert(const Work &w, int64_t k, const MixedViews &mv, hipStream_t s)
+{
+    const int64_t m = w.nt - k - 1;
+    if (m <= 0) return;
+    const int par = (int)(k & 1);
+    dim3 grid((unsigned)m, (unsigned)((w.b / 64) * (w.b / 64)));
+    float *p32 = mv.p32[par];
+    uint16_t *pl = mv.planes[par];
+    switch (w.b) {
+    case 128: panel_convert_kernel<128><<<grid, 256, 0, s>>>(w.tiles, k, p32, pl, mv.plane_stride, mv.np, w.info); break;
+    case 256: panel_convert_kernel<256><<<grid, 256, 0, s>>>(w.tiles, k, p32, pl, mv.plane_stride, mv.np, w.info); break;
+    case 384: panel_convert_kernel<384><<<grid, 256, 0, s>>>(w.tiles, k, p32, pl, mv.plane_stride, mv.np, w.info); break;
+    default: panel_convert_kernel<512><<<grid, 256, 0, s>>>(w.tiles, k, p32, pl, mv.plane_stride, mv.np, w.info); break;
+    }
+}
+
+// Device bytes of the mixed-precision side buffers for nt tiles of size b:
+// panel copies (two parities), the precision map and the tile lists.
+size_t mixed_extra_bytes(int64_t nt, int b, int precision)
+{
+    if (precision == GL_FP64) return 0;
+    const size_t slot = (size_t)nt * b * b;
+    size_t panel = (precision == GL_MIXED_FP32) ? 2 * slot * sizeof(float) : 2 * 3 * slot * sizeof(uint16_t);
+    const size_t tc = (size_t)tile_count(nt);
+    return panel + tc * sizeof(int2) + ((tc + 255) / 256) * 256 + 1024;
+}
+
 void mixed_views(Work &w)
 {
-    w.lo32 = nullptr;
-    w.pmap = nullptr;
+    MixedViews &mv = w.mv;
+    mv = MixedViews{};
+    if (w.precision == GL_FP64 || !w.mix) return;
+    const size_t slot = (size_t)w.nt * w.b * w.b;
+    char *p = static_cast<char *>(w.mix);
+    if (w.precision == GL_MIXED_FP32) {
+        mv.p32[0] = reinterpret_cast<float *>(p);
+        mv.p32[1] = mv.p32[0] + slot;
+        p += 2 * slot * sizeof(float);
+        mv.np = 0;
+    } else {
+        mv.planes[0] = reinterpret_cast<uint16_t *>(p);
+        mv.planes[1] = mv.planes[0] + 3 * slot;
+        mv.plane_stride = (int64_t)slot;
+        mv.np = 3;
+        p += 2 * 3 * slot * sizeof(uint16_t);
+    }
+    const size_t tc = (size_t)tile_count(w.nt);
+    mv.lists = reinterpret_cast<int2 *>(p);
+    p += tc * sizeof(int2);
+    mv.map = reinterpret_cast<uint8_t *>(p);
 }
-int mixed_factorize(Lanes &, Work &, gl_theta, const gl_opts &, hipStream_t) { return GL_EINVAL; }
-void mixed_backward(Work &, double *, hipStream_t) {}
+
+// Classify the tiles on the device, bring the map to the host, build the
+// per-class tile lists in column order and upload them.
+static int build_lists(Work &w, const gl_opts &o, hipStream_t s, MixedPlan &plan)
+{
+    const int64_t nt = w.nt;
+    const int64_t tc = tile_count(nt);
+    const int mode = w.precision;
+    const double tol_hi = o.tol_hi, tol_lo = o.tol_lo;
+    classify_kernel<<<(unsigned)ceil_div(tc, 256), 256, 0, s>>>(w.norm2, nt, o.band, mode, tol_hi, tol_lo, w.mv.map);
+    GL_HIP_TRY(hipGetLastError());
+    std::vector<uint8_t> map((size_t)tc);
+    GL_HIP_TRY(hipMemcpyAsync(map.data(), w.mv.map, (size_t)tc, hipMemcpyDeviceToHost, s));
+    GL_HIP_TRY(hipStreamSynchronize(s));
+    plan.start.assign(NCLASS, std::vector<int64_t>(nt + 2, 0));
+    std::vector<int2> all;
+    all.reserve((size_t)tc);
+    for (int c = 0; c < NCLASS; ++c) {
+        plan.base[c] = (int64_t)all.size();
+        plan.tiles[c] = 0;
+        plan.work[c] = 0.0;
+        for (int64_t j = 0; j < nt; ++j) {
+            plan.start[c][j] = (int64_t)all.size() - plan.base[c];
+            for (int64_t i = j; i < nt; ++i)
+                if (map[(size_t)tile_index(i, j)] == c) {
+                    all.push_back(make_int2((int)i, (int)j));
+                    plan.tiles[c] += 1;
+                    plan.work[c] += (double)j;  // tile (i, j) receives j trailing updates
+                }
+        }
+        plan.start[c][nt] = (int64_t)all.size() - plan.base[c];
+        plan.start[c][nt + 1] = plan.start[c][nt];
+    }
+    GL_HIP_TRY(hipMemcpyAsync(w.mv.lists, all.data(), all.size() * sizeof(int2), hipMemcpyHostToDevice, s));
+    GL_HIP_TRY(hipStreamSynchronize(s));  // `all` is a host temporary
+    return GL_OK;
+}
+
+// Trailing updates of step k for tile columns [j0, j1] of every class.
+static void class_updates(Work &w, int64_t k, int64_t j0, int64_t j1, const MixedPlan &plan, bool critical,
+                          hipStream_t s)
+{
+    for (int c = 0; c < NCLASS; ++c) {
+        const int64_t a = plan.start[c][j0], e = plan.start[c][j1 + 1];
+        if (e > a)
+            launch_class_any(w.b, c, w.tiles, k, w.mv, w.mv.lists + plan.base[c] + a, e - a, w.info, critical, s);
+    }
+}
+
+int mixed_factorize(Lanes &ln, Work &w, gl_theta th, const gl_opts &o, hipStream_t s, MixedPlan *plan_out)
+{
+    launch_gen_tiles(w.tiles, w.x, w.y, w.n, w.b, w.nt, th, w.norm2, s);
+    MixedPlan plan;
+    int rc = build_lists(w, o, s, plan);
+    if (rc != GL_OK) return rc;
+    if (plan_out) *plan_out = plan;
+    hipStream_t la = ln.la;
+    GL_HIP_TRY(hipEventRecord(ln.fork, s));
+    GL_HIP_TRY(hipStreamWaitEvent(la, ln.fork, 0));
+    for (int64_t k = 0; k < w.nt; ++k) {
+        launch_potrf(w.tiles, w.b, k, w.n, w.info, w.logsum, w.dinv, s);
+        launch_fwd_diag(w.tiles, w.b, k, w.n, w.v, w.quad, w.dinv, w.info, s);
+        launch_trsm(w.tiles, w.b, w.nt, k, w.dinv, w.info, s);
+        launch_fwd_update(w.tiles, w.b, w.nt, k, w.v, w.info, s);
+        if (k + 1 < w.nt) {
+            launch_panel_convert(w, k, w.mv, s);
+            GL_HIP_TRY(hipEventRecord(ln.panel, s));
+            if (k > 0) GL_HIP_TRY(hipStreamWaitEvent(s, ln.bulk, 0));
+            class_updates(w, k, k + 1, k + 1, plan, true, s);
+            if (k + 2 < w.nt) {
+                GL_HIP_TRY(hipStreamWaitEvent(la, ln.panel, 0));
+                class_updates(w, k, k + 2, w.nt - 1, plan, false, la);
+                GL_HIP_TRY(hipEventRecord(ln.bulk, la));
+            }
+        }
+    }
+    GL_HIP_TRY(hipGetLastError());
+    GL_HIP_TRY(hipEventRecord(ln.join, la));
+    GL_HIP_TRY(hipStreamWaitEvent(s, ln.join, 0));
+    return GL_OK;
+}
 
 }  // namespace gl

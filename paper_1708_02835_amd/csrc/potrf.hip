@@ -18,6 +18,7 @@
 // A non-positive (or NaN) pivot stores the 1-based global column in *info and
 // stops; every later kernel of the factorisation then returns immediately.
 // The tile's contribution 2 Σ log L_rr over rows r < n goes to logsum[k].
+#include "batch.hpp"
 #include "common.hpp"
 #include "mfma.hpp"
 
@@ -26,10 +27,9 @@ namespace gl {
 constexpr int PB = 64;  // diagonal block edge
 
 template <int B>
-__global__ __launch_bounds__(256) void potrf_kernel(double *__restrict__ tiles, int64_t k, int64_t n,
-                                                    int64_t *__restrict__ info,
-                                                    double *__restrict__ logsum,
-                                                    double *__restrict__ dinv)
+__device__ __forceinline__ void potrf_body(double *__restrict__ tiles, int64_t k, int64_t n,
+                                           int64_t *__restrict__ info, double *__restrict__ logsum,
+                                           double *__restrict__ dinv)
 {
     if (*info != 0) return;
     __builtin_amdgcn_s_setprio(3);  // critical path of the step schedule
@@ -186,6 +186,15 @@ __global__ __launch_bounds__(256) void potrf_kernel(double *__restrict__ tiles, 
     if (tid == 0) logsum[k] = 2.0 * ((red[0] + red[1]) + (red[2] + red[3]));
 }
 
+template <int B>
+__global__ __launch_bounds__(256) void potrf_kernel(double *__restrict__ tiles, int64_t k, int64_t n,
+                                                    int64_t *__restrict__ info,
+                                                    double *__restrict__ logsum,
+                                                    double *__restrict__ dinv)
+{
+    potrf_body<B>(tiles, k, n, info, logsum, dinv);
+}
+
 void launch_potrf(double *tiles, int b, int64_t k, int64_t n, int64_t *info, double *logsum,
                   double *dinv, hipStream_t s)
 {
@@ -195,6 +204,19 @@ void launch_potrf(double *tiles, int b, int64_t k, int64_t n, int64_t *info, dou
     case 384: potrf_kernel<384><<<1, 256, 0, s>>>(tiles, k, n, info, logsum, dinv); break;
     default: potrf_kernel<512><<<1, 256, 0, s>>>(tiles, k, n, info, logsum, dinv); break;
     }
+}
+
+template <int B>
+__global__ __launch_bounds__(256) void potrf_batched_kernel(const BatchReq *__restrict__ d)
+{
+    const BatchReq &r = d[blockIdx.x];
+    potrf_body<B>(r.tiles, r.k, r.n, r.info, r.logsum, r.dinv);
+}
+
+void launch_potrf_batched(int b, const BatchReq *d, int count, hipStream_t s)
+{
+    if (b == 128) potrf_batched_kernel<128><<<count, 256, 0, s>>>(d);
+    else potrf_batched_kernel<256><<<count, 256, 0, s>>>(d);
 }
 
 }  // namespace gl

@@ -1,13 +1,25 @@
 // Request queue for many concurrent likelihood clients (the optimiser callbacks
 // of Sec. 5.2, each asking for l(θ) at a new θ).
 //
-// A scheduler thread owns a set of device slots (a stream, a lookahead lane,
-// a workspace and a pinned result buffer each).  Queued requests are admitted
-// in arrival order while a slot is free and the device bytes held by slots
-// stay within the HBM budget; an admitted request's whole evaluation is
-// enqueued on its slot's stream, so requests that arrive while others are on
-// the device overlap with them.  Completion is detected with events and the
-// slot is reused for the next queued request.
+// A scheduler thread serves requests in two ways.
+//
+// Continuous batching (FP64 requests with n <= small_n): admitted requests
+// join a resident set; every scheduler tick advances each resident request by
+// one step of its tiled factorisation through one fused launch per kernel
+// (staging and Σ generation for newcomers, POTRF, forward diagonal solve,
+// TRSM, forward update, trailing update, final reduction for those whose last
+// step it is).  A launch covers all residents, each at its own step, so
+// requests that arrive while others are on the device join at the next tick
+// and leave when done.  Two ticks may be in flight.  Each request runs the
+// same per-request code as a single evaluation with tile 256, so its result
+// does not depend on the batch it rides in.
+//
+// Other requests use device slots (a stream, a lookahead lane, a workspace
+// and a pinned result buffer each) and run their whole evaluation on the
+// slot's stream.
+//
+// Admission is in arrival order, while the resident count stays within
+// max_inflight and the workspaces held stay within the HBM budget.
 #include <chrono>
 #include <condition_variable>
 #include <deque>
@@ -15,6 +27,7 @@
 #include <thread>
 #include <unordered_map>
 
+#include "batch.hpp"
 #include "engine.hpp"
 
 namespace gl {
@@ -92,6 +105,27 @@ struct Slot {
     Request *req = nullptr;
 };
 
+constexpr int TICK_B = 256;     // tile size of the batched engine
+constexpr int TICK_RING = 4;    // descriptor buffers
+constexpr int TICK_DEPTH = 2;   // ticks in flight
+constexpr int TICK_MAX = 64;    // residents per tick
+
+struct Resident {
+    Request *req = nullptr;
+    Work *w = nullptr;
+    int64_t k = 0;
+    bool is_new = true;
+};
+
+struct TickBuf {
+    BatchReq *host = nullptr;  // pinned
+    BatchReq *dev = nullptr;
+    DevResult *res_h = nullptr;  // pinned, one per finishing request
+    hipEvent_t done = nullptr;
+    bool busy = false;
+    std::vector<Resident> finishing;
+};
+
 }  // namespace
 
 struct lq_queue {
@@ -105,6 +139,13 @@ struct lq_queue {
     uint64_t next_ticket = 1;
     bool stop = false;
     std::vector<Slot> slots;
+    // continuous batching
+    hipStream_t ts = nullptr;
+    std::vector<Resident> residents;
+    std::vector<Work *> pool;  // idle workspaces of the batched engine
+    TickBuf ring[TICK_RING];
+    int ring_next = 0;
+    std::deque<int> ticks;     // ring indices in flight, oldest first
     int inflight = 0, peak_inflight = 0;
     size_t peak_bytes = 0;
     uint64_t completed = 0, fused = 0;
@@ -112,15 +153,6 @@ struct lq_queue {
 };
 
 namespace {
-
-size_t slot_bytes(const Slot &sl) { return sl.w.tile_cap + sl.w.vec_cap; }
-
-size_t held_bytes(const lq_queue *q)
-{
-    size_t t = 0;
-    for (const Slot &sl : q->slots) t += slot_bytes(sl);
-    return t;
-}
 
 void finish(lq_queue *q, Request *r, int status)
 {
@@ -132,6 +164,178 @@ void finish(lq_queue *q, Request *r, int status)
     q->cv_done.notify_all();
 }
 
+size_t slot_bytes(const Slot &sl) { return sl.w.bytes(); }
+
+size_t held_bytes(const lq_queue *q)
+{
+    size_t t = 0;
+    for (const Slot &sl : q->slots) t += slot_bytes(sl);
+    for (const Work *w : q->pool) t += w->bytes();
+    for (const Resident &r : q->residents) t += r.w->bytes();
+    for (int i = 0; i < TICK_RING; ++i)
+        for (const Resident &r : q->ring[i].finishing) t += r.w->bytes();
+    return t;
+}
+
+bool batch_eligible(const lq_queue *q, const Request *r)
+{
+    return q->cfg.batch_small && r->o.precision == GL_FP64 && r->o.reorder == 0 &&
+           (r->o.tile == 0 || r->o.tile == TICK_B) && r->ds->n <= q->cfg.small_n;
+}
+
+// A workspace for n points from the pool (grown when too small), or a new one.
+int take_work(lq_queue *q, int64_t n, Work *&out)
+{
+    Work *best = nullptr;
+    size_t need = work_bytes(n, TICK_B, GL_FP64);
+    for (size_t i = 0; i < q->pool.size(); ++i)
+        if (q->pool[i]->bytes() >= need) {
+            best = q->pool[i];
+            q->pool.erase(q->pool.begin() + i);
+            break;
+        }
+    if (!best) {
+        if (!q->pool.empty()) {
+            best = q->pool.back();
+            q->pool.pop_back();
+        } else {
+            best = new Work();
+        }
+    }
+    int rc = best->ensure(q->ctx, n, TICK_B, GL_FP64);
+    if (rc != GL_OK) {
+        q->ctx->used -= best->bytes();
+        best->release();
+        delete best;
+        return rc;
+    }
+    out = best;
+    return GL_OK;
+}
+
+// Enqueue one tick: every resident advances by one step.
+int build_tick(lq_queue *q)
+{
+    TickBuf &tb = q->ring[q->ring_next];
+    if (tb.busy) return GL_EBUSY;
+    const int count = (int)q->residents.size();
+    int64_t o_stage = 0, o_gen = 0, o_trsm = 0, o_tr = 0;
+    const int64_t sub = (TICK_B / 128) * (TICK_B / 128);
+    bool any_new = false, any_fin = false;
+    for (int i = 0; i < count; ++i) {
+        Resident &r = q->residents[i];
+        Work &w = *r.w;
+        BatchReq &d = tb.host[i];
+        d.tiles = w.tiles;
+        d.x = w.x;
+        d.y = w.y;
+        d.v = w.v;
+        d.dinv = w.dinv;
+        d.logsum = w.logsum;
+        d.quad = w.quad;
+        d.info = w.info;
+        d.res = w.res;
+        const int64_t n = r.req->ds->n;
+        d.sx = r.req->ds->buf;
+        d.sy = d.sx + n;
+        d.sz = d.sy + n;
+        d.th = r.req->th;
+        d.n = w.n;
+        d.nt = w.nt;
+        d.npad = w.npad;
+        d.k = r.k;
+        d.o_stage = o_stage;
+        d.o_gen = o_gen;
+        d.o_trsm = o_trsm;
+        d.o_tr = o_tr;
+        d.is_new = r.is_new ? 1 : 0;
+        d.finishing = (r.k == w.nt - 1) ? 1 : 0;
+        if (r.is_new) {
+            o_stage += ceil_div(w.npad, 256);
+            o_gen += tile_count(w.nt);
+            any_new = true;
+        }
+        const int64_t m = w.nt - r.k - 1;
+        o_trsm += m * (TICK_B / 64);
+        o_tr += m * (m + 1) / 2 * sub;
+        any_fin = any_fin || d.finishing;
+    }
+    hipStream_t s = q->ts;
+    GL_HIP_TRY(hipMemcpyAsync(tb.dev, tb.host, count * sizeof(BatchReq), hipMemcpyHostToDevice, s));
+    int launches = 0;
+    if (any_new) {
+        launch_stage_batched(tb.dev, count, o_stage, s);
+        launch_gen_batched(TICK_B, tb.dev, count, o_gen, s);
+        launches += 2;
+    }
+    launch_potrf_batched(TICK_B, tb.dev, count, s);
+    launch_fwd_diag_batched(TICK_B, tb.dev, count, s);
+    launch_trsm_batched(TICK_B, tb.dev, count, o_trsm, s);
+    launch_fwd_update_batched(TICK_B, tb.dev, count, o_trsm, s);
+    launch_trailing_batched(TICK_B, tb.dev, count, o_tr, s);
+    launches += 5;
+    tb.finishing.clear();
+    if (any_fin) {
+        launch_final_batched(tb.dev, count, s);
+        ++launches;
+    }
+    GL_HIP_TRY(hipGetLastError());
+    std::vector<Resident> keep;
+    keep.reserve(q->residents.size());
+    for (int i = 0; i < count; ++i) {
+        Resident r = q->residents[i];
+        r.is_new = false;
+        if (tb.host[i].finishing) {
+            GL_HIP_TRY(hipMemcpyAsync(&tb.res_h[tb.finishing.size()], r.w->res, sizeof(DevResult),
+                                      hipMemcpyDeviceToHost, s));
+            tb.finishing.push_back(r);
+        } else {
+            r.k += 1;
+            keep.push_back(r);
+        }
+    }
+    q->residents.swap(keep);
+    GL_HIP_TRY(hipEventRecord(tb.done, s));
+    tb.busy = true;
+    q->ticks.push_back(q->ring_next);
+    q->ring_next = (q->ring_next + 1) % TICK_RING;
+    q->fused += launches;
+    return GL_OK;
+}
+
+// Deliver the results of completed ticks (oldest first).
+void retire_ticks(lq_queue *q)
+{
+    while (!q->ticks.empty()) {
+        TickBuf &tb = q->ring[q->ticks.front()];
+        hipError_t e = hipEventQuery(tb.done);
+        if (e == hipErrorNotReady) return;
+        for (size_t i = 0; i < tb.finishing.size(); ++i) {
+            Resident &r = tb.finishing[i];
+            Request *req = r.req;
+            const DevResult &d = tb.res_h[i];
+            --q->inflight;
+            ++q->completed;
+            if (e != hipSuccess) {
+                finish(q, req, GL_EHIP);
+            } else {
+                req->res.loglik = d.loglik;
+                req->res.logdet = d.logdet;
+                req->res.quad = d.quad;
+                req->res.info = d.info;
+                req->res.tile = TICK_B;
+                req->res.factor = nullptr;
+                finish(q, req, d.info ? GL_NOT_SPD : GL_OK);
+            }
+            q->pool.push_back(r.w);
+        }
+        tb.finishing.clear();
+        tb.busy = false;
+        q->ticks.pop_front();
+    }
+}
+
+
 // Launch request r on slot sl (queue lock released by the caller).
 int launch_on_slot(gl_context *ctx, Slot &sl, Request *r)
 {
@@ -140,9 +344,7 @@ int launch_on_slot(gl_context *ctx, Slot &sl, Request *r)
     int rc = sl.w.ensure(ctx, n, b, r->o.precision);
     if (rc != GL_OK) return rc;
     const double *x = r->ds->buf, *y = x + n, *z = y + n;
-    launch_copy_pad(x, n, sl.w.x, sl.w.npad, 0.0, sl.s);
-    launch_copy_pad(y, n, sl.w.y, sl.w.npad, 0.0, sl.s);
-    launch_copy_pad(z, n, sl.w.v, sl.w.npad, 0.0, sl.s);
+    stage_inputs(sl.w, x, y, z, r->o.reorder, sl.s);
     rc = eval_launch(sl.ln, sl.w, r->th, r->o, sl.s, sl.res_h);
     if (rc != GL_OK) return rc;
     GL_HIP_TRY(hipEventRecord(sl.done, sl.s));
@@ -175,8 +377,52 @@ void scheduler(lq_queue *q)
             r->res.factor = nullptr;
             finish(q, r, sl.res_h->info ? GL_NOT_SPD : GL_OK);
         }
-        // admit queued requests into free slots, in arrival order
+        retire_ticks(q);
+        // admit queued requests in arrival order: batched residents or free slots
         while (!q->queue.empty()) {
+            Request *head = q->queue.front();
+            if (batch_eligible(q, head)) {
+                if (q->inflight >= q->cfg.max_inflight || (int)q->residents.size() >= TICK_MAX) break;
+                const size_t need = work_bytes(head->ds->n, TICK_B, GL_FP64);
+                bool have = false;
+                for (Work *w : q->pool) have = have || w->bytes() >= need;
+                if (!have && held_bytes(q) + need > q->budget) {
+                    // give back idle memory: pooled workspaces and idle slots
+                    for (Work *w : q->pool) {
+                        q->ctx->used -= w->bytes();
+                        w->release();
+                        delete w;
+                    }
+                    q->pool.clear();
+                    for (Slot &sl : q->slots)
+                        if (!sl.req && slot_bytes(sl)) {
+                            q->ctx->used -= slot_bytes(sl);
+                            sl.w.release();
+                        }
+                    if (held_bytes(q) + need > q->budget) {
+                        if (q->inflight > 0) break;  // wait for running requests to free memory
+                        q->queue.pop_front();
+                        finish(q, head, GL_ENOMEM);  // larger than the whole budget
+                        continue;
+                    }
+                }
+                Work *w = nullptr;
+                int rc = take_work(q, head->ds->n, w);
+                q->queue.pop_front();
+                if (rc != GL_OK) {
+                    finish(q, head, rc);
+                    continue;
+                }
+                head->state = RUNNING;
+                Resident res;
+                res.req = head;
+                res.w = w;
+                q->residents.push_back(res);
+                ++q->inflight;
+                if (q->inflight > q->peak_inflight) q->peak_inflight = q->inflight;
+                continue;
+            }
+            if (q->inflight >= q->cfg.max_inflight) break;
             Slot *free_slot = nullptr;
             for (Slot &sl : q->slots)
                 if (!sl.req) {
@@ -219,6 +465,20 @@ void scheduler(lq_queue *q)
             }
             const size_t h = held_bytes(q);
             if (h > q->peak_bytes) q->peak_bytes = h;
+        }
+        if (!q->residents.empty() && (int)q->ticks.size() < TICK_DEPTH) {
+            const int rc = build_tick(q);
+            if (rc != GL_OK && rc != GL_EBUSY) {
+                for (Resident &r : q->residents) {
+                    --q->inflight;
+                    finish(q, r.req, rc);
+                    q->pool.push_back(r.w);
+                }
+                q->residents.clear();
+            }
+            const size_t h = held_bytes(q);
+            if (h > q->peak_bytes) q->peak_bytes = h;
+            continue;
         }
         if (q->stop && q->queue.empty() && q->inflight == 0) break;
         if (q->inflight > 0) {
@@ -305,7 +565,7 @@ int gl_dataset_release(gl_context *ctx, uint64_t id)
 void lq_config_default(lq_config *c)
 {
     if (!c) return;
-    c->max_inflight = 8;
+    c->max_inflight = 32;
     c->streams = 4;
     c->batch_small = 1;
     c->small_n = 16384;
@@ -324,12 +584,29 @@ int lq_create(gl_context *ctx, const lq_config *cfg, lq_queue **out)
     q->ctx = ctx;
     q->cfg = c;
     q->budget = c.hbm_budget_bytes ? c.hbm_budget_bytes : ctx->budget;
-    q->slots.resize(c.max_inflight);
+    q->slots.resize(c.streams);
     for (Slot &sl : q->slots) {
         if (hipStreamCreateWithFlags(&sl.s, hipStreamNonBlocking) != hipSuccess || sl.ln.create() != GL_OK ||
             hipEventCreateWithFlags(&sl.done, hipEventDisableTiming) != hipSuccess ||
             hipHostMalloc(reinterpret_cast<void **>(&sl.res_h), sizeof(DevResult), hipHostMallocDefault) !=
                 hipSuccess) {
+            q->stop = true;
+            lq_destroy(q);
+            return GL_EHIP;
+        }
+    }
+    if (hipStreamCreateWithFlags(&q->ts, hipStreamNonBlocking) != hipSuccess) {
+        q->stop = true;
+        lq_destroy(q);
+        return GL_EHIP;
+    }
+    for (TickBuf &tb : q->ring) {
+        if (hipHostMalloc(reinterpret_cast<void **>(&tb.host), TICK_MAX * sizeof(BatchReq), hipHostMallocDefault) !=
+                hipSuccess ||
+            hipMalloc(reinterpret_cast<void **>(&tb.dev), TICK_MAX * sizeof(BatchReq)) != hipSuccess ||
+            hipHostMalloc(reinterpret_cast<void **>(&tb.res_h), TICK_MAX * sizeof(DevResult), hipHostMallocDefault) !=
+                hipSuccess ||
+            hipEventCreateWithFlags(&tb.done, hipEventDisableTiming) != hipSuccess) {
             q->stop = true;
             lq_destroy(q);
             return GL_EHIP;
@@ -353,6 +630,7 @@ int lq_submit(lq_queue *q, uint64_t ds, gl_theta th, const gl_opts *opts, uint64
     if (opts) o = *opts;
     o.keep_factor = 0;
     if (!valid_opts(o)) return GL_EINVAL;
+    o = resolved_opts(o);
     ServeState *st = serve_state(q->ctx);
     Request *r = new Request();
     {
@@ -472,6 +750,20 @@ int lq_destroy(lq_queue *q)
             }
     }
     hipSetDevice(q->ctx->device);
+    if (q->ts) hipStreamSynchronize(q->ts);
+    for (Work *w : q->pool) {
+        q->ctx->used -= w->bytes();
+        w->release();
+        delete w;
+    }
+    q->pool.clear();
+    for (TickBuf &tb : q->ring) {
+        if (tb.host) hipHostFree(tb.host);
+        if (tb.dev) hipFree(tb.dev);
+        if (tb.res_h) hipHostFree(tb.res_h);
+        if (tb.done) hipEventDestroy(tb.done);
+    }
+    if (q->ts) hipStreamDestroy(q->ts);
     for (Slot &sl : q->slots) {
         if (sl.s) hipStreamSynchronize(sl.s);
         q->ctx->used -= slot_bytes(sl);

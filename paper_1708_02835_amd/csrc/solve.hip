@@ -11,6 +11,7 @@
 // Every reduction has a fixed order, so results do not depend on scheduling.
 #include <math.h>
 
+#include "batch.hpp"
 #include "common.hpp"
 #include "mfma.hpp"
 
@@ -21,11 +22,10 @@ namespace gl {
 // Both products are split over four thread groups with fixed-order partial
 // sums.  The tile's part of wᵀw (rows < n) goes to quad_part[k].
 template <int B>
-__global__ __launch_bounds__(256) void fwd_diag_kernel(const double *__restrict__ tiles, int64_t k,
-                                                       int64_t n, double *__restrict__ v,
-                                                       double *__restrict__ quad_part,
-                                                       const double *__restrict__ dinv,
-                                                       const int64_t *__restrict__ info)
+__device__ __forceinline__ void fwd_diag_body(const double *__restrict__ tiles, int64_t k, int64_t n,
+                                              double *__restrict__ v, double *__restrict__ quad_part,
+                                              const double *__restrict__ dinv,
+                                              const int64_t *__restrict__ info)
 {
     if (info && *info != 0) return;
     __builtin_amdgcn_s_setprio(3);  // critical path of the step schedule
@@ -69,16 +69,26 @@ __global__ __launch_bounds__(256) void fwd_diag_kernel(const double *__restrict_
     }
 }
 
-// v_i -= L_ik v_k for every tile i > k; workgroup (i, 64-row strip).
 template <int B>
-__global__ __launch_bounds__(256) void fwd_update_kernel(const double *__restrict__ tiles, int64_t k,
-                                                         double *__restrict__ v,
-                                                         const int64_t *__restrict__ info)
+__global__ __launch_bounds__(256) void fwd_diag_kernel(const double *__restrict__ tiles, int64_t k,
+                                                       int64_t n, double *__restrict__ v,
+                                                       double *__restrict__ quad_part,
+                                                       const double *__restrict__ dinv,
+                                                       const int64_t *__restrict__ info)
+{
+    fwd_diag_body<B>(tiles, k, n, v, quad_part, dinv, info);
+}
+
+// v_i -= L_ik v_k for every tile i > k; workgroup (tile i = k + 1 + tix, 64-row strip).
+template <int B>
+__device__ __forceinline__ void fwd_update_body(const double *__restrict__ tiles, int64_t k,
+                                                double *__restrict__ v, const int64_t *__restrict__ info,
+                                                int64_t tix, int strip)
 {
     if (info && *info != 0) return;
     __builtin_amdgcn_s_setprio(3);
-    const int64_t i = k + 1 + blockIdx.x;
-    const int r0 = blockIdx.y * 64;
+    const int64_t i = k + 1 + tix;
+    const int r0 = strip * 64;
     const double *L = tiles + tile_offset(i, k, B);
     const int tid = threadIdx.x;
     __shared__ double wk[B];
@@ -91,6 +101,14 @@ __global__ __launch_bounds__(256) void fwd_update_kernel(const double *__restric
     red[g][r] = acc;
     __syncthreads();
     if (g == 0) v[i * B + r0 + r] -= (red[0][r] + red[1][r]) + (red[2][r] + red[3][r]);
+}
+
+template <int B>
+__global__ __launch_bounds__(256) void fwd_update_kernel(const double *__restrict__ tiles, int64_t k,
+                                                         double *__restrict__ v,
+                                                         const int64_t *__restrict__ info)
+{
+    fwd_update_body<B>(tiles, k, v, info, blockIdx.x, blockIdx.y);
 }
 
 // v_k <- L_kk⁻ᵀ v_k, 64-row blocks from the bottom: the block's rows first
@@ -185,9 +203,10 @@ __global__ __launch_bounds__(256) void trmv_kernel(const double *__restrict__ ti
 }
 
 // One wave: logdet = Σ_k logsum[k], quad = Σ_k quad_part[k], l by Eq. (1).
-__global__ void final_reduce_kernel(const double *__restrict__ logsum,
-                                    const double *__restrict__ quad_part, int64_t nt, int64_t n,
-                                    const int64_t *__restrict__ info, DevResult *__restrict__ res)
+__device__ __forceinline__ void final_reduce_body(const double *__restrict__ logsum,
+                                                  const double *__restrict__ quad_part, int64_t nt,
+                                                  int64_t n, const int64_t *__restrict__ info,
+                                                  DevResult *__restrict__ res)
 {
     const int lane = threadIdx.x;
     double a = 0.0, b = 0.0;
@@ -210,6 +229,13 @@ __global__ void final_reduce_kernel(const double *__restrict__ logsum,
             res->loglik = -0.5 * b - 0.5 * a - 0.5 * (double)n * log(2.0 * M_PI);
         }
     }
+}
+
+__global__ void final_reduce_kernel(const double *__restrict__ logsum,
+                                    const double *__restrict__ quad_part, int64_t nt, int64_t n,
+                                    const int64_t *__restrict__ info, DevResult *__restrict__ res)
+{
+    final_reduce_body(logsum, quad_part, nt, n, info, res);
 }
 
 __global__ void fill_kernel(double *__restrict__ p, int64_t count, double v)
@@ -239,6 +265,69 @@ __global__ void tiles_to_dense_kernel(const double *__restrict__ tiles, int b, i
         }
         out[r + c * ld] = v;
     }
+}
+
+template <int B>
+__global__ __launch_bounds__(256) void fwd_diag_batched_kernel(const BatchReq *__restrict__ d)
+{
+    const BatchReq &r = d[blockIdx.x];
+    fwd_diag_body<B>(r.tiles, r.k, r.n, r.v, r.quad, r.dinv, r.info);
+}
+
+template <int B>
+__global__ __launch_bounds__(256) void fwd_update_batched_kernel(const BatchReq *__restrict__ d, int count)
+{
+    const int64_t g = blockIdx.x;
+    const int r = GL_BATCH_FIND(d, count, g, o_trsm);
+    const BatchReq &q = d[r];
+    const int64_t local = g - q.o_trsm;
+    fwd_update_body<B>(q.tiles, q.k, q.v, q.info, local / (B / 64), (int)(local % (B / 64)));
+}
+
+__global__ void final_batched_kernel(const BatchReq *__restrict__ d)
+{
+    const BatchReq &r = d[blockIdx.x];
+    if (!r.finishing) return;
+    final_reduce_body(r.logsum, r.quad, r.nt, r.n, r.info, r.res);
+}
+
+// Padded copies of new requests' inputs, and their info word cleared.
+__global__ void stage_batched_kernel(const BatchReq *__restrict__ d, int count)
+{
+    const int64_t g = blockIdx.x;
+    const int r = GL_BATCH_FIND(d, count, g, o_stage);
+    const BatchReq &q = d[r];
+    const int64_t i = (g - q.o_stage) * 256 + threadIdx.x;
+    if (i == 0) *q.info = 0;
+    if (i >= q.npad) return;
+    const bool in = i < q.n;
+    q.x[i] = in ? q.sx[i] : 0.0;
+    q.y[i] = in ? q.sy[i] : 0.0;
+    q.v[i] = in ? q.sz[i] : 0.0;
+}
+
+void launch_fwd_diag_batched(int b, const BatchReq *d, int count, hipStream_t s)
+{
+    if (b == 128) fwd_diag_batched_kernel<128><<<count, 256, 0, s>>>(d);
+    else fwd_diag_batched_kernel<256><<<count, 256, 0, s>>>(d);
+}
+
+void launch_fwd_update_batched(int b, const BatchReq *d, int count, int64_t blocks, hipStream_t s)
+{
+    if (blocks <= 0) return;
+    if (b == 128) fwd_update_batched_kernel<128><<<(unsigned)blocks, 256, 0, s>>>(d, count);
+    else fwd_update_batched_kernel<256><<<(unsigned)blocks, 256, 0, s>>>(d, count);
+}
+
+void launch_final_batched(const BatchReq *d, int count, hipStream_t s)
+{
+    final_batched_kernel<<<count, 64, 0, s>>>(d);
+}
+
+void launch_stage_batched(const BatchReq *d, int count, int64_t blocks, hipStream_t s)
+{
+    if (blocks <= 0) return;
+    stage_batched_kernel<<<(unsigned)blocks, 256, 0, s>>>(d, count);
 }
 
 #define GL_DISPATCH_B(b, KERNEL, GRID, ...)                                   \

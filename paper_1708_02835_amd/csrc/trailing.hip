@@ -15,6 +15,7 @@
 // index is remapped so that each XCD works on a contiguous run of blocks,
 // i.e. on whole tiles and on neighbouring tiles of one column, which share
 // the L_jk operand in that XCD's L2.
+#include "batch.hpp"
 #include "common.hpp"
 #include "mfma.hpp"
 
@@ -37,28 +38,11 @@ __device__ inline void trailing_tile(int64_t t, int64_t jbeg, int64_t nt, int64_
     i = j + (t - (c * m0 - c * (c - 1) / 2));
 }
 
+// One 128×128 block (rb, cb) of the update of tile (i, j) by panel column k.
 template <int B>
-__global__ __launch_bounds__(256, 2) void trailing_f64_kernel(double *__restrict__ tiles, int64_t k,
-                                                              int64_t jbeg, int64_t nt,
-                                                              int64_t nblocks,
-                                                              const int64_t *__restrict__ info,
-                                                              int critical)
+__device__ __forceinline__ void trailing_block_body(double *__restrict__ tiles, int64_t k, int64_t i,
+                                                    int64_t j, int rb, int cb)
 {
-    if (*info != 0) return;
-    if (critical) __builtin_amdgcn_s_setprio(3);
-    constexpr int SB = B / GB;
-    constexpr int SUB = SB * SB;
-    const int64_t G = gridDim.x;  // a multiple of 8
-    const int64_t g = blockIdx.x;
-    const int64_t lid = (g & 7) * (G >> 3) + (g >> 3);
-    if (lid >= nblocks) return;
-    const int64_t t = lid / SUB;
-    const int sub = (int)(lid % SUB);
-    int64_t i, j;
-    trailing_tile(t, jbeg, nt, i, j);
-    const int rb = sub / SB, cb = sub % SB;
-    if (i == j && cb > rb) return;
-
     const double *Ap = tiles + tile_offset(i, k, B) + rb * GB;
     const double *Bp = tiles + tile_offset(j, k, B) + cb * GB;
     double *C = tiles + tile_offset(i, j, B) + (int64_t)(cb * GB) * B + rb * GB;
@@ -148,6 +132,37 @@ __global__ __launch_bounds__(256, 2) void trailing_f64_kernel(double *__restrict
     }
 }
 
+template <int B>
+__global__ __launch_bounds__(256, 2) void trailing_f64_kernel(double *__restrict__ tiles, int64_t k,
+                                                              int64_t jbeg, int64_t nt,
+                                                              int64_t nblocks,
+                                                              const int64_t *__restrict__ info,
+                                                              int critical,
+                                                              const int2 *__restrict__ list)
+{
+    if (*info != 0) return;
+    if (critical) __builtin_amdgcn_s_setprio(3);
+    constexpr int SB = B / GB;
+    constexpr int SUB = SB * SB;
+    const int64_t G = gridDim.x;  // a multiple of 8
+    const int64_t g = blockIdx.x;
+    const int64_t lid = (g & 7) * (G >> 3) + (g >> 3);
+    if (lid >= nblocks) return;
+    const int64_t t = lid / SUB;
+    const int sub = (int)(lid % SUB);
+    int64_t i, j;
+    if (list) {
+        const int2 ij = list[t];
+        i = ij.x;
+        j = ij.y;
+    } else {
+        trailing_tile(t, jbeg, nt, i, j);
+    }
+    const int rb = sub / SB, cb = sub % SB;
+    if (i == j && cb > rb) return;
+    trailing_block_body<B>(tiles, k, i, j, rb, cb);
+}
+
 void launch_trailing(double *tiles, int b, int64_t nt, int64_t k, int64_t jbeg, int64_t jend,
                      const int64_t *info, bool critical, hipStream_t s)
 {
@@ -160,10 +175,60 @@ void launch_trailing(double *tiles, int b, int64_t nt, int64_t k, int64_t jbeg, 
     const int64_t nblocks = ntiles * sub;
     const int64_t grid = ceil_div(nblocks, 8) * 8;
     switch (b) {
-    case 128: trailing_f64_kernel<128><<<(unsigned)grid, 256, 0, s>>>(tiles, k, jbeg, nt, nblocks, info, critical ? 1 : 0); break;
-    case 256: trailing_f64_kernel<256><<<(unsigned)grid, 256, 0, s>>>(tiles, k, jbeg, nt, nblocks, info, critical ? 1 : 0); break;
-    case 384: trailing_f64_kernel<384><<<(unsigned)grid, 256, 0, s>>>(tiles, k, jbeg, nt, nblocks, info, critical ? 1 : 0); break;
-    default: trailing_f64_kernel<512><<<(unsigned)grid, 256, 0, s>>>(tiles, k, jbeg, nt, nblocks, info, critical ? 1 : 0); break;
+    case 128: trailing_f64_kernel<128><<<(unsigned)grid, 256, 0, s>>>(tiles, k, jbeg, nt, nblocks, info, critical ? 1 : 0, nullptr); break;
+    case 256: trailing_f64_kernel<256><<<(unsigned)grid, 256, 0, s>>>(tiles, k, jbeg, nt, nblocks, info, critical ? 1 : 0, nullptr); break;
+    case 384: trailing_f64_kernel<384><<<(unsigned)grid, 256, 0, s>>>(tiles, k, jbeg, nt, nblocks, info, critical ? 1 : 0, nullptr); break;
+    default: trailing_f64_kernel<512><<<(unsigned)grid, 256, 0, s>>>(tiles, k, jbeg, nt, nblocks, info, critical ? 1 : 0, nullptr); break;
+    }
+}
+
+// Fused trailing updates of many requests, each at its own step k (columns
+// k+1 .. nt-1).  The flattened block index is remapped XCD-contiguously.
+template <int B>
+__global__ __launch_bounds__(256, 2) void trailing_batched_kernel(const BatchReq *__restrict__ d, int count,
+                                                                  int64_t nblocks)
+{
+    constexpr int SB = B / GB;
+    constexpr int SUB = SB * SB;
+    const int64_t G = gridDim.x;
+    const int64_t g = blockIdx.x;
+    const int64_t lid = (g & 7) * (G >> 3) + (g >> 3);
+    if (lid >= nblocks) return;
+    const int r = GL_BATCH_FIND(d, count, lid, o_tr);
+    const BatchReq &q = d[r];
+    if (*q.info != 0) return;
+    const int64_t local = lid - q.o_tr;
+    const int64_t t = local / SUB;
+    const int sub = (int)(local % SUB);
+    int64_t i, j;
+    trailing_tile(t, q.k + 1, q.nt, i, j);
+    const int rb = sub / SB, cb = sub % SB;
+    if (i == j && cb > rb) return;
+    trailing_block_body<B>(q.tiles, q.k, i, j, rb, cb);
+}
+
+void launch_trailing_batched(int b, const BatchReq *d, int count, int64_t blocks, hipStream_t s)
+{
+    if (blocks <= 0) return;
+    const int64_t grid = ceil_div(blocks, 8) * 8;
+    if (b == 128) trailing_batched_kernel<128><<<(unsigned)grid, 256, 0, s>>>(d, count, blocks);
+    else trailing_batched_kernel<256><<<(unsigned)grid, 256, 0, s>>>(d, count, blocks);
+}
+
+// Trailing updates of the tiles listed in `list` (count tiles, (i, j) pairs).
+void launch_trailing_list(double *tiles, int b, int64_t k, const int2 *list, int64_t count,
+                          const int64_t *info, bool critical, hipStream_t s)
+{
+    if (count <= 0) return;
+    const int64_t sub = (int64_t)(b / GB) * (b / GB);
+    const int64_t nblocks = count * sub;
+    const int64_t grid = ceil_div(nblocks, 8) * 8;
+    const int crit = critical ? 1 : 0;
+    switch (b) {
+    case 128: trailing_f64_kernel<128><<<(unsigned)grid, 256, 0, s>>>(tiles, k, 0, 0, nblocks, info, crit, list); break;
+    case 256: trailing_f64_kernel<256><<<(unsigned)grid, 256, 0, s>>>(tiles, k, 0, 0, nblocks, info, crit, list); break;
+    case 384: trailing_f64_kernel<384><<<(unsigned)grid, 256, 0, s>>>(tiles, k, 0, 0, nblocks, info, crit, list); break;
+    default: trailing_f64_kernel<512><<<(unsigned)grid, 256, 0, s>>>(tiles, k, 0, 0, nblocks, info, crit, list); break;
     }
 }
 

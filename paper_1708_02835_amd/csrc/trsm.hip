@@ -10,6 +10,7 @@
 // `dinv` by the POTRF of the same step.  The product streams 16-column chunks
 // of X and L_kk through LDS, double-buffered; X[:, 0:J] was written by this
 // workgroup in earlier blocks (visible after the block barrier).
+#include "batch.hpp"
 #include "common.hpp"
 #include "mfma.hpp"
 
@@ -19,15 +20,16 @@ constexpr int TB = 64;  // column block and strip height
 constexpr int TC = 16;  // k chunk
 constexpr int TP = TB + 16;  // LDS row pitch (bank spread of the 16-lane groups)
 
+// Strip `strip` (64 rows) of tile i = k + 1 + tix.
 template <int B>
-__global__ __launch_bounds__(256) void trsm_kernel(double *__restrict__ tiles, int64_t k,
-                                                   const double *__restrict__ dinv,
-                                                   const int64_t *__restrict__ info)
+__device__ __forceinline__ void trsm_body(double *__restrict__ tiles, int64_t k,
+                                          const double *__restrict__ dinv,
+                                          const int64_t *__restrict__ info, int64_t tix, int strip)
 {
     if (*info != 0) return;
     __builtin_amdgcn_s_setprio(3);  // critical path of the step schedule
-    const int64_t i = k + 1 + blockIdx.x;
-    const int r0 = blockIdx.y * TB;
+    const int64_t i = k + 1 + tix;
+    const int r0 = strip * TB;
     const double *L = tiles + tile_offset(k, k, B);
     double *X = tiles + tile_offset(i, k, B);
     const int tid = threadIdx.x;
@@ -124,6 +126,14 @@ __global__ __launch_bounds__(256) void trsm_kernel(double *__restrict__ tiles, i
     }
 }
 
+template <int B>
+__global__ __launch_bounds__(256) void trsm_kernel(double *__restrict__ tiles, int64_t k,
+                                                   const double *__restrict__ dinv,
+                                                   const int64_t *__restrict__ info)
+{
+    trsm_body<B>(tiles, k, dinv, info, blockIdx.x, blockIdx.y);
+}
+
 void launch_trsm(double *tiles, int b, int64_t nt, int64_t k, const double *dinv, const int64_t *info,
                  hipStream_t s)
 {
@@ -136,6 +146,23 @@ void launch_trsm(double *tiles, int b, int64_t nt, int64_t k, const double *dinv
     case 384: trsm_kernel<384><<<grid, 256, 0, s>>>(tiles, k, dinv, info); break;
     default: trsm_kernel<512><<<grid, 256, 0, s>>>(tiles, k, dinv, info); break;
     }
+}
+
+template <int B>
+__global__ __launch_bounds__(256) void trsm_batched_kernel(const BatchReq *__restrict__ d, int count)
+{
+    const int64_t g = blockIdx.x;
+    const int r = GL_BATCH_FIND(d, count, g, o_trsm);
+    const BatchReq &q = d[r];
+    const int64_t local = g - q.o_trsm;
+    trsm_body<B>(q.tiles, q.k, q.dinv, q.info, local / (B / TB), (int)(local % (B / TB)));
+}
+
+void launch_trsm_batched(int b, const BatchReq *d, int count, int64_t blocks, hipStream_t s)
+{
+    if (blocks <= 0) return;
+    if (b == 128) trsm_batched_kernel<128><<<(unsigned)blocks, 256, 0, s>>>(d, count);
+    else trsm_batched_kernel<256><<<(unsigned)blocks, 256, 0, s>>>(d, count);
 }
 
 }  // namespace gl

@@ -52,7 +52,8 @@ def test_status_strings_and_defaults():
     for st in [g.GL_EINVAL, g.GL_ENOMEM, g.GL_EHIP, g.GL_EBUSY, g.GL_ECANCELED, g.GL_ETIMEDOUT, g.GL_ENODEV]:
         assert g.gl_status_string(st) != "unknown status"
     o = g.gl_opts_default()
-    assert (o.precision, o.tile, o.keep_factor, o.band) == (g.GL_FP64, 0, 0, 2)
+    assert (o.precision, o.tile, o.keep_factor, o.band, o.reorder) == (g.GL_FP64, 0, 0, 2, -1)
+    assert o.tol_hi < 0 and o.tol_lo < 0
     c = g.lq_config_default()
     assert c.max_inflight >= 1 and 1 <= c.streams <= 8
 
@@ -63,8 +64,17 @@ def test_footprint_formula(n, tile):
     import paper_1708_02835_amd as g
     nt = -(-n // tile)
     tiles = nt * (nt + 1) // 2 * tile * tile * 8
-    vec = (3 * nt * tile + 4 * nt + nt * (nt + 1) // 2 + 64 * tile + 64) * 8
+    p2 = 1
+    while p2 < n:
+        p2 *= 2
+    vec = (3 * nt * tile + 2 * nt + nt * (nt + 1) // 2 + 64 * tile + 16 + p2 + 4) * 8
     assert g.gl_footprint_bytes(n, tile, g.GL_FP64) == tiles + vec
+    # mixed modes add the double-buffered panel copies, the tile lists and the map
+    tc = nt * (nt + 1) // 2
+    extra32 = 2 * nt * tile * tile * 4 + tc * 8 + ((tc + 255) // 256) * 256 + 1024
+    extra16 = 2 * 3 * nt * tile * tile * 2 + tc * 8 + ((tc + 255) // 256) * 256 + 1024
+    assert g.gl_footprint_bytes(n, tile, g.GL_MIXED_FP32) == tiles + vec + extra32
+    assert g.gl_footprint_bytes(n, tile, g.GL_MIXED_BF16) == tiles + vec + extra16
 
 
 def test_automatic_tile_choice_footprints_are_monotone():

@@ -1,0 +1,195 @@
+"""GPU checks of the Morton reordering and of the mixed-precision path.
+
+* The Morton permutation is integer work: it must equal, bit for bit, the
+  permutation defined by the documented keys, computed here with numpy.
+* Reordering is exact in real arithmetic (l is permutation invariant), so the
+  FP64 path in Morton order must agree with the oracle to the FP64 bound.
+* Mixed precision has no closed form; its error is measured against the
+  oracle's exact l.  The bound stated for the default modes is 1e-4 relative
+  on l.  Each precision class forced on every off-band tile gets the bound its
+  unit roundoff supports on a well-conditioned Σ (θ = (1, 0.1, 0.5), n = 2048,
+  about 2e-8 for FP32-grade products, 2e-5 for single bfloat16 products in
+  CPU emulations of the same algorithm), with a margin of 25-50×, so that a
+  missing product term or a wrong operand fails loudly.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import geoinputs
+import oracle
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def g():
+    import paper_1708_02835_amd as pkg
+    pkg.lib()
+    return pkg
+
+
+@pytest.fixture(scope="module")
+def ctx(g):
+    c = g.Context(0)
+    yield c
+    c.close()
+
+
+def dev(a):
+    return torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+
+
+def rel(a, b):
+    return abs(a - b) / abs(b)
+
+
+def morton_reference(x, y):
+    """Permutation of the documented keys: 16-bit quantisation over the bounding
+    box, x in the even bits, ties broken by the input index."""
+    def q(v):
+        lo, hi = v.min(), v.max()
+        span = hi - lo
+        if not span > 0:
+            return np.zeros(v.size, dtype=np.uint64)
+        f = np.floor((v - lo) / span * 65535.0)
+        return np.clip(f, 0, 65535).astype(np.uint64)
+
+    def spread(v):
+        v = (v | (v << np.uint64(8))) & np.uint64(0x00FF00FF)
+        v = (v | (v << np.uint64(4))) & np.uint64(0x0F0F0F0F)
+        v = (v | (v << np.uint64(2))) & np.uint64(0x33333333)
+        v = (v | (v << np.uint64(1))) & np.uint64(0x55555555)
+        return v
+    code = spread(q(x)) | (spread(q(y)) << np.uint64(1))
+    keys = (code << np.uint64(32)) | np.arange(x.size, dtype=np.uint64)
+    return np.argsort(keys, kind="stable")
+
+
+@pytest.mark.parametrize("case", ["grid", "uniform", "duplicates", "tiny", "line"])
+def test_morton_order_bit_exact(g, ctx, case):
+    if case == "grid":
+        x, y = geoinputs.jittered_grid(5000, 1)
+    elif case == "uniform":
+        x, y = geoinputs.uniform_points(3333, 2)
+    elif case == "duplicates":
+        x, y = geoinputs.uniform_points(700, 3)
+        x[100:200] = x[0]
+        y[100:200] = y[0]
+    elif case == "tiny":
+        x, y = np.array([0.3]), np.array([0.7])
+    else:
+        x = np.linspace(0.0, 1.0, 513)
+        y = np.full(513, 0.25)
+    got = g.gl_morton_order(ctx, dev(x), dev(y)).cpu().numpy()
+    assert np.array_equal(got, morton_reference(x, y))
+
+
+@pytest.mark.parametrize("n,tile", [(3000, 256), (1100, 128)])
+def test_fp64_in_morton_order(g, ctx, n, tile):
+    theta = (1.0, 0.1, 0.5)
+    x, y = geoinputs.jittered_grid(n, 31)
+    z = geoinputs.normal_vector(n, 31)
+    ref = oracle.loglik(x, y, z, theta)
+    a = g.loglik_eval(ctx, dev(x), dev(y), dev(z), theta, g.gl_opts_default(tile=tile, reorder=0))
+    b = g.loglik_eval(ctx, dev(x), dev(y), dev(z), theta, g.gl_opts_default(tile=tile, reorder=1))
+    assert rel(a["loglik"], ref[0]) <= 1e-10
+    assert rel(b["loglik"], ref[0]) <= 1e-10
+    assert rel(b["logdet"], ref[1]) <= 1e-10
+
+
+N_MIX = 2048
+_cache = {}
+
+
+def _problem(theta):
+    key = tuple(theta)
+    if key not in _cache:
+        x, y = geoinputs.jittered_grid(N_MIX, 3000)
+        e = geoinputs.normal_vector(N_MIX, 3000)
+        z, info = oracle.synth(x, y, e, theta)
+        assert info == 0
+        _cache[key] = (x, y, z, oracle.loglik(x, y, z, theta))
+    return _cache[key]
+
+
+# (name, precision, tol_hi, tol_lo, class that must hold every off-band tile, bound)
+FORCED = [
+    ("fp32", 1, -1.0, -1.0, "fp32", 1e-6),
+    ("bf16x6", 2, 0.0, 0.0, "bf16x6", 1e-6),
+    ("bf16x3", 2, math.inf, 0.0, "bf16x3", 1e-5),
+    ("bf16", 2, math.inf, math.inf, "bf16", 5e-4),
+]
+
+
+@pytest.mark.parametrize("name,prec,thi,tlo,cls,bound", FORCED)
+def test_mixed_forced_class(g, ctx, name, prec, thi, tlo, cls, bound):
+    theta = (1.0, 0.1, 0.5)
+    x, y, z, ref = _problem(theta)
+    opts = g.gl_opts_default(precision=prec, tile=256, band=1, tol_hi=thi, tol_lo=tlo)
+    r = g.loglik_eval(ctx, dev(x), dev(y), dev(z), theta, opts)
+    assert r["status"] == g.GL_OK
+    st = g.gl_precision_stats(ctx)
+    nt = N_MIX // 256
+    assert st[cls]["tiles"] == nt * (nt - 1) // 2  # every off-band tile
+    assert st["fp64"]["tiles"] == nt                # diagonal tiles only
+    err = rel(r["loglik"], ref[0])
+    assert err <= bound, (name, err)
+    assert rel(r["logdet"], ref[1]) <= 10 * bound
+
+
+@pytest.mark.parametrize("theta", [(1.0, 0.1, 0.5), (1.0, 0.3, 1.0)])
+@pytest.mark.parametrize("prec", [1, 2])
+def test_mixed_default_bound(g, ctx, theta, prec):
+    x, y, z, ref = _problem(theta)
+    r = g.loglik_eval(ctx, dev(x), dev(y), dev(z), theta, g.gl_opts_default(precision=prec, tile=256))
+    assert r["status"] == g.GL_OK
+    assert rel(r["loglik"], ref[0]) <= 1e-4
+
+
+@pytest.mark.parametrize("tile", [128, 256, 384, 512])
+@pytest.mark.parametrize("prec", [1, 2])
+def test_mixed_all_tile_sizes_ragged(g, ctx, tile, prec):
+    n, theta = 1700, (1.3, 0.07, 1.5)
+    x, y = geoinputs.jittered_grid(n, 77)
+    z = geoinputs.normal_vector(n, 77)
+    ref = oracle.loglik(x, y, z, theta)
+    # every off-band tile in the FP32-grade class of the mode (FP32, or BF16x6)
+    thi = math.inf if prec == 1 else 0.0
+    r = g.loglik_eval(ctx, dev(x), dev(y), dev(z), theta,
+                      g.gl_opts_default(precision=prec, tile=tile, band=1, tol_hi=thi, tol_lo=0.0))
+    assert r["status"] == g.GL_OK
+    assert rel(r["loglik"], ref[0]) <= 1e-5
+
+
+def test_mixed_not_spd(g, ctx):
+    """A failed factorisation is reported, not hidden.  An exactly singular Σ
+    (a repeated location) is no use here: rounding decides whether its last
+    pivot comes out positive or not.  A very smooth, long-range Σ (ν = 2.5,
+    range 0.3, n = 2048: smallest eigenvalues far below the 4e-3 relative
+    perturbation of single bfloat16 products) with every off-band tile in
+    bfloat16 is indefinite after rounding, and must fail."""
+    x, y = geoinputs.jittered_grid(N_MIX, 5)
+    z = geoinputs.normal_vector(N_MIX, 5)
+    opts = g.gl_opts_default(precision=2, tile=256, band=1, tol_hi=math.inf, tol_lo=math.inf)
+    r = g.loglik_eval(ctx, dev(x), dev(y), dev(z), (1.0, 0.3, 2.5), opts)
+    assert r["status"] == g.GL_NOT_SPD and r["loglik"] == -math.inf and r["info"] > 0
+    # the context stays usable after a failure
+    ok = g.loglik_eval(ctx, dev(x), dev(y), dev(z), (1.0, 0.05, 0.5), g.gl_opts_default(precision=2, tile=256))
+    assert ok["status"] == g.GL_OK and math.isfinite(ok["loglik"])
+
+
+def test_mixed_factor_kriging(g, ctx):
+    theta = (1.0, 0.1, 0.5)
+    x, y, z, _ = _problem(theta)
+    xn, yn = geoinputs.uniform_points(50, 9)
+    ref, _ = oracle.krige(x, y, z, xn, yn, theta)
+    r = g.loglik_eval(ctx, dev(x), dev(y), dev(z), theta, g.gl_opts_default(precision=2, tile=256, keep_factor=1))
+    try:
+        out = g.krige_predict(ctx, r["factor"], dev(xn), dev(yn)).cpu().numpy()
+    finally:
+        g.gl_factor_release(ctx, r["factor"])
+    # prediction error against exact kriging, relative to the field's scale
+    assert np.max(np.abs(out - ref)) <= 1e-4 * np.max(np.abs(z))

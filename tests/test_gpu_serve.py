@@ -1,0 +1,230 @@
+"""GPU checks of the request queue (continuous batching of likelihood requests).
+
+A request served by the queue must give what a single evaluation with the same
+options and tile size gives: the fused launches run the same per-request code
+at each factorisation step, so FP64 results are compared bit for bit with
+loglik_eval at tile 256, alone and in a mix of sizes, precisions and failing
+requests, and against the oracle to the FP64 bound.
+"""
+import math
+import time
+
+import numpy as np
+import pytest
+
+import geoinputs
+import oracle
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def g():
+    import paper_1708_02835_amd as pkg
+    pkg.lib()
+    return pkg
+
+
+@pytest.fixture(scope="module")
+def ctx(g):
+    c = g.Context(0)
+    yield c
+    c.close()
+
+
+def dev(a):
+    return torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+
+
+def field(n, seed, dup=None):
+    x, y = geoinputs.jittered_grid(n, seed)
+    z = geoinputs.normal_vector(n, seed)
+    if dup is not None:
+        x[dup[1]], y[dup[1]] = x[dup[0]], y[dup[0]]
+    return x, y, z
+
+
+def register(g, ctx, x, y, z):
+    return g.gl_dataset_register(ctx, dev(x), dev(y), dev(z))
+
+
+def single(g, ctx, x, y, z, theta, **kw):
+    opts = g.gl_opts_default(**kw)
+    return g.loglik_eval(ctx, dev(x), dev(y), dev(z), theta, opts)
+
+
+def wait_all(g, q, tickets, timeout_s=60):
+    out = []
+    for t in tickets:
+        r = g.lq_wait(q, t, int(timeout_s * 1e6))
+        assert r is not None, "request timed out"
+        out.append(r)
+    return out
+
+
+THETAS = [(1.0, 0.1, 0.5), (1.3, 0.07, 1.5), (0.8, 0.15, 1.0)]
+
+
+def test_serve_single_request_matches_eval(g, ctx):
+    x, y, z = field(1000, 11)
+    theta = THETAS[0]
+    ds = register(g, ctx, x, y, z)
+    q = g.lq_create(ctx)
+    try:
+        r = wait_all(g, q, [g.lq_submit(q, ds, theta)])[0]
+    finally:
+        g.lq_destroy(q)
+        g.gl_dataset_release(ctx, ds)
+    ref = single(g, ctx, x, y, z, theta, tile=256)
+    assert r["status"] == g.GL_OK and r["tile"] == 256
+    assert r["loglik"] == ref["loglik"] and r["logdet"] == ref["logdet"] and r["quad"] == ref["quad"]
+    o = oracle.loglik(x, y, z, theta)
+    assert abs(r["loglik"] - o[0]) <= 1e-10 * abs(o[0])
+
+
+def test_serve_mix_bit_identical(g, ctx):
+    """Sizes 1..1800 (one tile, several tiles, ragged tails), three θ, one
+    NOT_SPD dataset, submitted together so the fused launches mix them."""
+    sizes = [1, 7, 256, 257, 600, 1000, 1800]
+    data, dss = [], []
+    for i, n in enumerate(sizes):
+        x, y, z = field(n, 100 + i)
+        data.append((x, y, z))
+        dss.append(register(g, ctx, x, y, z))
+    bad = field(700, 5, dup=(2, 300))
+    data.append(bad)
+    dss.append(register(g, ctx, *bad))
+    q = g.lq_create(ctx, g.lq_config_default(max_inflight=16))
+    jobs = []
+    try:
+        for rep in range(2):
+            for i, ds in enumerate(dss):
+                theta = THETAS[(i + rep) % len(THETAS)]
+                jobs.append((i, theta, g.lq_submit(q, ds, theta)))
+        res = wait_all(g, q, [t for _, _, t in jobs])
+        stats = g.lq_stats(q)
+    finally:
+        g.lq_destroy(q)
+        for ds in dss:
+            g.gl_dataset_release(ctx, ds)
+    assert stats["completed"] == len(jobs)
+    assert stats["peak_inflight"] > 1
+    for (i, theta, _), r in zip(jobs, res):
+        x, y, z = data[i]
+        ref = single(g, ctx, x, y, z, theta, tile=256)
+        if i == len(data) - 1:
+            assert r["status"] == g.GL_NOT_SPD and r["loglik"] == -math.inf
+            assert r["info"] == ref["info"] > 0
+            continue
+        assert r["status"] == g.GL_OK, (i, theta)
+        assert r["loglik"] == ref["loglik"], (len(x), theta, r["loglik"], ref["loglik"])
+        assert r["logdet"] == ref["logdet"] and r["quad"] == ref["quad"]
+
+
+def test_serve_routes_large_and_mixed_precision(g, ctx):
+    """n above small_n and mixed-precision requests run beside fused ones."""
+    small = field(900, 21)
+    large = field(2500, 22)
+    theta = THETAS[0]
+    ds_s, ds_l = register(g, ctx, *small), register(g, ctx, *large)
+    q = g.lq_create(ctx, g.lq_config_default(small_n=2000))
+    try:
+        ts = [g.lq_submit(q, ds_s, theta),
+              g.lq_submit(q, ds_l, theta),
+              g.lq_submit(q, ds_s, theta, g.gl_opts_default(precision=1, tile=128)),
+              g.lq_submit(q, ds_s, theta)]
+        res = wait_all(g, q, ts)
+    finally:
+        g.lq_destroy(q)
+        g.gl_dataset_release(ctx, ds_s)
+        g.gl_dataset_release(ctx, ds_l)
+    ref_s = single(g, ctx, *small, theta, tile=256)
+    ref_l = single(g, ctx, *large, theta)
+    ref_m = single(g, ctx, *small, theta, precision=1, tile=128)
+    assert res[0]["loglik"] == ref_s["loglik"] == res[3]["loglik"]
+    assert res[1]["loglik"] == ref_l["loglik"] and res[1]["tile"] == ref_l["tile"]
+    assert res[2]["loglik"] == ref_m["loglik"]
+
+
+def test_serve_budget_admission(g, ctx):
+    """A budget that holds two workspaces: everything still completes, the
+    bytes held never exceed it, and a request larger than it fails."""
+    n = 1500
+    need = g.gl_footprint_bytes(n, 256, 0)
+    sets = [field(n, 40 + i) for i in range(6)]
+    dss = [register(g, ctx, *s) for s in sets]
+    big = field(4000, 49)
+    ds_big = register(g, ctx, *big)
+    budget = 2 * need + need // 2
+    q = g.lq_create(ctx, g.lq_config_default(hbm_budget_bytes=budget, small_n=8000))
+    try:
+        ts = [g.lq_submit(q, ds, THETAS[1]) for ds in dss]
+        res = wait_all(g, q, ts)
+        r_big = wait_all(g, q, [g.lq_submit(q, ds_big, THETAS[1])])[0]
+        stats = g.lq_stats(q)
+    finally:
+        g.lq_destroy(q)
+        for ds in dss + [ds_big]:
+            g.gl_dataset_release(ctx, ds)
+    assert all(r["status"] == g.GL_OK for r in res)
+    assert 1 <= stats["peak_inflight"] <= 2
+    assert stats["peak_bytes"] <= budget
+    assert r_big["status"] == g.GL_ENOMEM
+    for s, r in zip(sets, res):
+        assert r["loglik"] == single(g, ctx, *s, THETAS[1], tile=256)["loglik"]
+
+
+def test_serve_cancel_and_release(g, ctx):
+    sets = [field(1200, 60 + i) for i in range(4)]
+    dss = [register(g, ctx, *s) for s in sets]
+    q = g.lq_create(ctx, g.lq_config_default(max_inflight=1, streams=1))
+    try:
+        ts = [g.lq_submit(q, ds, THETAS[0]) for ds in dss for _ in range(3)]
+        rc = g.lq_cancel(q, ts[-1])
+        res = wait_all(g, q, ts[:-1])
+        last = g.lq_wait(q, ts[-1], 0) if rc == g.GL_OK else None
+    finally:
+        g.lq_destroy(q)
+        for ds in dss:
+            g.gl_dataset_release(ctx, ds)
+    assert rc in (g.GL_OK, g.GL_EBUSY)
+    if rc == g.GL_OK:
+        assert last is None or last["status"] == g.GL_ECANCELED
+    for k, r in enumerate(res):
+        assert r["status"] == g.GL_OK
+        assert r["loglik"] == single(g, ctx, *sets[k // 3], THETAS[0], tile=256)["loglik"]
+
+
+def test_serve_many_clients_threads(g, ctx):
+    """Submission from several host threads while the scheduler runs."""
+    import threading
+    sets = [field(n, 80 + n) for n in (300, 800, 1300)]
+    dss = [register(g, ctx, *s) for s in sets]
+    refs = {(i, t): single(g, ctx, *sets[i], THETAS[t], tile=256)["loglik"]
+            for i in range(3) for t in range(3)}
+    q = g.lq_create(ctx)
+    errors = []
+
+    def client(cid):
+        try:
+            for k in range(6):
+                i, t = (cid + k) % 3, (cid * 2 + k) % 3
+                r = g.lq_wait(q, g.lq_submit(q, dss[i], THETAS[t]), int(60e6))
+                if r is None or r["status"] != g.GL_OK or r["loglik"] != refs[(i, t)]:
+                    errors.append((cid, k, r))
+                time.sleep(0.001 * (cid % 3))
+        except Exception as e:  # noqa: BLE001
+            errors.append((cid, repr(e)))
+
+    th = [threading.Thread(target=client, args=(c,)) for c in range(8)]
+    try:
+        for t in th:
+            t.start()
+        for t in th:
+            t.join(120)
+    finally:
+        g.lq_destroy(q)
+        for ds in dss:
+            g.gl_dataset_release(ctx, ds)
+    assert not errors, errors[:3]
