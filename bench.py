@@ -42,6 +42,12 @@ def parse():
     p.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision legs")
     p.add_argument("--theta-b", type=float, nargs=3, default=(1.0, 0.3, 1.0),
                    help="second parameter vector of the mixed-precision comparison")
+    p.add_argument("--no-serve", action="store_true", help="skip the serving leg")
+    p.add_argument("--serve-clients", type=int, default=64)
+    p.add_argument("--serve-evals", type=int, default=5, help="l(theta) requests per client")
+    p.add_argument("--serve-rate", type=float, default=400.0, help="client arrivals per second (Poisson)")
+    p.add_argument("--serve-think-ms", type=float, default=1.0,
+                   help="mean exponential pause of a client between a result and its next request")
     p.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                    help="only run device-to-device copies of MIB mebibytes (HBM counter calibration)")
     return p.parse_args()
@@ -126,6 +132,115 @@ def mixed_legs(g, ctx, xd, yd, ed, zd, theta, theta_b, args, res64, t64, log):
             log(f"mixed {label} {name}: {dt:.3f} s, x{t64b / dt:.2f}, rel err {leg[name]['rel_err_loglik']:.2e}")
         out[label] = leg
     return out
+
+
+def serving_leg(g, ctx, args, log):
+    """Many concurrent maximum-likelihood clients, each on its own synthetic
+    field (n uniform in 1,000..16,000, true θ drawn per client), arriving as a
+    Poisson process and each issuing a closed loop of l(θ) requests (the next
+    θ after the previous result and an exponential pause).  The same requests
+    are then evaluated one at a time with loglik_eval for comparison."""
+    import threading
+
+    import numpy as np
+    import torch
+
+    import geoinputs
+
+    clients, evals = args.serve_clients, args.serve_evals
+    fields = geoinputs.serving_fields(clients, args.seed)
+    rng = np.random.Generator(np.random.PCG64([args.seed, 77]))
+    data, dss, plans = [], [], []
+    t_s = time.perf_counter()
+    for c, f in enumerate(fields):
+        n, th = f["n"], f["theta"]
+        x, y = geoinputs.jittered_grid(n, args.seed + 1 + c)
+        e = geoinputs.normal_vector(n, args.seed + 1 + c)
+        xd, yd, ed = (torch.as_tensor(a).cuda() for a in (x, y, e))
+        z, info = g.synth_generate(ctx, xd, yd, ed, th)
+        if info != 0:
+            z = ed  # Σ(θ) not numerically SPD at the true θ: serve white noise
+        data.append((xd, yd, z))
+        dss.append(g.gl_dataset_register(ctx, xd, yd, z))
+        # proposals of a derivative-free optimiser around the true θ
+        steps = np.exp(rng.normal(0.0, [0.15, 0.15, 0.1], size=(evals, 3)))
+        plans.append([tuple(float(v) for v in np.array(th) * s_) for s_ in steps])
+    starts = geoinputs.arrival_times(clients, args.serve_rate, args.seed)
+    pauses = rng.exponential(args.serve_think_ms * 1e-3, size=(clients, evals))
+    log(f"serving: {clients} fields ready ({time.perf_counter() - t_s:.2f} s)")
+
+    q = g.lq_create(ctx, g.lq_config_default())
+    try:
+        # warm-up: one request per client, all at once (workspace pool, code objects)
+        for t in [g.lq_submit(q, ds, plans[c][0]) for c, ds in enumerate(dss)]:
+            g.lq_wait(q, t)
+        lat = [[] for _ in range(clients)]
+        res = [[None] * evals for _ in range(clients)]
+        errors = []
+        t0 = time.perf_counter()
+
+        def client(c):
+            try:
+                due = t0 + starts[c]
+                for k in range(evals):
+                    now = time.perf_counter()
+                    if due > now:
+                        time.sleep(due - now)
+                    s0 = time.perf_counter()
+                    r = g.lq_wait(q, g.lq_submit(q, dss[c], plans[c][k]))
+                    done = time.perf_counter()
+                    lat[c].append(done - s0)
+                    res[c][k] = r
+                    due = done + pauses[c][k]
+            except Exception as exc:  # noqa: BLE001
+                errors.append(repr(exc))
+
+        threads = [threading.Thread(target=client, args=(c,)) for c in range(clients)]
+        for th_ in threads:
+            th_.start()
+        for th_ in threads:
+            th_.join()
+        wall = time.perf_counter() - t0
+        stats = g.lq_stats(q)
+    finally:
+        g.lq_destroy(q)
+    if errors:
+        raise SystemExit(f"serving clients failed: {errors[:3]}")
+    all_lat = np.array([v for c in lat for v in c])
+    total = clients * evals
+    log(f"serving: {total} evals in {wall:.2f} s, p50 {np.median(all_lat) * 1e3:.1f} ms")
+
+    # the same requests, one at a time
+    opts = g.gl_opts_default()
+    for c in range(clients):
+        g.loglik_eval(ctx, *data[c], plans[c][0], opts)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    single = [[g.loglik_eval(ctx, *data[c], plans[c][k], opts) for k in range(evals)] for c in range(clients)]
+    torch.cuda.synchronize()
+    t_single = time.perf_counter() - t1
+    for ds in dss:
+        g.gl_dataset_release(ctx, ds)
+    worst, statuses = 0.0, {}
+    for c in range(clients):
+        for k in range(evals):
+            a, b = res[c][k], single[c][k]
+            statuses[str(a["status"])] = statuses.get(str(a["status"]), 0) + 1
+            if a["status"] == g.GL_OK and b["status"] == g.GL_OK:
+                worst = max(worst, abs(a["loglik"] - b["loglik"]) / abs(b["loglik"]))
+            elif a["status"] != b["status"]:
+                statuses["mismatch"] = statuses.get("mismatch", 0) + 1
+    ns = [f["n"] for f in fields]
+    log(f"serving: one at a time {total / t_single:.1f} evals/s")
+    return {"clients": clients, "evals_per_client": evals, "evals": total,
+            "n_range": [min(ns), max(ns)], "n_mean": float(np.mean(ns)),
+            "evals_per_s": total / wall, "p50_ms": float(np.percentile(all_lat, 50) * 1e3),
+            "p99_ms": float(np.percentile(all_lat, 99) * 1e3), "max_ms": float(all_lat.max() * 1e3),
+            "one_at_a_time_evals_per_s": total / t_single, "speedup_vs_one_at_a_time": t_single / wall,
+            "status_counts": statuses, "max_rel_diff_vs_one_at_a_time": worst,
+            "peak_inflight": stats["peak_inflight"], "peak_bytes": stats["peak_bytes"],
+            "fused_launches": stats["fused_launches"],
+            "arrivals": f"Poisson, {args.serve_rate:g} clients/s; pause {args.serve_think_ms:g} ms mean"}
 
 
 def main():
@@ -214,6 +329,8 @@ def main():
     }
     if not args.no_mixed:
         out["mixed"] = mixed_legs(g, ctx, xd, yd, ed, zd, theta, tuple(args.theta_b), args, res, step_s, log)
+    if not args.no_serve:
+        out["serving"] = serving_leg(g, ctx, args, log)
     ctx.close()
     if not args.no_cpu_baseline:
         log("timing the oracle on the host")

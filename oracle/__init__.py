@@ -10,10 +10,13 @@ Functions (each follows the passage named in ``oracle.c``):
 
 * ``bessel_k(nu, x)`` / ``bessel_k_scaled`` — K_ν from its integral form.
 * ``matern(r, theta)`` — Sec. 2.2 Eq. (2).
+* ``distance(x1, y1, x2, y2, metric, radius)`` — Euclidean (metric 0) or
+  great-circle by the haversine formula (metric 1, Sec. 7; x = longitude,
+  y = latitude in degrees).
 * ``cov_matrix`` / ``cov_symmetric`` — genDistanceMatrix + genCovMatrix.
 * ``cholesky``, ``forward``, ``backward``, ``trmv`` — unblocked dense kernels.
 * ``loglik`` — Alg. 2 / Eq. (1), returns (l, logdet, quad, info).
-* ``krige`` — Alg. 3 / Eq. (5).
+* ``krige`` — Alg. 3 / Eq. (5), optionally the variances of Eq. (4).
 * ``synth`` — Alg. 1, Z = L e.
 """
 from __future__ import annotations
@@ -53,17 +56,18 @@ def _load():
         "oracle_bessel_k": (D, [D, D]),
         "oracle_bessel_k_scaled": (D, [D, D]),
         "oracle_matern": (D, [D, D, D, D]),
-        "oracle_cov_matrix": (None, [P, P, I64, P, P, I64, D, D, D, P]),
-        "oracle_cov_symmetric": (None, [P, P, I64, D, D, D, P]),
+        "oracle_distance": (D, [ctypes.c_int, D, D, D, D, D]),
+        "oracle_cov_matrix": (None, [P, P, I64, P, P, I64, D, D, D, ctypes.c_int, D, P]),
+        "oracle_cov_symmetric": (None, [P, P, I64, D, D, D, ctypes.c_int, D, P]),
         "oracle_cholesky": (I64, [P, I64]),
         "oracle_forward": (None, [P, I64, P, P]),
         "oracle_backward": (None, [P, I64, P, P]),
         "oracle_trmv": (None, [P, I64, P, P]),
         "oracle_logdet": (D, [P, I64]),
         "oracle_dot": (D, [P, I64]),
-        "oracle_loglik": (I64, [P, P, P, I64, D, D, D, P, P]),
-        "oracle_krige": (I64, [P, P, P, I64, P, P, I64, D, D, D, P]),
-        "oracle_synth": (I64, [P, P, P, I64, D, D, D, P]),
+        "oracle_loglik": (I64, [P, P, P, I64, D, D, D, ctypes.c_int, D, P, P]),
+        "oracle_krige": (I64, [P, P, P, I64, P, P, I64, D, D, D, ctypes.c_int, D, P, P]),
+        "oracle_synth": (I64, [P, P, P, I64, D, D, D, ctypes.c_int, D, P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -95,18 +99,26 @@ def matern(r: float, theta) -> float:
     return _load().oracle_matern(float(r), t1, t2, t3)
 
 
-def cov_matrix(x1, y1, x2, y2, theta) -> np.ndarray:
+EUCLIDEAN, GREAT_CIRCLE = 0, 1
+EARTH_RADIUS_KM = 6371.0
+
+
+def distance(x1, y1, x2, y2, metric: int = EUCLIDEAN, radius: float = EARTH_RADIUS_KM) -> float:
+    return _load().oracle_distance(int(metric), float(radius), float(x1), float(y1), float(x2), float(y2))
+
+
+def cov_matrix(x1, y1, x2, y2, theta, metric: int = EUCLIDEAN, radius: float = EARTH_RADIUS_KM) -> np.ndarray:
     x1, y1, x2, y2 = map(_f64, (x1, y1, x2, y2))
     out = np.empty((x1.size, x2.size), dtype=np.float64)
     _load().oracle_cov_matrix(_p(x1), _p(y1), x1.size, _p(x2), _p(y2), x2.size,
-                              *map(float, theta), _p(out))
+                              *map(float, theta), int(metric), float(radius), _p(out))
     return out
 
 
-def cov_symmetric(x, y, theta) -> np.ndarray:
+def cov_symmetric(x, y, theta, metric: int = EUCLIDEAN, radius: float = EARTH_RADIUS_KM) -> np.ndarray:
     x, y = _f64(x), _f64(y)
     out = np.empty((x.size, x.size), dtype=np.float64)
-    _load().oracle_cov_symmetric(_p(x), _p(y), x.size, *map(float, theta), _p(out))
+    _load().oracle_cov_symmetric(_p(x), _p(y), x.size, *map(float, theta), int(metric), float(radius), _p(out))
     return out
 
 
@@ -148,29 +160,35 @@ def dot(w) -> float:
     return _load().oracle_dot(_p(w), w.size)
 
 
-def loglik(x, y, z, theta, return_factor: bool = False):
+def loglik(x, y, z, theta, return_factor: bool = False, metric: int = EUCLIDEAN,
+           radius: float = EARTH_RADIUS_KM):
     """Alg. 2: returns (l, logdet, quad, info) [, L]."""
     x, y, z = map(_f64, (x, y, z))
     out = np.zeros(3, dtype=np.float64)
     fac = np.empty((x.size, x.size), dtype=np.float64) if return_factor else None
-    info = _load().oracle_loglik(_p(x), _p(y), _p(z), x.size, *map(float, theta), _p(out),
-                                 _p(fac) if fac is not None else None)
+    info = _load().oracle_loglik(_p(x), _p(y), _p(z), x.size, *map(float, theta), int(metric), float(radius),
+                                 _p(out), _p(fac) if fac is not None else None)
     res = (float(out[0]), float(out[1]), float(out[2]), int(info))
     return (res + (fac,)) if return_factor else res
 
 
-def krige(x, y, z, xnew, ynew, theta) -> tuple[np.ndarray, int]:
-    """Alg. 3 / Eq. (5): returns (Z1, info)."""
+def krige(x, y, z, xnew, ynew, theta, return_variance: bool = False, metric: int = EUCLIDEAN,
+          radius: float = EARTH_RADIUS_KM):
+    """Alg. 3 / Eq. (5): returns (Z1, info), or (Z1, var, info) with the
+    prediction variances of Eq. (4)."""
     x, y, z, xnew, ynew = map(_f64, (x, y, z, xnew, ynew))
     out = np.zeros(xnew.size, dtype=np.float64)
+    var = np.zeros(xnew.size, dtype=np.float64) if return_variance else None
     info = _load().oracle_krige(_p(x), _p(y), _p(z), x.size, _p(xnew), _p(ynew), xnew.size,
-                                *map(float, theta), _p(out))
-    return out, int(info)
+                                *map(float, theta), int(metric), float(radius), _p(out),
+                                _p(var) if var is not None else None)
+    return (out, var, int(info)) if return_variance else (out, int(info))
 
 
-def synth(x, y, e, theta) -> tuple[np.ndarray, int]:
+def synth(x, y, e, theta, metric: int = EUCLIDEAN, radius: float = EARTH_RADIUS_KM) -> tuple[np.ndarray, int]:
     """Alg. 1: returns (Z = L e, info)."""
     x, y, e = map(_f64, (x, y, e))
     z = np.zeros_like(e)
-    info = _load().oracle_synth(_p(x), _p(y), _p(e), x.size, *map(float, theta), _p(z))
+    info = _load().oracle_synth(_p(x), _p(y), _p(e), x.size, *map(float, theta), int(metric), float(radius),
+                                _p(z))
     return z, int(info)

@@ -23,8 +23,14 @@
  *   - log|Σ| = 2 Σ_i log L_ii (Sec. 5.1) and the dot product wᵀw (Alg. 2),
  *     both with Neumaier-compensated summation.
  *   - l(θ) = -n/2 log(2π) - ½ log|Σ| - ½ wᵀw (Sec. 2 Eq. (1), Alg. 2 last step).
- *   - Kriging Z1 = Σ12 Σ22⁻¹ Z2 (Sec. 2.3 Eq. (5), Alg. 3).
+ *   - Kriging Z1 = Σ12 Σ22⁻¹ Z2 (Sec. 2.3 Eq. (5), Alg. 3), and the
+ *     prediction variance, the diagonal of Σ11 - Σ12 Σ22⁻¹ Σ21 (Eq. (4)),
+ *     as θ1 - ‖L⁻¹ σ_k‖² with σ_k the k-th column of Σ21.
  *   - Synthetic field Z = L e (Sec. 5.3, Alg. 1).
+ *   - Distances: Euclidean in the plane (Sec. 2), or great-circle distance on
+ *     a sphere of radius ρ by the haversine formula (Sec. 7, used for the
+ *     longitude/latitude data): hav(d/ρ) = hav(Δφ) + cos φ1 cos φ2 hav(Δλ),
+ *     hav(a) = sin²(a/2), with x = longitude and y = latitude in degrees.
  *
  * Matrices are dense row-major n×n arrays owned by the caller.
  */
@@ -74,32 +80,51 @@ double oracle_matern(double r, double theta1, double theta2, double theta3)
     return pref * exp(theta3 * log(x) - x) * oracle_bessel_k_scaled(theta3, x);
 }
 
-/* Euclidean distance between two points of the plane (Sec. 2, d = 2). */
-static double dist2d(double x1, double y1, double x2, double y2)
+/* ---------------------------------------------------------- distances ---- */
+
+/* metric 0: Euclidean distance in the plane (Sec. 2, d = 2).
+ * metric 1: great-circle distance on a sphere of radius `radius` (Sec. 7),
+ *           x = longitude, y = latitude, both in degrees; the haversine
+ *           relation is solved for d as d = 2 ρ asin(√h), with h clamped to
+ *           [0, 1] against rounding. */
+double oracle_distance(int metric, double radius, double x1, double y1, double x2, double y2)
 {
-    double dx = x1 - x2, dy = y1 - y2;
-    return sqrt(dx * dx + dy * dy);
+    if (metric == 0) {
+        double dx = x1 - x2, dy = y1 - y2;
+        return sqrt(dx * dx + dy * dy);
+    }
+    const double deg = M_PI / 180.0;
+    double phi1 = y1 * deg, phi2 = y2 * deg;
+    double dphi = phi2 - phi1, dlam = (x2 - x1) * deg;
+    double s1 = sin(0.5 * dphi), s2 = sin(0.5 * dlam);
+    double h = s1 * s1 + cos(phi1) * cos(phi2) * s2 * s2;
+    if (h < 0.0) h = 0.0;
+    if (h > 1.0) h = 1.0;
+    return 2.0 * radius * asin(sqrt(h));
 }
 
 /* Dense n1×n2 row-major covariance between point sets 1 and 2
  * (genDistanceMatrix followed by genCovMatrix in Alg. 1-3). */
 void oracle_cov_matrix(const double *x1, const double *y1, int64_t n1,
                        const double *x2, const double *y2, int64_t n2,
-                       double theta1, double theta2, double theta3, double *out)
+                       double theta1, double theta2, double theta3,
+                       int metric, double radius, double *out)
 {
     for (int64_t i = 0; i < n1; ++i)
         for (int64_t j = 0; j < n2; ++j)
-            out[i * n2 + j] = oracle_matern(dist2d(x1[i], y1[i], x2[j], y2[j]),
+            out[i * n2 + j] = oracle_matern(oracle_distance(metric, radius, x1[i], y1[i], x2[j], y2[j]),
                                             theta1, theta2, theta3);
 }
 
 /* Symmetric n×n covariance: lower triangle evaluated, mirrored above. */
 void oracle_cov_symmetric(const double *x, const double *y, int64_t n,
-                          double theta1, double theta2, double theta3, double *out)
+                          double theta1, double theta2, double theta3,
+                          int metric, double radius, double *out)
 {
     for (int64_t i = 0; i < n; ++i)
         for (int64_t j = 0; j <= i; ++j) {
-            double v = oracle_matern(dist2d(x[i], y[i], x[j], y[j]), theta1, theta2, theta3);
+            double v = oracle_matern(oracle_distance(metric, radius, x[i], y[i], x[j], y[j]),
+                                     theta1, theta2, theta3);
             out[i * n + j] = v;
             out[j * n + i] = v;
         }
@@ -203,12 +228,12 @@ double oracle_dot(const double *w, int64_t n)
  * When l_out is not NULL the factor (row-major n×n) is copied there.
  */
 int64_t oracle_loglik(const double *x, const double *y, const double *z, int64_t n,
-                      double theta1, double theta2, double theta3, double *out,
-                      double *l_out)
+                      double theta1, double theta2, double theta3, int metric, double radius,
+                      double *out, double *l_out)
 {
     double *a = (double *)malloc((size_t)n * (size_t)n * sizeof(double));
     double *w = (double *)malloc((size_t)n * sizeof(double));
-    oracle_cov_symmetric(x, y, n, theta1, theta2, theta3, a);
+    oracle_cov_symmetric(x, y, n, theta1, theta2, theta3, metric, radius, a);
     int64_t info = oracle_cholesky(a, n);
     if (info != 0) {
         out[0] = -INFINITY;
@@ -230,41 +255,54 @@ int64_t oracle_loglik(const double *x, const double *y, const double *z, int64_t
 
 /*
  * Kriging, Sec. 2.3 Eq. (5) with Alg. 3: X = Σ22⁻¹ Z2 through the Cholesky
- * factor (forward then backward substitution), then Z1 = Σ12 X.
- * Returns the Cholesky info.
+ * factor (forward then backward substitution), then Z1 = Σ12 X.  When var is
+ * not NULL, the prediction variances of Eq. (4): var_k = θ1 - uᵀu with
+ * L u = σ_k, σ_k the covariances between new point k and the n observed
+ * points (Σ11 has θ1 on its diagonal).  Returns the Cholesky info.
  */
 int64_t oracle_krige(const double *x, const double *y, const double *z, int64_t n,
                      const double *xn, const double *yn, int64_t m,
-                     double theta1, double theta2, double theta3, double *znew)
+                     double theta1, double theta2, double theta3, int metric, double radius,
+                     double *znew, double *var)
 {
     double *a = (double *)malloc((size_t)n * (size_t)n * sizeof(double));
     double *w = (double *)malloc((size_t)n * sizeof(double));
     double *v = (double *)malloc((size_t)n * sizeof(double));
-    oracle_cov_symmetric(x, y, n, theta1, theta2, theta3, a);
+    double *sk = (double *)malloc((size_t)n * sizeof(double));
+    oracle_cov_symmetric(x, y, n, theta1, theta2, theta3, metric, radius, a);
     int64_t info = oracle_cholesky(a, n);
     if (info == 0) {
         oracle_forward(a, n, z, w);
         oracle_backward(a, n, w, v);
         for (int64_t k = 0; k < m; ++k) {
             double s = 0.0;
-            for (int64_t j = 0; j < n; ++j)
-                s += oracle_matern(dist2d(xn[k], yn[k], x[j], y[j]), theta1, theta2, theta3) * v[j];
+            for (int64_t j = 0; j < n; ++j) {
+                sk[j] = oracle_matern(oracle_distance(metric, radius, xn[k], yn[k], x[j], y[j]),
+                                      theta1, theta2, theta3);
+                s += sk[j] * v[j];
+            }
             znew[k] = s;
+            if (var) {
+                oracle_forward(a, n, sk, w);
+                var[k] = theta1 - oracle_dot(w, n);
+            }
         }
     }
     free(a);
     free(w);
     free(v);
+    free(sk);
     return info;
 }
 
 /* Synthetic measurements, Sec. 5.3 Alg. 1: Σ(θ) = L Lᵀ, Z = L e.
  * Returns the Cholesky info. */
 int64_t oracle_synth(const double *x, const double *y, const double *e, int64_t n,
-                     double theta1, double theta2, double theta3, double *z)
+                     double theta1, double theta2, double theta3, int metric, double radius,
+                     double *z)
 {
     double *a = (double *)malloc((size_t)n * (size_t)n * sizeof(double));
-    oracle_cov_symmetric(x, y, n, theta1, theta2, theta3, a);
+    oracle_cov_symmetric(x, y, n, theta1, theta2, theta3, metric, radius, a);
     int64_t info = oracle_cholesky(a, n);
     if (info == 0) oracle_trmv(a, n, e, z);
     free(a);

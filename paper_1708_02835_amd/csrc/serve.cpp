@@ -183,33 +183,31 @@ bool batch_eligible(const lq_queue *q, const Request *r)
            (r->o.tile == 0 || r->o.tile == TICK_B) && r->ds->n <= q->cfg.small_n;
 }
 
-// A workspace for n points from the pool (grown when too small), or a new one.
+// A workspace for n points: the smallest pooled one that is large enough,
+// else a new one (growing a pooled workspace would free memory, which waits
+// for the device; smaller pooled workspaces stay for smaller requests).
 int take_work(lq_queue *q, int64_t n, Work *&out)
 {
-    Work *best = nullptr;
-    size_t need = work_bytes(n, TICK_B, GL_FP64);
+    const size_t need = work_bytes(n, TICK_B, GL_FP64);
+    size_t pick = q->pool.size();
     for (size_t i = 0; i < q->pool.size(); ++i)
-        if (q->pool[i]->bytes() >= need) {
-            best = q->pool[i];
-            q->pool.erase(q->pool.begin() + i);
-            break;
-        }
-    if (!best) {
-        if (!q->pool.empty()) {
-            best = q->pool.back();
-            q->pool.pop_back();
-        } else {
-            best = new Work();
-        }
+        if (q->pool[i]->bytes() >= need && (pick == q->pool.size() || q->pool[i]->bytes() < q->pool[pick]->bytes()))
+            pick = i;
+    Work *w;
+    if (pick < q->pool.size()) {
+        w = q->pool[pick];
+        q->pool.erase(q->pool.begin() + pick);
+    } else {
+        w = new Work();
     }
-    int rc = best->ensure(q->ctx, n, TICK_B, GL_FP64);
+    const int rc = w->ensure(q->ctx, n, TICK_B, GL_FP64);
     if (rc != GL_OK) {
-        q->ctx->used -= best->bytes();
-        best->release();
-        delete best;
+        q->ctx->used -= w->bytes();
+        w->release();
+        delete w;
         return rc;
     }
-    out = best;
+    out = w;
     return GL_OK;
 }
 

@@ -1,0 +1,183 @@
+"""GPU checks at full size, where the oracle cannot factor the whole matrix.
+
+n = 40,000 (a 200 x 200 jittered grid) for θ = (1, 0.1, 0.5) and
+(1, 0.03, 1.5), with 1,000 held-out kriging locations.  The oracle computes
+single outputs one by one; everything else is a property that holds at any
+size:
+
+* factor entries: for sampled pairs (i, j), row i of L dotted with row j of L
+  must equal the oracle's C(||s_i - s_j||) within the backward-error bound of
+  Cholesky in binary64, |L Lᵀ - Σ| <= γ_{n+1} |L| |Lᵀ| elementwise, with
+  γ_m = m u / (1 - m u), u = 2⁻⁵³ (Higham, Accuracy and Stability of
+  Numerical Algorithms, Thm. 10.3);
+* log|Σ| = 2 Σ log L_ii, summed on the host from the factor's diagonal;
+* l does not depend on the tile size or on the order of the locations: four
+  binary64 evaluations (tiles 256, 384, 512 and tile 512 in Morton order)
+  agree to the FP64 parity bound;
+* kriging at observed locations returns the observations (Eq. 5 with
+  s_new = s_j gives Σ_j·ᵀ Σ⁻¹ Z = Z_j);
+* held-out predictions from the FP64 factor are unchanged when the factor is
+  taken at another tile size.
+
+The mixed-precision case at n = 150,000 compares BF16 off-band kriging with
+FP64 kriging and with the simulated truth at 5,000 held-out locations.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import geoinputs
+import oracle
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+U = 2.0 ** -53
+
+
+@pytest.fixture(scope="module")
+def g():
+    import paper_1708_02835_amd as pkg
+    pkg.lib()
+    return pkg
+
+
+def dev(a):
+    return torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+
+
+def gamma(m):
+    return m * U / (1.0 - m * U)
+
+
+N40 = 40000
+THETAS40 = [(1.0, 0.1, 0.5), (1.0, 0.03, 1.5)]
+
+
+@pytest.fixture(scope="module")
+def field40(g):
+    x, y = geoinputs.jittered_grid(N40, 2)
+    e = geoinputs.normal_vector(N40, 2)
+    xn, yn = geoinputs.uniform_points(1000, 2)
+    return x, y, e, xn, yn
+
+
+@pytest.mark.parametrize("theta", THETAS40)
+def test_n40000_factor_logdet_invariance_kriging(g, field40, theta):
+    x, y, e, xn, yn = field40
+    ctx = g.Context(0)
+    factor = None
+    try:
+        xd, yd, ed = dev(x), dev(y), dev(e)
+        zd, info = g.synth_generate(ctx, xd, yd, ed, theta)
+        assert info == 0
+        z = zd.cpu().numpy()
+        evals = {}
+        for tile, reorder in ((256, 0), (384, 0), (512, 1)):
+            evals[(tile, reorder)] = g.loglik_eval(ctx, xd, yd, zd, theta,
+                                                   g.gl_opts_default(tile=tile, reorder=reorder))
+        r = g.loglik_eval(ctx, xd, yd, zd, theta, g.gl_opts_default(tile=512, keep_factor=1))
+        factor = r["factor"]
+        evals[(512, 0)] = r
+        ls = np.array([v["loglik"] for v in evals.values()])
+        assert all(v["status"] == g.GL_OK for v in evals.values())
+        spread = (ls.max() - ls.min()) / abs(ls).max()
+        print(f"theta={theta} l={ls} spread={spread:.2e}")
+        assert spread <= 1e-10
+
+        # kriging: interpolation at observed points, and held-out predictions
+        obs = np.random.Generator(np.random.PCG64(5)).choice(N40, 500, replace=False)
+        at_obs = g.krige_predict(ctx, factor, dev(x[obs]), dev(y[obs])).cpu().numpy()
+        interp = np.max(np.abs(at_obs - z[obs])) / np.max(np.abs(z))
+        pred512 = g.krige_predict(ctx, factor, dev(xn), dev(yn)).cpu().numpy()
+        print(f"interpolation error {interp:.2e}")
+        assert interp <= 1e-6
+
+        # factor entries against the oracle, and log|Σ| from the diagonal
+        dense = g.gl_factor_to_dense(ctx, factor)  # Lᵀ, row-major
+        rng = np.random.Generator(np.random.PCG64(9))
+        ii = np.concatenate([rng.integers(0, N40, 150), np.arange(N40 - 50, N40)])
+        jj = np.concatenate([rng.integers(0, N40, 150), rng.integers(0, N40, 50)])
+        jj[:20] = ii[:20]  # diagonal entries too
+        Li = dense[:, torch.as_tensor(ii).cuda()].T.cpu().numpy()
+        Lj = dense[:, torch.as_tensor(jj).cuda()].T.cpu().numpy()
+        diag = torch.diagonal(dense).cpu().numpy()
+        del dense
+        torch.cuda.empty_cache()
+        worst = 0.0
+        for k in range(ii.size):
+            i, j = int(ii[k]), int(jj[k])
+            got = math.fsum(Li[k] * Lj[k])
+            want = oracle.matern(math.sqrt((x[i] - x[j]) ** 2 + (y[i] - y[j]) ** 2), theta)
+            bound = gamma(N40 + 1) * float(np.abs(Li[k]) @ np.abs(Lj[k]))
+            worst = max(worst, abs(got - want) / bound)
+        print(f"worst |LLT - Sigma| / backward-error bound = {worst:.3f}")
+        assert worst <= 1.0
+        logdet = 2.0 * math.fsum(np.log(diag))
+        assert abs(logdet - r["logdet"]) <= 1e-12 * abs(logdet)
+    finally:
+        if factor is not None:
+            g.gl_factor_release(ctx, factor)
+        ctx.close()
+
+    # held-out predictions at another tile size
+    ctx = g.Context(0)
+    try:
+        r = g.loglik_eval(ctx, dev(x), dev(y), dev(z), theta, g.gl_opts_default(tile=256, keep_factor=1))
+        try:
+            pred256 = g.krige_predict(ctx, r["factor"], dev(xn), dev(yn)).cpu().numpy()
+        finally:
+            g.gl_factor_release(ctx, r["factor"])
+    finally:
+        ctx.close()
+    diff = np.max(np.abs(pred256 - pred512)) / np.max(np.abs(z))
+    print(f"held-out prediction change across tile sizes {diff:.2e}")
+    assert diff <= 1e-6
+
+
+N150 = 150000
+HELD = 5000
+
+
+def test_n150000_mixed_bf16_kriging(g):
+    """BF16 off-band factor (FP64 band, POTRF and log-det) reused to krige
+    5,000 held-out locations; Z simulated jointly at all 155,000 points."""
+    theta = (1.0, 0.1, 0.5)
+    nall = N150 + HELD
+    x, y = geoinputs.jittered_grid(nall, 150)
+    e = geoinputs.normal_vector(nall, 150)
+    held = np.random.Generator(np.random.PCG64(151)).choice(nall, HELD, replace=False)
+    keep = np.setdiff1d(np.arange(nall), held)
+    ctx = g.Context(0)
+    try:
+        zall, info = g.synth_generate(ctx, dev(x), dev(y), dev(e), theta)
+        assert info == 0
+        zall = zall.cpu().numpy()
+    finally:
+        ctx.close()
+    torch.cuda.empty_cache()
+    xo, yo, zo = dev(x[keep]), dev(y[keep]), dev(zall[keep])
+    xh, yh, truth = dev(x[held]), dev(y[held]), zall[held]
+    preds, ls = {}, {}
+    for name, prec in (("fp64", 0), ("bf16", 2)):
+        ctx = g.Context(0)
+        try:
+            r = g.loglik_eval(ctx, xo, yo, zo, theta, g.gl_opts_default(precision=prec, keep_factor=1))
+            assert r["status"] == g.GL_OK
+            ls[name] = r["loglik"]
+            try:
+                preds[name] = g.krige_predict(ctx, r["factor"], xh, yh).cpu().numpy()
+            finally:
+                g.gl_factor_release(ctx, r["factor"])
+        finally:
+            ctx.close()
+        torch.cuda.empty_cache()
+    mse64 = float(np.mean((preds["fp64"] - truth) ** 2))
+    mse16 = float(np.mean((preds["bf16"] - truth) ** 2))
+    dmse = float(np.mean((preds["bf16"] - preds["fp64"]) ** 2))
+    rel_l = abs(ls["bf16"] - ls["fp64"]) / abs(ls["fp64"])
+    print(f"l rel err {rel_l:.2e}; MSE vs truth fp64 {mse64:.4e} bf16 {mse16:.4e}; MSE bf16 vs fp64 {dmse:.3e}")
+    assert rel_l <= 1e-4
+    assert dmse <= 1e-6 * float(np.var(truth))
+    assert abs(mse16 - mse64) <= 0.01 * mse64

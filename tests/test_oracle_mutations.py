@@ -35,6 +35,12 @@ MUTANTS = {
     "krige_backward_skipped": ("oracle_backward(a, n, w, v);", "memcpy(v, w, (size_t)n * sizeof(double));"),
     "trmv_upper": ("for (int64_t k = 0; k <= i; ++k) s += l[i * n + k] * e[k];",
                    "for (int64_t k = 0; k <= i; ++k) s += l[k * n + i] * e[k];"),
+    "gcd_cos_twice": ("cos(phi1) * cos(phi2)", "cos(phi1) * cos(phi1)"),
+    "gcd_full_angle": ("double s1 = sin(0.5 * dphi)", "double s1 = sin(dphi)"),
+    "gcd_no_degrees": ("const double deg = M_PI / 180.0;", "const double deg = 1.0;"),
+    "gcd_no_factor_two": ("return 2.0 * radius * asin(sqrt(h));", "return radius * asin(sqrt(h));"),
+    "variance_sign": ("var[k] = theta1 - oracle_dot(w, n);", "var[k] = theta1 + oracle_dot(w, n);"),
+    "variance_backward": ("oracle_forward(a, n, sk, w);", "oracle_backward(a, n, sk, w);"),
 }
 
 
@@ -54,11 +60,14 @@ def _build(tmp_path, name, mutation):
     lib.oracle_matern.restype = D
     lib.oracle_matern.argtypes = [D, D, D, D]
     lib.oracle_loglik.restype = I64
-    lib.oracle_loglik.argtypes = [P, P, P, I64, D, D, D, P, P]
+    INT = ctypes.c_int
+    lib.oracle_distance.restype = D
+    lib.oracle_distance.argtypes = [INT, D, D, D, D, D]
+    lib.oracle_loglik.argtypes = [P, P, P, I64, D, D, D, INT, D, P, P]
     lib.oracle_krige.restype = I64
-    lib.oracle_krige.argtypes = [P, P, P, I64, P, P, I64, D, D, D, P]
+    lib.oracle_krige.argtypes = [P, P, P, I64, P, P, I64, D, D, D, INT, D, P, P]
     lib.oracle_synth.restype = I64
-    lib.oracle_synth.argtypes = [P, P, P, I64, D, D, D, P]
+    lib.oracle_synth.argtypes = [P, P, P, I64, D, D, D, INT, D, P]
     return lib
 
 
@@ -92,13 +101,13 @@ def _pins(lib):
     ref_q = float(np.sum((u.T @ z) ** 2 / lam))
     ref_l = -0.5 * n * math.log(2 * math.pi) - 0.5 * ref_ld - 0.5 * ref_q
     out = np.zeros(3)
-    lib.oracle_loglik(_p(x), _p(y), _p(z), n, *theta, _p(out), None)
+    lib.oracle_loglik(_p(x), _p(y), _p(z), n, *theta, 0, 1.0, _p(out), None)
     if not abs(out[0] - ref_l) <= 1e-9 * abs(ref_l):
         failed.append("loglik_eig")
     # kriging vs dense solve
     xn, yn = geoinputs.uniform_points(4, 7)
-    zn = np.zeros(4)
-    lib.oracle_krige(_p(x), _p(y), _p(z), n, _p(xn), _p(yn), 4, *theta, _p(zn))
+    zn, vn = np.zeros(4), np.zeros(4)
+    lib.oracle_krige(_p(x), _p(y), _p(z), n, _p(xn), _p(yn), 4, *theta, 0, 1.0, _p(zn), _p(vn))
     s12 = np.empty((4, n))
     for k in range(4):
         for j in range(n):
@@ -107,10 +116,27 @@ def _pins(lib):
             s12[k, j] = theta[0] * (1 + rr) * math.exp(-rr)
     if not np.allclose(zn, s12 @ np.linalg.solve(a, z), rtol=1e-8, atol=1e-10):
         failed.append("krige_dense")
+    # prediction variance (Eq. 4) vs dense solve
+    dense_var = theta[0] - np.einsum("kj,jk->k", s12, np.linalg.solve(a, s12.T))
+    if not np.allclose(vn, dense_var, rtol=1e-8, atol=1e-12):
+        failed.append("variance_dense")
+    # great-circle distance: equator, meridian, 3-D chord
+    R = 6371.0
+    if abs(lib.oracle_distance(1, R, 10.0, 0.0, 40.0, 0.0) - R * math.pi / 6) > 1e-9:
+        failed.append("gcd_equator")
+    if abs(lib.oracle_distance(1, R, -90.0, 10.0, -90.0, 55.0) - R * math.pi / 4) > 1e-9:
+        failed.append("gcd_meridian")
+    for (l1, p1, l2, p2) in [(-95.0, 33.0, -88.5, 41.2), (-99.0, 44.0, -86.0, 30.5)]:
+        u = [np.array([math.cos(math.radians(p)) * math.cos(math.radians(l)),
+                       math.cos(math.radians(p)) * math.sin(math.radians(l)), math.sin(math.radians(p))])
+             for l, p in ((l1, p1), (l2, p2))]
+        want = 2 * R * math.asin(np.linalg.norm(u[0] - u[1]) / 2)
+        if abs(lib.oracle_distance(1, R, l1, p1, l2, p2) - want) > 1e-9 * want:
+            failed.append("gcd_chord")
     # synth vs LAPACK factor
     e = geoinputs.normal_vector(n, 8)
     zs = np.zeros(n)
-    lib.oracle_synth(_p(x), _p(y), _p(e), n, *theta, _p(zs))
+    lib.oracle_synth(_p(x), _p(y), _p(e), n, *theta, 0, 1.0, _p(zs))
     if not np.allclose(zs, sla.cholesky(a, lower=True) @ e, rtol=1e-9, atol=1e-10):
         failed.append("synth_lapack")
     return failed
