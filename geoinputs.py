@@ -4,7 +4,7 @@ This module holds only random draws and the placement of locations; it does no
 covariance, factorisation or likelihood arithmetic.  Both the HIP path and the
 CPU oracle receive exactly the arrays produced here.
 
-Recipes (Sec. 6.1 of the paper describes the synthetic workload):
+Recipes (Sec. 7.1 of the paper describes the synthetic workload):
 
 * ``jittered_grid(n, seed)`` — irregular locations in the unit square: a g×g
   grid with g = ceil(sqrt(n)), each point moved by independent U(-0.4, 0.4)

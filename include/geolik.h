@@ -62,13 +62,22 @@ typedef enum {
  * the diagonal tiles, POTRF, TRSM, the solve and log|Σ| stay binary64; the
  * trailing products of off-band tiles (i, j) run at a precision chosen from
  * the normalised tile norm ν_ij = ||Σ_ij||_F / sqrt(||Σ_ii||_F ||Σ_jj||_F):
- *   GL_MIXED_FP32: FP32 products, or binary64 when ν_ij > tol_hi
- *                  (tol_hi < 0: +infinity, i.e. every off-band tile FP32);
+ *   both modes:    binary64 when ν_ij > tol_64 (strongly correlated tiles,
+ *                  whose Schur complements cancel most);
+ *   GL_MIXED_FP32: FP32 products otherwise;
  *   GL_MIXED_BF16: bfloat16 products with FP32 accumulation, operands split
  *                  in three parts (about FP32 accuracy) when ν_ij > tol_hi,
- *                  two parts when tol_lo < ν_ij <= tol_hi, one part below
- *                  (tol_hi < 0: 1e-2, tol_lo < 0: 1e-4).
- * Tiles with i - j < band stay binary64. */
+ *                  two parts when tol_lo < ν_ij <= tol_hi, one part below.
+ * Negative thresholds take the defaults tol_64 = 0.3, tol_hi = 1e-2,
+ * tol_lo = 1e-4.
+ * Tiles with i - j < band stay binary64.
+ *
+ * Distance (Sec. 2 and Sec. 7.4): metric GL_EUCLIDEAN uses r = ||s_i - s_j||
+ * in the plane; GL_GREAT_CIRCLE reads x as longitude and y as latitude in
+ * degrees and uses the great-circle distance on a sphere of the given radius
+ * (haversine formula), in the radius' unit (θ2 in the same unit). */
+enum { GL_EUCLIDEAN = 0, GL_GREAT_CIRCLE = 1 };
+
 typedef struct {
     int32_t precision;   /* gl_precision */
     int32_t tile;        /* tile size b: 0 = automatic, else 128, 256, 384 or 512 */
@@ -77,9 +86,11 @@ typedef struct {
     int32_t reorder;     /* -1: automatic (Morton order for the mixed modes, input order for
                             GL_FP64); 0: input order; 1: Morton order.  l(θ) does not depend
                             on the order; kept factors are in the order used. */
-    int32_t reserved;    /* 0 */
-    double tol_hi;       /* mixed modes: see above (negative: mode default) */
-    double tol_lo;       /* GL_MIXED_BF16: see above (negative: mode default) */
+    int32_t metric;      /* GL_EUCLIDEAN (default) or GL_GREAT_CIRCLE */
+    double tol_hi;       /* GL_MIXED_BF16: see above (negative: default) */
+    double tol_lo;       /* GL_MIXED_BF16: see above (negative: default) */
+    double radius;       /* GL_GREAT_CIRCLE: sphere radius (> 0; default 6371, the Earth in km) */
+    double tol_64;       /* mixed modes: see above (negative: default) */
 } gl_opts;
 
 /* Result of one likelihood evaluation, host memory. */
@@ -119,14 +130,16 @@ size_t gl_footprint_bytes(int64_t n, int32_t tile, int32_t precision);
 
 /*
  * Matérn covariance between point sets 1 and 2, Sec. 2.2 Eq. (2) with the
- * Euclidean distance r = ||s1_i - s2_j|| (genDistanceMatrix + genCovMatrix
- * of Alg. 1-3, the distance matrix is never stored).  r == 0 gives θ1.
+ * distance of opts->metric (NULL opts: Euclidean; other fields ignored)
+ * (genDistanceMatrix + genCovMatrix of Alg. 1-3, the distance matrix is never
+ * stored).  r == 0 gives θ1.
  * Output: column-major n1×n2, out[i + j*ld], ld >= n1; the caller owns it.
- * Errors: GL_EINVAL for n1 < 1, n2 < 1, ld < n1, NULL pointers or bad θ.
+ * Errors: GL_EINVAL for n1 < 1, n2 < 1, ld < n1, NULL pointers, bad θ or a
+ * bad metric/radius.
  */
 int matern_generate(gl_context *ctx, const double *x1, const double *y1, int64_t n1,
                     const double *x2, const double *y2, int64_t n2, gl_theta theta,
-                    double *out, int64_t ld, void *stream);
+                    const gl_opts *opts, double *out, int64_t ld, void *stream);
 
 /*
  * l(θ) = -n/2 log 2π - ½ log|Σ(θ)| - ½ Zᵀ Σ(θ)⁻¹ Z, Sec. 2 Eq. (1), computed
@@ -145,12 +158,34 @@ int loglik_eval(gl_context *ctx, const double *x, const double *y, const double 
  * Kriging, Sec. 2.3 Eq. (5) and Alg. 3: Z1 = Σ12 Σ22⁻¹ Z2 at m new locations,
  * reusing the factor L of a previous loglik_eval (keep_factor = 1) and its
  * forward solution w: X = L⁻ᵀ w, then Z1_k = Σ_j C(||s_new,k - s_j||) X_j with
- * Σ12 generated on the fly and never stored.  Output znew: m doubles (device,
- * caller-owned).  Asynchronous on `stream`.
- * Errors: GL_EINVAL for a NULL factor, m < 1 or NULL pointers.
+ * Σ12 generated on the fly and never stored, with the factor's distance.
+ * Output znew: m doubles (device, caller-owned).
+ * var (may be NULL): the prediction variances, the diagonal of the
+ * conditional covariance of Eq. (4), var_k = θ1 - ||L⁻¹ σ_k||² with σ_k the
+ * covariances between new location k and the n observed ones; the m
+ * right-hand sides are solved together on the matrix cores, 512 at a time.
+ * Asynchronous on `stream`.
+ * Errors: GL_EINVAL for a NULL factor, m < 1 or NULL pointers; GL_ENOMEM
+ * when the variance workspace (n·min(m, 512) doubles) does not fit.
  */
 int krige_predict(gl_context *ctx, gl_factor *factor, const double *xnew, const double *ynew,
-                  int64_t m, double *znew, void *stream);
+                  int64_t m, double *znew, double *var, void *stream);
+
+/*
+ * k-fold cross-validation of kriging (Sec. 7.3: the prediction MSE
+ * of held-out measurements).  fold_h (host, n values in
+ * 0..k-1, drawn by the caller) assigns each location to a fold; for each fold
+ * f the locations outside it are factored (loglik_eval with keep_factor, the
+ * other opts as given), the fold's measurements are predicted by Eq. (5), and
+ * mse_h[f] (host, k doubles) receives the mean squared prediction error over
+ * the fold.  Synchronous with respect to `stream`.
+ * Returns GL_OK; GL_NOT_SPD when some fold's Σ was not positive definite (its
+ * mse_h is NaN, the other folds are still computed); GL_EINVAL for k < 2, a
+ * fold id out of range, an empty fold or a fold holding every location.
+ */
+int krige_cv(gl_context *ctx, const double *x, const double *y, const double *z, int64_t n,
+             gl_theta theta, const gl_opts *opts, const int32_t *fold_h, int32_t k, double *mse_h,
+             void *stream);
 
 /* Release a factor returned by loglik_eval. */
 int gl_factor_release(gl_context *ctx, gl_factor *factor);
@@ -164,13 +199,14 @@ int gl_factor_to_dense(gl_context *ctx, gl_factor *factor, double *out, int64_t 
 int gl_factor_shape(const gl_factor *factor, int64_t *n, int32_t *tile);
 
 /*
- * Synthetic measurements, Sec. 5.3 Alg. 1: Σ(θ) = L Lᵀ (tiled Cholesky) and
+ * Synthetic measurements, Sec. 6.4 Alg. 1: Σ(θ) = L Lᵀ (tiled Cholesky) and
  * Z = L e.  Inputs x, y, e: n values each (device).  Output z: n doubles.
- * tile: 0 = automatic.  Synchronous with respect to `stream`; *info_h (may be
+ * opts (may be NULL): tile and distance; precision must be GL_FP64, other
+ * fields are ignored.  Synchronous with respect to `stream`; *info_h (may be
  * NULL) receives the Cholesky info.  Returns GL_OK or GL_NOT_SPD.
  */
 int synth_generate(gl_context *ctx, const double *x, const double *y, const double *e,
-                   int64_t n, gl_theta theta, int32_t tile, double *z, int64_t *info_h,
+                   int64_t n, gl_theta theta, const gl_opts *opts, double *z, int64_t *info_h,
                    void *stream);
 
 /* ------------------------------------------------------------ serving ---- */

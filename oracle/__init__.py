@@ -11,7 +11,7 @@ Functions (each follows the passage named in ``oracle.c``):
 * ``bessel_k(nu, x)`` / ``bessel_k_scaled`` — K_ν from its integral form.
 * ``matern(r, theta)`` — Sec. 2.2 Eq. (2).
 * ``distance(x1, y1, x2, y2, metric, radius)`` — Euclidean (metric 0) or
-  great-circle by the haversine formula (metric 1, Sec. 7; x = longitude,
+  great-circle by the haversine formula (metric 1, Sec. 7.4; x = longitude,
   y = latitude in degrees).
 * ``cov_matrix`` / ``cov_symmetric`` — genDistanceMatrix + genCovMatrix.
 * ``cholesky``, ``forward``, ``backward``, ``trmv`` — unblocked dense kernels.

@@ -17,18 +17,18 @@
  *     integral representation K_ν(x) = ∫_0^∞ exp(-x cosh t) cosh(ν t) dt
  *     (DLMF 10.32.9), evaluated with the trapezoidal rule.  The paper names
  *     K_ν but gives no algorithm for it.
- *   - Cholesky factorisation Σ = L Lᵀ (Sec. 5.4, Alg. 2 step "dpotrf"),
+ *   - Cholesky factorisation Σ = L Lᵀ (Sec. 6.5, Alg. 2 step "dpotrf"),
  *     unblocked, row by row (Cholesky–Banachiewicz).
  *   - Forward substitution L w = Z (Alg. 2, "dtrsm").
- *   - log|Σ| = 2 Σ_i log L_ii (Sec. 5.1) and the dot product wᵀw (Alg. 2),
+ *   - log|Σ| = 2 Σ_i log L_ii (Sec. 6.1) and the dot product wᵀw (Alg. 2),
  *     both with Neumaier-compensated summation.
  *   - l(θ) = -n/2 log(2π) - ½ log|Σ| - ½ wᵀw (Sec. 2 Eq. (1), Alg. 2 last step).
  *   - Kriging Z1 = Σ12 Σ22⁻¹ Z2 (Sec. 2.3 Eq. (5), Alg. 3), and the
  *     prediction variance, the diagonal of Σ11 - Σ12 Σ22⁻¹ Σ21 (Eq. (4)),
  *     as θ1 - ‖L⁻¹ σ_k‖² with σ_k the k-th column of Σ21.
- *   - Synthetic field Z = L e (Sec. 5.3, Alg. 1).
+ *   - Synthetic field Z = L e (Sec. 6.4, Alg. 1).
  *   - Distances: Euclidean in the plane (Sec. 2), or great-circle distance on
- *     a sphere of radius ρ by the haversine formula (Sec. 7, used for the
+ *     a sphere of radius ρ by the haversine formula (Sec. 7.4, used for the
  *     longitude/latitude data): hav(d/ρ) = hav(Δφ) + cos φ1 cos φ2 hav(Δλ),
  *     hav(a) = sin²(a/2), with x = longitude and y = latitude in degrees.
  *
@@ -83,7 +83,7 @@ double oracle_matern(double r, double theta1, double theta2, double theta3)
 /* ---------------------------------------------------------- distances ---- */
 
 /* metric 0: Euclidean distance in the plane (Sec. 2, d = 2).
- * metric 1: great-circle distance on a sphere of radius `radius` (Sec. 7),
+ * metric 1: great-circle distance on a sphere of radius `radius` (Sec. 7.4),
  *           x = longitude, y = latitude, both in degrees; the haversine
  *           relation is solved for d as d = 2 ρ asin(√h), with h clamped to
  *           [0, 1] against rounding. */
@@ -201,7 +201,7 @@ static double neumaier_sum(const double *v, int64_t n)
     return s + c;
 }
 
-/* log|Σ| = 2 Σ log L_ii, summed as logs (Sec. 5.1 reads "product of the
+/* log|Σ| = 2 Σ log L_ii, summed as logs (Sec. 6.1 reads "product of the
  * diagonal"; the product itself under/overflows at realistic n). */
 double oracle_logdet(const double *l, int64_t n)
 {
@@ -295,7 +295,7 @@ int64_t oracle_krige(const double *x, const double *y, const double *z, int64_t 
     return info;
 }
 
-/* Synthetic measurements, Sec. 5.3 Alg. 1: Σ(θ) = L Lᵀ, Z = L e.
+/* Synthetic measurements, Sec. 6.4 Alg. 1: Σ(θ) = L Lᵀ, Z = L e.
  * Returns the Cholesky info. */
 int64_t oracle_synth(const double *x, const double *y, const double *e, int64_t n,
                      double theta1, double theta2, double theta3, int metric, double radius,

@@ -26,6 +26,9 @@ GL_FP64 = 0
 GL_MIXED_FP32 = 1
 GL_MIXED_BF16 = 2
 
+GL_EUCLIDEAN = 0
+GL_GREAT_CIRCLE = 1
+
 
 class GeolikError(RuntimeError):
     def __init__(self, status: int, what: str = ""):
@@ -39,8 +42,9 @@ class gl_theta(ctypes.Structure):
 
 class gl_opts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("tile", ctypes.c_int32), ("keep_factor", ctypes.c_int32),
-                ("band", ctypes.c_int32), ("reorder", ctypes.c_int32), ("reserved", ctypes.c_int32),
-                ("tol_hi", ctypes.c_double), ("tol_lo", ctypes.c_double)]
+                ("band", ctypes.c_int32), ("reorder", ctypes.c_int32), ("metric", ctypes.c_int32),
+                ("tol_hi", ctypes.c_double), ("tol_lo", ctypes.c_double), ("radius", ctypes.c_double),
+                ("tol_64", ctypes.c_double)]
 
 
 class gl_result(ctypes.Structure):
@@ -72,13 +76,14 @@ _SIGNATURES = {
     "gl_opts_default": (None, [ctypes.POINTER(gl_opts)]),
     "gl_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "gl_footprint_bytes": (_SZ, [_I64, _I32, _I32]),
-    "matern_generate": (_I32, [_P, _P, _P, _I64, _P, _P, _I64, gl_theta, _P, _I64, _P]),
+    "matern_generate": (_I32, [_P, _P, _P, _I64, _P, _P, _I64, gl_theta, _P, _P, _I64, _P]),
     "loglik_eval": (_I32, [_P, _P, _P, _P, _I64, gl_theta, ctypes.POINTER(gl_opts), ctypes.POINTER(gl_result), _P]),
-    "krige_predict": (_I32, [_P, _P, _P, _P, _I64, _P, _P]),
+    "krige_predict": (_I32, [_P, _P, _P, _P, _I64, _P, _P, _P]),
+    "krige_cv": (_I32, [_P, _P, _P, _P, _I64, gl_theta, _P, _P, _I32, _P, _P]),
     "gl_factor_release": (_I32, [_P, _P]),
     "gl_factor_to_dense": (_I32, [_P, _P, _P, _I64, _P]),
     "gl_factor_shape": (_I32, [_P, ctypes.POINTER(_I64), ctypes.POINTER(_I32)]),
-    "synth_generate": (_I32, [_P, _P, _P, _P, _I64, gl_theta, _I32, _P, ctypes.POINTER(_I64), _P]),
+    "synth_generate": (_I32, [_P, _P, _P, _P, _I64, gl_theta, _P, _P, ctypes.POINTER(_I64), _P]),
     "gl_dataset_register": (_I32, [_P, _P, _P, _P, _I64, ctypes.POINTER(_U64)]),
     "gl_dataset_release": (_I32, [_P, _U64]),
     "lq_config_default": (None, [ctypes.POINTER(lq_config)]),
@@ -192,15 +197,17 @@ def gl_context_destroy(ctx: Context) -> None:
     ctx.close()
 
 
-def matern_generate(ctx: Context, x1, y1, x2, y2, theta, out=None, stream=None):
-    """Dense column-major n1×n2 Matérn covariance; returns a torch tensor of shape (n2, n1)
-    whose transpose is Σ12 (i.e. out.T[i, j] = C(||s1_i - s2_j||))."""
+def matern_generate(ctx: Context, x1, y1, x2, y2, theta, opts: gl_opts | None = None, out=None, stream=None):
+    """Dense column-major n1×n2 Matérn covariance (distance from opts.metric);
+    returns a torch tensor of shape (n2, n1) whose transpose is Σ12
+    (out.T[i, j] = C(d(s1_i, s2_j)))."""
     import torch
     n1, n2 = x1.numel(), x2.numel()
     if out is None:
         out = torch.empty((n2, n1), dtype=torch.float64, device=x1.device)
     _check(lib().matern_generate(ctx.handle, _ptr(x1), _ptr(y1), n1, _ptr(x2), _ptr(y2), n2, _theta(theta),
-                                 _ptr(out), n1, _stream(stream)), "matern_generate")
+                                 ctypes.byref(opts) if opts is not None else None, _ptr(out), n1,
+                                 _stream(stream)), "matern_generate")
     return out
 
 
@@ -214,14 +221,34 @@ def loglik_eval(ctx: Context, x, y, z, theta, opts: gl_opts | None = None, strea
     return res.as_dict()
 
 
-def krige_predict(ctx: Context, factor, xnew, ynew, out=None, stream=None):
+def krige_predict(ctx: Context, factor, xnew, ynew, out=None, return_variance: bool = False, var=None,
+                  stream=None):
+    """Eq. (5) predictions at the new locations; with return_variance, also
+    the prediction variances of Eq. (4): returns (pred, var)."""
     import torch
     m = xnew.numel()
     if out is None:
         out = torch.empty(m, dtype=torch.float64, device=xnew.device)
-    _check(lib().krige_predict(ctx.handle, factor, _ptr(xnew), _ptr(ynew), m, _ptr(out), _stream(stream)),
-           "krige_predict")
-    return out
+    if return_variance and var is None:
+        var = torch.empty(m, dtype=torch.float64, device=xnew.device)
+    _check(lib().krige_predict(ctx.handle, factor, _ptr(xnew), _ptr(ynew), m, _ptr(out),
+                               _ptr(var) if return_variance else None, _stream(stream)), "krige_predict")
+    return (out, var) if return_variance else out
+
+
+def krige_cv(ctx: Context, x, y, z, theta, folds, opts: gl_opts | None = None, stream=None):
+    """k-fold cross-validation MSE of kriging; folds: n fold ids (0..k-1).
+    Returns (mse per fold as a list, status)."""
+    import numpy as np
+    f = np.ascontiguousarray(np.asarray(folds, dtype=np.int32))
+    k = int(f.max()) + 1 if f.size else 0
+    mse = (ctypes.c_double * max(k, 1))()
+    st = lib().krige_cv(ctx.handle, _ptr(x), _ptr(y), _ptr(z), x.numel(), _theta(theta),
+                        ctypes.byref(opts) if opts is not None else None,
+                        f.ctypes.data_as(ctypes.c_void_p), k, mse, _stream(stream))
+    if st < 0:
+        _check(st, "krige_cv")
+    return [float(v) for v in mse[:k]], int(st)
 
 
 def gl_factor_release(ctx: Context, factor) -> None:
@@ -244,15 +271,17 @@ def gl_factor_to_dense(ctx: Context, factor, out=None, stream=None):
     return out
 
 
-def synth_generate(ctx: Context, x, y, e, theta, tile: int = 0, out=None, stream=None):
-    """Alg. 1: returns (z, info)."""
+def synth_generate(ctx: Context, x, y, e, theta, tile: int = 0, opts: gl_opts | None = None, out=None,
+                   stream=None):
+    """Alg. 1: returns (z, info).  opts (tile, metric, radius) overrides tile."""
     import torch
     n = x.numel()
     if out is None:
         out = torch.empty(n, dtype=torch.float64, device=x.device)
+    o = opts if opts is not None else gl_opts_default(tile=int(tile))
     info = _I64()
-    _check(lib().synth_generate(ctx.handle, _ptr(x), _ptr(y), _ptr(e), n, _theta(theta), int(tile), _ptr(out),
-                                ctypes.byref(info), _stream(stream)), "synth_generate")
+    _check(lib().synth_generate(ctx.handle, _ptr(x), _ptr(y), _ptr(e), n, _theta(theta), ctypes.byref(o),
+                                _ptr(out), ctypes.byref(info), _stream(stream)), "synth_generate")
     return out, int(info.value)
 
 

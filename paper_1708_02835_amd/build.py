@@ -35,7 +35,7 @@ def _compile(src: str) -> str:
     if src.endswith(".hip"):
         cmd = [HIPCC, *COMMON, *DEVICE, "-x", "hip", "-c", path, "-o", out]
     else:
-        cmd = [HIPCC, *COMMON, "-D__HIP_PLATFORM_AMD__", "-c", path, "-o", out]
+        cmd = [HIPCC, *COMMON, *DEVICE, "-D__HIP_PLATFORM_AMD__", "-c", path, "-o", out]
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         raise RuntimeError(f"compile failed: {' '.join(cmd)}\n{res.stdout}\n{res.stderr}")

@@ -15,6 +15,7 @@ struct BatchReq {
     DevResult *res;
     const double *sx, *sy, *sz;  // dataset (sources of the staging copy)
     gl_theta th;
+    Geom geo;
     int64_t n, nt, npad, k;      // k: the step this launch performs
     int64_t o_stage, o_gen, o_trsm, o_tr;
     int32_t is_new, finishing;

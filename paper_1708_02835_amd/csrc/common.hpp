@@ -37,12 +37,20 @@ struct DevResult {
     int64_t pad2;
 };
 
+// Distance used by Σ(θ): metric 0 = Euclidean in the plane, 1 = great-circle
+// on a sphere of the given radius (x = longitude, y = latitude, degrees).
+struct Geom {
+    int32_t metric;
+    double radius;
+};
+inline Geom geom_of(const gl_opts &o) { return Geom{o.metric, o.radius}; }
+
 // Launchers (one per kernel family); all asynchronous on `s`.
 // Matérn generation
 void launch_gen_tiles(double *tiles, const double *x, const double *y, int64_t n, int b, int64_t nt,
-                      gl_theta th, double *tile_norm2, hipStream_t s);
+                      gl_theta th, Geom geo, double *tile_norm2, hipStream_t s);
 void launch_gen_dense(const double *x1, const double *y1, int64_t n1, const double *x2,
-                      const double *y2, int64_t n2, gl_theta th, double *out, int64_t ld,
+                      const double *y2, int64_t n2, gl_theta th, Geom geo, double *out, int64_t ld,
                       hipStream_t s);
 // Cholesky steps (FP64)
 // POTRF leaves the inverses of the b/64 diagonal 64×64 blocks of L_kk in dinv
@@ -70,12 +78,27 @@ void launch_copy_pad(const double *src, int64_t n, double *dst, int64_t npad, do
 void launch_tiles_to_dense(const double *tiles, int b, int64_t n, double *out, int64_t ld,
                            hipStream_t s);
 // Kriging
-void launch_krige(const double *x, const double *y, int64_t n, const double *v, gl_theta th,
+void launch_krige(const double *x, const double *y, int64_t n, const double *v, gl_theta th, Geom geo,
                   const double *xn, const double *yn, int64_t m, double *part, int64_t nchunk,
                   hipStream_t s);
 void launch_krige_reduce(const double *part, int64_t m, int64_t nchunk, double *out, hipStream_t s);
 int64_t krige_chunks(int64_t n);
 // Diagnostics
 int selftest_mfma(int which, double *out_h, int64_t cap);
+
+// Kriging variances (Eq. 4): chunks of b right-hand sides solved together.
+void launch_gen_rhs(double *st, const double *x, const double *y, int64_t n, int b, int64_t nt, const double *xn,
+                    const double *yn, int64_t m, int64_t chunks, gl_theta th, Geom geo, hipStream_t s);
+void launch_mrhs_diag(const double *tiles, double *st, int b, int64_t nt, int64_t k, const double *dinv,
+                      int64_t chunks, hipStream_t s);
+void launch_mrhs_update(const double *tiles, double *st, int b, int64_t nt, int64_t k, int64_t chunks,
+                        hipStream_t s);
+void launch_rhs_variance(const double *st, int b, int64_t nt, int64_t chunks, int64_t m, double theta1,
+                         double *part, double *var, hipStream_t s);
+
+// Cross-validation helpers.
+void launch_gather3(const double *a, const double *b, const double *c, const int64_t *idx, int64_t m, double *oa,
+                    double *ob, double *oc, hipStream_t s);
+void launch_mse(const double *p, const double *q, int64_t m, double *out, hipStream_t s);
 
 }  // namespace gl

@@ -10,6 +10,8 @@
 #include <vector>
 
 #include "common.hpp"
+#include <algorithm>
+
 #include "engine.hpp"
 
 int gl_hip_fail(hipError_t e, const char *what)
@@ -40,8 +42,8 @@ static void work_sizes(int64_t n, int b, int precision, size_t &tiles, size_t &v
     const int64_t nt = ceil_div(n, b);
     const int64_t npad = nt * b;
     tiles = (size_t)tile_count(nt) * (size_t)b * b * sizeof(double);
-    // x, y, v | logsum, quad | norm2 | dinv | info + result | Morton keys
-    vec = (size_t)(3 * npad + 2 * nt + tile_count(nt) + 64 * b + 16 + npow2_of(n) + 4) * sizeof(double);
+    // x, y, v | logsum, quad | norm2 | dinv (every diagonal tile) | info + result | Morton keys
+    vec = (size_t)(3 * npad + 2 * nt + tile_count(nt) + 64 * npad + 16 + npow2_of(n) + 4) * sizeof(double);
     mix = mixed_extra_bytes(nt, b, precision);
 }
 
@@ -104,7 +106,7 @@ int Work::ensure(gl_context *ctx, int64_t n_, int b_, int precision_)
     quad = logsum + nt;
     norm2 = quad + nt;
     dinv = norm2 + tile_count(nt);
-    info = reinterpret_cast<int64_t *>(dinv + 64 * b);
+    info = reinterpret_cast<int64_t *>(dinv + 64 * npad);
     res = reinterpret_cast<DevResult *>(info + 8);
     keys = reinterpret_cast<uint64_t *>(info + 16);
     mixed_views(*this);
@@ -174,9 +176,9 @@ int factorize(Lanes &ln, Work &w, hipStream_t s, bool solve)
     GL_HIP_TRY(hipEventRecord(ln.fork, s));
     GL_HIP_TRY(hipStreamWaitEvent(la, ln.fork, 0));
     for (int64_t k = 0; k < w.nt; ++k) {
-        launch_potrf(w.tiles, w.b, k, w.n, w.info, w.logsum, w.dinv, s);
-        if (solve) launch_fwd_diag(w.tiles, w.b, k, w.n, w.v, w.quad, w.dinv, w.info, s);
-        launch_trsm(w.tiles, w.b, w.nt, k, w.dinv, w.info, s);
+        launch_potrf(w.tiles, w.b, k, w.n, w.info, w.logsum, w.dinv_k(k), s);
+        if (solve) launch_fwd_diag(w.tiles, w.b, k, w.n, w.v, w.quad, w.dinv_k(k), w.info, s);
+        launch_trsm(w.tiles, w.b, w.nt, k, w.dinv_k(k), w.info, s);
         if (solve) launch_fwd_update(w.tiles, w.b, w.nt, k, w.v, w.info, s);
         if (k + 1 < w.nt) {
             GL_HIP_TRY(hipEventRecord(ln.panel, s));
@@ -225,9 +227,11 @@ void gl_opts_default(gl_opts *o)
     o->keep_factor = 0;
     o->band = 2;
     o->reorder = -1;
-    o->reserved = 0;
+    o->metric = GL_EUCLIDEAN;
     o->tol_hi = -1.0;
     o->tol_lo = -1.0;
+    o->tol_64 = -1.0;
+    o->radius = 6371.0;
 }
 
 size_t gl_footprint_bytes(int64_t n, int32_t tile, int32_t precision)
@@ -282,13 +286,18 @@ void gl_context_destroy(gl_context *c)
 }
 
 int matern_generate(gl_context *ctx, const double *x1, const double *y1, int64_t n1, const double *x2,
-                    const double *y2, int64_t n2, gl_theta th, double *out, int64_t ld, void *stream)
+                    const double *y2, int64_t n2, gl_theta th, const gl_opts *opts, double *out, int64_t ld,
+                    void *stream)
 {
     if (!ctx || !x1 || !y1 || !x2 || !y2 || !out || n1 < 1 || n2 < 1 || ld < n1 || !valid_theta(th))
         return GL_EINVAL;
+    gl_opts o;
+    gl_opts_default(&o);
+    if (opts) o = *opts;
+    if (!valid_metric(o)) return GL_EINVAL;
     GL_HIP_TRY(hipSetDevice(ctx->device));
     hipStream_t s = static_cast<hipStream_t>(stream);
-    launch_gen_dense(x1, y1, n1, x2, y2, n2, th, out, ld, s);
+    launch_gen_dense(x1, y1, n1, x2, y2, n2, th, geom_of(o), out, ld, s);
     GL_HIP_TRY(hipGetLastError());
     return GL_OK;
 }
@@ -306,7 +315,7 @@ int eval_launch(Lanes &ln, Work &w, gl_theta th, const gl_opts &o, hipStream_t s
     launch_fill(reinterpret_cast<double *>(w.info), 1, 0.0, s);
     int rc;
     if (o.precision == GL_FP64) {
-        launch_gen_tiles(w.tiles, w.x, w.y, w.n, w.b, w.nt, th, nullptr, s);
+        launch_gen_tiles(w.tiles, w.x, w.y, w.n, w.b, w.nt, th, geom_of(o), nullptr, s);
         rc = factorize(ln, w, s, true);
     } else {
         rc = mixed_factorize(ln, w, th, o, s, plan_out);
@@ -318,13 +327,20 @@ int eval_launch(Lanes &ln, Work &w, gl_theta th, const gl_opts &o, hipStream_t s
     return GL_OK;
 }
 
+bool valid_metric(const gl_opts &o)
+{
+    if (o.metric == GL_EUCLIDEAN) return true;
+    return o.metric == GL_GREAT_CIRCLE && o.radius > 0.0 && isfinite(o.radius);
+}
+
 bool valid_opts(const gl_opts &o)
 {
+    if (!valid_metric(o)) return false;
     if (o.precision < GL_FP64 || o.precision > GL_MIXED_BF16) return false;
     if (o.tile != 0 && o.tile != 128 && o.tile != 256 && o.tile != 384 && o.tile != 512) return false;
     if (o.reorder < -1 || o.reorder > 1) return false;
     if (o.precision != GL_FP64 && o.band < 1) return false;
-    if (isnan(o.tol_hi) || isnan(o.tol_lo)) return false;
+    if (isnan(o.tol_hi) || isnan(o.tol_lo) || isnan(o.tol_64)) return false;
     return true;
 }
 
@@ -345,9 +361,8 @@ void stage_inputs(Work &w, const double *x, const double *y, const double *z, in
 gl_opts resolved_opts(const gl_opts &in)
 {
     gl_opts o = in;
-    if (o.precision == GL_MIXED_FP32) {
-        if (o.tol_hi < 0) o.tol_hi = INFINITY;
-    } else if (o.precision == GL_MIXED_BF16) {
+    if (o.precision != GL_FP64) {
+        if (o.tol_64 < 0) o.tol_64 = 0.3;
         if (o.tol_hi < 0) o.tol_hi = 1e-2;
         if (o.tol_lo < 0) o.tol_lo = 1e-4;
     }
@@ -393,6 +408,7 @@ int loglik_eval(gl_context *ctx, const double *x, const double *y, const double 
         if (!f) return res->status = GL_ENOMEM;
         f->ctx = ctx;
         f->theta = th;
+        f->opts = o;
         w = &f->w;
     }
     int rc = w->ensure(ctx, n, b, o.precision);
@@ -465,46 +481,137 @@ int gl_factor_to_dense(gl_context *ctx, gl_factor *f, double *out, int64_t ld, v
 }
 
 int krige_predict(gl_context *ctx, gl_factor *f, const double *xnew, const double *ynew, int64_t m,
-                  double *znew, void *stream)
+                  double *znew, double *var, void *stream)
 {
     if (!ctx || !f || f->ctx != ctx || !xnew || !ynew || !znew || m < 1) return GL_EINVAL;
     GL_HIP_TRY(hipSetDevice(ctx->device));
     hipStream_t s = static_cast<hipStream_t>(stream);
     Work &w = f->w;
+    const Geom geo = geom_of(f->opts);
     const int64_t nchunk = krige_chunks(w.n);
+    // variances: groups of up to 8 chunks of b right-hand sides
+    const int64_t chunks = var ? std::min<int64_t>(8, ceil_div(m, w.b)) : 0;
+    const size_t st_len = (size_t)chunks * w.npad * w.b;
     double *scratch = nullptr;
-    const size_t bytes = (size_t)(w.npad + m * nchunk) * sizeof(double);
-    GL_HIP_TRY(hipMallocAsync(reinterpret_cast<void **>(&scratch), bytes, s));
+    const size_t bytes = ((size_t)w.npad + m * nchunk + st_len + (size_t)chunks * w.npad) * sizeof(double);
+    if (hipMallocAsync(reinterpret_cast<void **>(&scratch), bytes, s) != hipSuccess) {
+        (void)hipGetLastError();
+        return GL_ENOMEM;
+    }
     double *xv = scratch;
     double *part = scratch + w.npad;
+    double *st = part + m * nchunk;
+    double *vpart = st + st_len;
     // X = L⁻ᵀ w: backward substitution over tile rows, last to first
     GL_HIP_TRY(hipMemcpyAsync(xv, w.v, (size_t)w.npad * sizeof(double), hipMemcpyDeviceToDevice, s));
     for (int64_t k = w.nt - 1; k >= 0; --k) {
         launch_bwd_diag(w.tiles, w.b, k, xv, s);
         launch_bwd_update(w.tiles, w.b, k, xv, s);
     }
-    launch_krige(w.x, w.y, w.n, xv, f->theta, xnew, ynew, m, part, nchunk, s);
+    launch_krige(w.x, w.y, w.n, xv, f->theta, geo, xnew, ynew, m, part, nchunk, s);
     launch_krige_reduce(part, m, nchunk, znew, s);
+    // var_k = θ1 - ||L⁻¹ σ_k||², right-hand sides solved on the matrix cores
+    for (int64_t k0 = 0; var && k0 < m; k0 += chunks * w.b) {
+        const int64_t mg = std::min<int64_t>(m - k0, chunks * w.b);
+        const int64_t cg = ceil_div(mg, w.b);
+        launch_gen_rhs(st, w.x, w.y, w.n, w.b, w.nt, xnew + k0, ynew + k0, mg, cg, f->theta, geo, s);
+        for (int64_t k = 0; k < w.nt; ++k) {
+            launch_mrhs_diag(w.tiles, st, w.b, w.nt, k, w.dinv_k(k), cg, s);
+            launch_mrhs_update(w.tiles, st, w.b, w.nt, k, cg, s);
+        }
+        launch_rhs_variance(st, w.b, w.nt, cg, mg, f->theta.theta1, vpart, var + k0, s);
+    }
     GL_HIP_TRY(hipGetLastError());
     GL_HIP_TRY(hipFreeAsync(scratch, s));
     return GL_OK;
 }
 
+int krige_cv(gl_context *ctx, const double *x, const double *y, const double *z, int64_t n, gl_theta th,
+             const gl_opts *opts, const int32_t *fold_h, int32_t k, double *mse_h, void *stream)
+{
+    if (!ctx || !x || !y || !z || !fold_h || !mse_h || n < 2 || k < 2 || !valid_theta(th)) return GL_EINVAL;
+    gl_opts o;
+    gl_opts_default(&o);
+    if (opts) o = *opts;
+    o.keep_factor = 1;
+    if (!valid_opts(o)) return GL_EINVAL;
+    std::vector<int64_t> count(k, 0);
+    for (int64_t i = 0; i < n; ++i) {
+        if (fold_h[i] < 0 || fold_h[i] >= k) return GL_EINVAL;
+        ++count[fold_h[i]];
+    }
+    for (int32_t f = 0; f < k; ++f)
+        if (count[f] == 0 || count[f] == n) return GL_EINVAL;
+    GL_HIP_TRY(hipSetDevice(ctx->device));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    // scratch: index list (n) | known x, y, z | missing x, y, z, prediction | mse
+    double *buf = nullptr;
+    const size_t len = (size_t)n + 7 * (size_t)n + 8;
+    if (hipMallocAsync(reinterpret_cast<void **>(&buf), len * sizeof(double), s) != hipSuccess) {
+        (void)hipGetLastError();
+        return GL_ENOMEM;
+    }
+    int64_t *idx = reinterpret_cast<int64_t *>(buf);
+    double *kx = buf + n, *ky = kx + n, *kz = ky + n;
+    double *mx = kz + n, *my = mx + n, *mz = my + n, *pred = mz + n, *dmse = pred + n;
+    std::vector<int64_t> order(n);
+    int status = GL_OK;
+    for (int32_t f = 0; f < k; ++f) {
+        // known locations first, then the fold's (missing) ones, each in input order
+        int64_t a = 0, b = n - count[f];
+        for (int64_t i = 0; i < n; ++i) order[fold_h[i] == f ? b++ : a++] = i;
+        const int64_t nk = n - count[f], nm = count[f];
+        int rc = GL_OK;
+        if (hipMemcpyAsync(idx, order.data(), n * sizeof(int64_t), hipMemcpyHostToDevice, s) != hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess)
+            rc = GL_EHIP;
+        if (rc == GL_OK) {
+            launch_gather3(x, y, z, idx, nk, kx, ky, kz, s);
+            launch_gather3(x, y, z, idx + nk, nm, mx, my, mz, s);
+            gl_result r;
+            rc = loglik_eval(ctx, kx, ky, kz, nk, th, &o, &r, stream);
+            if (rc == GL_OK) {
+                rc = krige_predict(ctx, r.factor, mx, my, nm, pred, nullptr, stream);
+                if (rc == GL_OK) {
+                    launch_mse(pred, mz, nm, dmse, s);
+                    if (hipMemcpyAsync(&mse_h[f], dmse, sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess ||
+                        hipStreamSynchronize(s) != hipSuccess)
+                        rc = GL_EHIP;
+                }
+                gl_factor_release(ctx, r.factor);
+            } else if (rc == GL_NOT_SPD) {
+                mse_h[f] = NAN;
+            }
+        }
+        if (rc < 0) {
+            status = rc;
+            break;
+        }
+        if (rc == GL_NOT_SPD) status = GL_NOT_SPD;
+    }
+    (void)hipFreeAsync(buf, s);
+    (void)hipStreamSynchronize(s);
+    return status;
+}
+
 int synth_generate(gl_context *ctx, const double *x, const double *y, const double *e, int64_t n,
-                   gl_theta th, int32_t tile, double *z, int64_t *info_h, void *stream)
+                   gl_theta th, const gl_opts *opts, double *z, int64_t *info_h, void *stream)
 {
     if (!ctx || !x || !y || !e || !z || n < 1 || !valid_theta(th)) return GL_EINVAL;
-    if (tile != 0 && tile != 128 && tile != 256 && tile != 384 && tile != 512) return GL_EINVAL;
+    gl_opts o;
+    gl_opts_default(&o);
+    if (opts) o = *opts;
+    if (!valid_opts(o) || o.precision != GL_FP64) return GL_EINVAL;
     GL_HIP_TRY(hipSetDevice(ctx->device));
     hipStream_t s = static_cast<hipStream_t>(stream);
     Work &w = ctx->ws;
-    int rc = w.ensure(ctx, n, pick_tile(n, tile), GL_FP64);
+    int rc = w.ensure(ctx, n, pick_tile(n, o.tile), GL_FP64);
     if (rc != GL_OK) return rc;
     launch_copy_pad(x, n, w.x, w.npad, 0.0, s);
     launch_copy_pad(y, n, w.y, w.npad, 0.0, s);
     launch_copy_pad(e, n, w.v, w.npad, 0.0, s);
     launch_fill(reinterpret_cast<double *>(w.info), 1, 0.0, s);
-    launch_gen_tiles(w.tiles, w.x, w.y, w.n, w.b, w.nt, th, nullptr, s);
+    launch_gen_tiles(w.tiles, w.x, w.y, w.n, w.b, w.nt, th, geom_of(o), nullptr, s);
     rc = factorize(ctx->lanes, w, s, false);
     if (rc != GL_OK) return rc;
     // z = L e: e is read from v, the padded product goes to the x buffer (no

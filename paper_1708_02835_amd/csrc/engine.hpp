@@ -45,13 +45,15 @@ struct Work {
     double *logsum = nullptr;           // per diagonal tile: 2 Σ log L_rr
     double *quad = nullptr;             // per tile: Σ w_r²
     double *norm2 = nullptr;            // per tile: ||Σ_ij||_F² (mixed precision)
-    double *dinv = nullptr;             // inverses of the 64×64 diagonal blocks of the current L_kk
+    double *dinv = nullptr;             // inverses of the 64×64 diagonal blocks of every L_kk:
+                                        // 64·b doubles per diagonal tile, kept with the factor
     int64_t *info = nullptr;
     DevResult *res = nullptr;
     uint64_t *keys = nullptr;           // Morton sort keys (+ bounding box)
     MixedViews mv;
     int ensure(gl_context *ctx, int64_t n, int b, int precision);
     size_t bytes() const { return tile_cap + vec_cap + mix_cap; }
+    double *dinv_k(int64_t k) const { return dinv + k * 64 * (int64_t)b; }
     void release();
 };
 
@@ -86,6 +88,7 @@ int eval_launch(Lanes &ln, Work &w, gl_theta th, const gl_opts &o, hipStream_t s
 void stage_inputs(Work &w, const double *x, const double *y, const double *z, int reorder, hipStream_t s);
 gl_opts resolved_opts(const gl_opts &in);
 bool valid_opts(const gl_opts &o);
+bool valid_metric(const gl_opts &o);
 
 // mixed precision (mixed.hip)
 size_t mixed_extra_bytes(int64_t nt, int b, int precision);
@@ -108,6 +111,7 @@ void serve_context_cleanup(gl_context *ctx);
 struct gl_factor {
     gl_context *ctx = nullptr;
     gl_theta theta{};
+    gl_opts opts{};  // options of the evaluation (distance, precision, order)
     gl::Work w;
 };
 

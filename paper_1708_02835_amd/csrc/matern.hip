@@ -28,7 +28,7 @@ __device__ inline void tile_from_index(int64_t t, int64_t &i, int64_t &j)
 // fixed-order block reduction.
 template <int B>
 __device__ __forceinline__ void gen_tiles_body(double *__restrict__ tiles, const double *__restrict__ x,
-                                               const double *__restrict__ y, int64_t n, gl_theta th,
+                                               const double *__restrict__ y, int64_t n, gl_theta th, Geom geo,
                                                double *__restrict__ norm2, int64_t t)
 {
     int64_t ti, tj;
@@ -57,7 +57,7 @@ __device__ __forceinline__ void gen_tiles_body(double *__restrict__ tiles, const
             int r = threadIdx.x + 256 * q;
             if (r >= B) continue;
             double v;
-            if (colok && gr[q] < n) v = matern_eval(ms, dist2d(xr[q], yr[q], xc, yc));
+            if (colok && gr[q] < n) v = matern_eval(ms, geo_dist(geo, xr[q], yr[q], xc, yc));
             else v = (gr[q] == gc) ? 1.0 : 0.0;
             T[(int64_t)c * B + r] = v;
             ss += v * v;
@@ -76,20 +76,20 @@ template <int B>
 __global__ __launch_bounds__(256) void gen_tiles_kernel(double *__restrict__ tiles,
                                                         const double *__restrict__ x,
                                                         const double *__restrict__ y, int64_t n,
-                                                        gl_theta th, double *__restrict__ norm2)
+                                                        gl_theta th, Geom geo, double *__restrict__ norm2)
 {
-    gen_tiles_body<B>(tiles, x, y, n, th, norm2, blockIdx.x);
+    gen_tiles_body<B>(tiles, x, y, n, th, geo, norm2, blockIdx.x);
 }
 
 void launch_gen_tiles(double *tiles, const double *x, const double *y, int64_t n, int b, int64_t nt,
-                      gl_theta th, double *norm2, hipStream_t s)
+                      gl_theta th, Geom geo, double *norm2, hipStream_t s)
 {
     dim3 grid((unsigned)tile_count(nt));
     switch (b) {
-    case 128: gen_tiles_kernel<128><<<grid, 256, 0, s>>>(tiles, x, y, n, th, norm2); break;
-    case 256: gen_tiles_kernel<256><<<grid, 256, 0, s>>>(tiles, x, y, n, th, norm2); break;
-    case 384: gen_tiles_kernel<384><<<grid, 256, 0, s>>>(tiles, x, y, n, th, norm2); break;
-    default: gen_tiles_kernel<512><<<grid, 256, 0, s>>>(tiles, x, y, n, th, norm2); break;
+    case 128: gen_tiles_kernel<128><<<grid, 256, 0, s>>>(tiles, x, y, n, th, geo, norm2); break;
+    case 256: gen_tiles_kernel<256><<<grid, 256, 0, s>>>(tiles, x, y, n, th, geo, norm2); break;
+    case 384: gen_tiles_kernel<384><<<grid, 256, 0, s>>>(tiles, x, y, n, th, geo, norm2); break;
+    default: gen_tiles_kernel<512><<<grid, 256, 0, s>>>(tiles, x, y, n, th, geo, norm2); break;
     }
 }
 
@@ -99,7 +99,7 @@ __global__ __launch_bounds__(256) void gen_batched_kernel(const BatchReq *__rest
     const int64_t g = blockIdx.x;
     const int r = GL_BATCH_FIND(d, count, g, o_gen);
     const BatchReq &q = d[r];
-    gen_tiles_body<B>(q.tiles, q.x, q.y, q.n, q.th, nullptr, g - q.o_gen);
+    gen_tiles_body<B>(q.tiles, q.x, q.y, q.n, q.th, q.geo, nullptr, g - q.o_gen);
 }
 
 void launch_gen_batched(int b, const BatchReq *d, int count, int64_t tiles, hipStream_t s)
@@ -115,7 +115,7 @@ __global__ __launch_bounds__(256) void gen_dense_kernel(const double *__restrict
                                                         const double *__restrict__ y1, int64_t n1,
                                                         const double *__restrict__ x2,
                                                         const double *__restrict__ y2, int64_t n2,
-                                                        gl_theta th, double *__restrict__ out,
+                                                        gl_theta th, Geom geo, double *__restrict__ out,
                                                         int64_t ld)
 {
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
@@ -126,16 +126,16 @@ __global__ __launch_bounds__(256) void gen_dense_kernel(const double *__restrict
     for (int c = 0; c < 16; ++c) {
         int64_t j = j0 + c;
         if (j >= n2) break;
-        out[i + j * ld] = matern_eval(ms, dist2d(xi, yi, x2[j], y2[j]));
+        out[i + j * ld] = matern_eval(ms, geo_dist(geo, xi, yi, x2[j], y2[j]));
     }
 }
 
 void launch_gen_dense(const double *x1, const double *y1, int64_t n1, const double *x2,
-                      const double *y2, int64_t n2, gl_theta th, double *out, int64_t ld,
+                      const double *y2, int64_t n2, gl_theta th, Geom geo, double *out, int64_t ld,
                       hipStream_t s)
 {
     dim3 grid((unsigned)ceil_div(n1, 256), (unsigned)ceil_div(n2, 16));
-    gen_dense_kernel<<<grid, 256, 0, s>>>(x1, y1, n1, x2, y2, n2, th, out, ld);
+    gen_dense_kernel<<<grid, 256, 0, s>>>(x1, y1, n1, x2, y2, n2, th, geo, out, ld);
 }
 
 // Kriging, Eq. (5): Z1_k = Σ_j C(||s_new,k - s_j||) v_j with v = Σ22⁻¹ Z2.
@@ -145,7 +145,7 @@ constexpr int KRIGE_CHUNK = 4096;
 
 __global__ __launch_bounds__(256) void krige_kernel(const double *__restrict__ x,
                                                     const double *__restrict__ y, int64_t n,
-                                                    const double *__restrict__ v, gl_theta th,
+                                                    const double *__restrict__ v, gl_theta th, Geom geo,
                                                     const double *__restrict__ xn,
                                                     const double *__restrict__ yn,
                                                     double *__restrict__ part, int64_t nchunk)
@@ -158,7 +158,7 @@ __global__ __launch_bounds__(256) void krige_kernel(const double *__restrict__ x
     const int64_t j1 = min(n, j0 + KRIGE_CHUNK);
     double acc = 0.0;
     for (int64_t j = j0 + threadIdx.x; j < j1; j += 256)
-        acc += matern_eval(ms, dist2d(xk, yk, x[j], y[j])) * v[j];
+        acc += matern_eval(ms, geo_dist(geo, xk, yk, x[j], y[j])) * v[j];
     __shared__ double red[4];
     double w = wave_sum(acc);
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = w;
@@ -176,12 +176,12 @@ __global__ void krige_reduce_kernel(const double *__restrict__ part, int64_t m, 
     out[k] = s;
 }
 
-void launch_krige(const double *x, const double *y, int64_t n, const double *v, gl_theta th,
+void launch_krige(const double *x, const double *y, int64_t n, const double *v, gl_theta th, Geom geo,
                   const double *xn, const double *yn, int64_t m, double *part, int64_t nchunk,
                   hipStream_t s)
 {
     dim3 grid((unsigned)m, (unsigned)nchunk);
-    krige_kernel<<<grid, 256, 0, s>>>(x, y, n, v, th, xn, yn, part, nchunk);
+    krige_kernel<<<grid, 256, 0, s>>>(x, y, n, v, th, geo, xn, yn, part, nchunk);
 }
 
 void launch_krige_reduce(const double *part, int64_t m, int64_t nchunk, double *out, hipStream_t s)
@@ -190,5 +190,56 @@ void launch_krige_reduce(const double *part, int64_t m, int64_t nchunk, double *
 }
 
 int64_t krige_chunks(int64_t n) { return ceil_div(n, KRIGE_CHUNK); }
+
+// Right-hand sides of the kriging variances (Eq. 4), transposed: tile (c, i)
+// of st (b×b column-major) holds C(||s_new,r - s_p||) for new location
+// c·b + r and observed location i·b + p; zero where either is padding.  One
+// workgroup per tile; stores are coalesced along r.
+template <int B>
+__global__ __launch_bounds__(256) void gen_rhs_kernel(double *__restrict__ st, const double *__restrict__ x,
+                                                      const double *__restrict__ y, int64_t n, int64_t nt,
+                                                      const double *__restrict__ xn, const double *__restrict__ yn,
+                                                      int64_t m, gl_theta th, Geom geo)
+{
+    const int64_t t = blockIdx.x;
+    const int64_t c = t / nt, i = t % nt;
+    const MaternSetup ms = matern_setup(th.theta1, th.theta2, th.theta3);
+    double *T = st + t * (int64_t)B * B;
+    constexpr int RPT = (B + 255) / 256;
+    double xr[RPT], yr[RPT];
+    bool rok[RPT];
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) {
+        const int r = threadIdx.x + 256 * q;
+        const int64_t kn = c * B + r;
+        rok[q] = (r < B) && kn < m;
+        xr[q] = rok[q] ? xn[kn] : 0.0;
+        yr[q] = rok[q] ? yn[kn] : 0.0;
+    }
+    for (int p = 0; p < B; ++p) {
+        const int64_t gp = i * B + p;
+        const bool pok = gp < n;
+        const double xp = pok ? x[gp] : 0.0;
+        const double yp = pok ? y[gp] : 0.0;
+#pragma unroll
+        for (int q = 0; q < RPT; ++q) {
+            const int r = threadIdx.x + 256 * q;
+            if (r >= B) continue;
+            T[(int64_t)p * B + r] = (pok && rok[q]) ? matern_eval(ms, geo_dist(geo, xr[q], yr[q], xp, yp)) : 0.0;
+        }
+    }
+}
+
+void launch_gen_rhs(double *st, const double *x, const double *y, int64_t n, int b, int64_t nt, const double *xn,
+                    const double *yn, int64_t m, int64_t chunks, gl_theta th, Geom geo, hipStream_t s)
+{
+    const unsigned grid = (unsigned)(chunks * nt);
+    switch (b) {
+    case 128: gen_rhs_kernel<128><<<grid, 256, 0, s>>>(st, x, y, n, nt, xn, yn, m, th, geo); break;
+    case 256: gen_rhs_kernel<256><<<grid, 256, 0, s>>>(st, x, y, n, nt, xn, yn, m, th, geo); break;
+    case 384: gen_rhs_kernel<384><<<grid, 256, 0, s>>>(st, x, y, n, nt, xn, yn, m, th, geo); break;
+    default: gen_rhs_kernel<512><<<grid, 256, 0, s>>>(st, x, y, n, nt, xn, yn, m, th, geo); break;
+    }
+}
 
 }  // namespace gl

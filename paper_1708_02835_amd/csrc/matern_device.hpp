@@ -25,6 +25,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include "common.hpp"
 #include "rgamma_table.hpp"
 
 namespace gl {
@@ -175,6 +176,25 @@ __host__ __device__ inline double dist2d(double x1, double y1, double x2, double
 {
     double dx = x1 - x2, dy = y1 - y2;
     return sqrt(dx * dx + dy * dy);
+}
+
+// Great-circle distance on a sphere of radius rho (Sec. 7.4): x = longitude,
+// y = latitude in degrees; the haversine h = sin²(Δφ/2) + cos φ1 cos φ2
+// sin²(Δλ/2) gives d = 2 rho asin(√h), h clamped to [0, 1].
+__host__ __device__ inline double gcd_dist(double x1, double y1, double x2, double y2, double rho)
+{
+    const double deg = M_PI / 180.0;
+    const double p1 = y1 * deg, p2 = y2 * deg;
+    const double sp = sin(0.5 * (p2 - p1));
+    const double sl = sin(0.5 * ((x2 - x1) * deg));
+    double h = sp * sp + cos(p1) * cos(p2) * sl * sl;
+    h = fmin(fmax(h, 0.0), 1.0);
+    return 2.0 * rho * asin(sqrt(h));
+}
+
+__host__ __device__ inline double geo_dist(const Geom &g, double x1, double y1, double x2, double y2)
+{
+    return g.metric ? gcd_dist(x1, y1, x2, y2, g.radius) : dist2d(x1, y1, x2, y2);
 }
 
 }  // namespace gl

@@ -6,8 +6,8 @@
 // tile (i, j) from the normalised tile norm
 //     ν_ij = ||Σ_ij||_F / sqrt(||Σ_ii||_F ||Σ_jj||_F)
 // measured when Σ is generated:
-//   class 0  FP64    diagonal tiles, tiles with i - j < band, and (FP32 mode)
-//                    tiles with ν_ij > tol_hi;
+//   class 0  FP64    diagonal tiles, tiles with i - j < band, and tiles
+//                    with ν_ij > tol_64 (both modes);
 //   class 1  FP32    FP32 matrix-core products (GL_MIXED_FP32);
 //   class 2  BF16x6  operands split into three bfloat16 parts a = h + m + l,
 //                    products hh + hm + mh + hl + lh + mm: about FP32 accuracy
@@ -37,7 +37,7 @@ enum { C64 = 0, C32 = 1, CB6 = 2, CB3 = 3, CB1 = 4, NCLASS = 5 };
 // ------------------------------------------------------------ precision map --
 
 __global__ void classify_kernel(const double *__restrict__ norm2, int64_t nt, int band, int mode,
-                                double tol_hi, double tol_lo, uint8_t *__restrict__ map)
+                                double tol_64, double tol_hi, double tol_lo, uint8_t *__restrict__ map)
 {
     const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (t >= tile_count(nt)) return;
@@ -53,7 +53,8 @@ __global__ void classify_kernel(const double *__restrict__ norm2, int64_t nt, in
         const double nii = sqrt(norm2[tile_index(i, i)]);
         const double njj = sqrt(norm2[tile_index(j, j)]);
         const double v = nij / sqrt(nii * njj);
-        if (mode == GL_MIXED_FP32) c = (v > tol_hi) ? C64 : C32;
+        if (v > tol_64) c = C64;
+        else if (mode == GL_MIXED_FP32) c = C32;
         else c = (v > tol_hi) ? CB6 : (v > tol_lo) ? CB3 : CB1;
     }
     map[t] = c;
@@ -444,8 +445,8 @@ static int build_lists(Work &w, const gl_opts &o, hipStream_t s, MixedPlan &plan
     const int64_t nt = w.nt;
     const int64_t tc = tile_count(nt);
     const int mode = w.precision;
-    const double tol_hi = o.tol_hi, tol_lo = o.tol_lo;
-    classify_kernel<<<(unsigned)ceil_div(tc, 256), 256, 0, s>>>(w.norm2, nt, o.band, mode, tol_hi, tol_lo, w.mv.map);
+    classify_kernel<<<(unsigned)ceil_div(tc, 256), 256, 0, s>>>(w.norm2, nt, o.band, mode, o.tol_64, o.tol_hi,
+                                                                o.tol_lo, w.mv.map);
     GL_HIP_TRY(hipGetLastError());
     std::vector<uint8_t> map((size_t)tc);
     GL_HIP_TRY(hipMemcpyAsync(map.data(), w.mv.map, (size_t)tc, hipMemcpyDeviceToHost, s));
@@ -487,7 +488,7 @@ static void class_updates(Work &w, int64_t k, int64_t j0, int64_t j1, const Mixe
 
 int mixed_factorize(Lanes &ln, Work &w, gl_theta th, const gl_opts &o, hipStream_t s, MixedPlan *plan_out)
 {
-    launch_gen_tiles(w.tiles, w.x, w.y, w.n, w.b, w.nt, th, w.norm2, s);
+    launch_gen_tiles(w.tiles, w.x, w.y, w.n, w.b, w.nt, th, geom_of(o), w.norm2, s);
     MixedPlan plan;
     int rc = build_lists(w, o, s, plan);
     if (rc != GL_OK) return rc;
@@ -496,9 +497,9 @@ int mixed_factorize(Lanes &ln, Work &w, gl_theta th, const gl_opts &o, hipStream
     GL_HIP_TRY(hipEventRecord(ln.fork, s));
     GL_HIP_TRY(hipStreamWaitEvent(la, ln.fork, 0));
     for (int64_t k = 0; k < w.nt; ++k) {
-        launch_potrf(w.tiles, w.b, k, w.n, w.info, w.logsum, w.dinv, s);
-        launch_fwd_diag(w.tiles, w.b, k, w.n, w.v, w.quad, w.dinv, w.info, s);
-        launch_trsm(w.tiles, w.b, w.nt, k, w.dinv, w.info, s);
+        launch_potrf(w.tiles, w.b, k, w.n, w.info, w.logsum, w.dinv_k(k), s);
+        launch_fwd_diag(w.tiles, w.b, k, w.n, w.v, w.quad, w.dinv_k(k), w.info, s);
+        launch_trsm(w.tiles, w.b, w.nt, k, w.dinv_k(k), w.info, s);
         launch_fwd_update(w.tiles, w.b, w.nt, k, w.v, w.info, s);
         if (k + 1 < w.nt) {
             launch_panel_convert(w, k, w.mv, s);

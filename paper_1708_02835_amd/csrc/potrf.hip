@@ -1,5 +1,5 @@
 // Diagonal-tile Cholesky factorisation (the POTRF task of the tile algorithm,
-// Sec. 4.2 and Alg. 2 step 3).
+// Sec. 5.2 and Alg. 2 step 3).
 //
 // One workgroup of 256 threads factors the b×b tile A_kk = L_kk L_kkᵀ in place
 // (lower triangle), right-looking over 64-column panels s:

@@ -1,5 +1,5 @@
 // Request queue for many concurrent likelihood clients (the optimiser callbacks
-// of Sec. 5.2, each asking for l(θ) at a new θ).
+// of Sec. 6.3, each asking for l(θ) at a new θ).
 //
 // A scheduler thread serves requests in two ways.
 //
@@ -228,7 +228,7 @@ int build_tick(lq_queue *q)
         d.x = w.x;
         d.y = w.y;
         d.v = w.v;
-        d.dinv = w.dinv;
+        d.dinv = w.dinv_k(r.k);
         d.logsum = w.logsum;
         d.quad = w.quad;
         d.info = w.info;
@@ -238,6 +238,7 @@ int build_tick(lq_queue *q)
         d.sy = d.sx + n;
         d.sz = d.sy + n;
         d.th = r.req->th;
+        d.geo = geom_of(r.req->o);
         d.n = w.n;
         d.nt = w.nt;
         d.npad = w.npad;

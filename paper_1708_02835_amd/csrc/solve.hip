@@ -395,4 +395,87 @@ void launch_tiles_to_dense(const double *tiles, int b, int64_t n, double *out, i
     tiles_to_dense_kernel<<<grid, 256, 0, s>>>(tiles, b, n, out, ld);
 }
 
+// Kriging variances from the solved right-hand sides U (layout of st):
+// part[(c·nt + i)·b + r] = Σ_p U(c, i)[r, p]² per tile (one workgroup per
+// tile, threads along r), then var[c·b + r] = θ1 - Σ_i part[...] in tile
+// order (fixed order, deterministic).
+template <int B>
+__global__ __launch_bounds__(256) void rhs_sq_partial_kernel(const double *__restrict__ st, double *__restrict__ part)
+{
+    const int64_t t = blockIdx.x;
+    const double *T = st + t * (int64_t)B * B;
+    for (int r = threadIdx.x; r < B; r += 256) {
+        double acc = 0.0;
+        for (int p = 0; p < B; ++p) {
+            const double u = T[(int64_t)p * B + r];
+            acc += u * u;
+        }
+        part[t * B + r] = acc;
+    }
+}
+
+__global__ void rhs_var_kernel(const double *__restrict__ part, int64_t nt, int b, int64_t m, double theta1,
+                               double *__restrict__ var)
+{
+    const int64_t kn = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (kn >= m) return;
+    const int64_t c = kn / b, r = kn % b;
+    double acc = 0.0;
+    for (int64_t i = 0; i < nt; ++i) acc += part[(c * nt + i) * b + r];
+    var[kn] = theta1 - acc;
+}
+
+void launch_rhs_variance(const double *st, int b, int64_t nt, int64_t chunks, int64_t m, double theta1,
+                         double *part, double *var, hipStream_t s)
+{
+    const unsigned grid = (unsigned)(chunks * nt);
+    switch (b) {
+    case 128: rhs_sq_partial_kernel<128><<<grid, 256, 0, s>>>(st, part); break;
+    case 256: rhs_sq_partial_kernel<256><<<grid, 256, 0, s>>>(st, part); break;
+    case 384: rhs_sq_partial_kernel<384><<<grid, 256, 0, s>>>(st, part); break;
+    default: rhs_sq_partial_kernel<512><<<grid, 256, 0, s>>>(st, part); break;
+    }
+    rhs_var_kernel<<<(unsigned)ceil_div(m, 256), 256, 0, s>>>(part, nt, b, m, theta1, var);
+}
+
+// Cross-validation helpers: gather three arrays through an index list, and
+// the mean squared difference of two vectors (one workgroup, fixed order).
+__global__ void gather3_kernel(const double *__restrict__ a, const double *__restrict__ b,
+                               const double *__restrict__ c, const int64_t *__restrict__ idx, int64_t m,
+                               double *__restrict__ oa, double *__restrict__ ob, double *__restrict__ oc)
+{
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= m) return;
+    const int64_t j = idx[i];
+    oa[i] = a[j];
+    ob[i] = b[j];
+    oc[i] = c[j];
+}
+
+void launch_gather3(const double *a, const double *b, const double *c, const int64_t *idx, int64_t m, double *oa,
+                    double *ob, double *oc, hipStream_t s)
+{
+    gather3_kernel<<<(unsigned)ceil_div(m, 256), 256, 0, s>>>(a, b, c, idx, m, oa, ob, oc);
+}
+
+__global__ __launch_bounds__(256) void mse_kernel(const double *__restrict__ p, const double *__restrict__ q,
+                                                  int64_t m, double *__restrict__ out)
+{
+    double acc = 0.0;
+    for (int64_t i = threadIdx.x; i < m; i += 256) {
+        const double d = p[i] - q[i];
+        acc += d * d;
+    }
+    __shared__ double red[4];
+    const double w = wave_sum(acc);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = w;
+    __syncthreads();
+    if (threadIdx.x == 0) *out = ((red[0] + red[1]) + (red[2] + red[3])) / (double)m;
+}
+
+void launch_mse(const double *p, const double *q, int64_t m, double *out, hipStream_t s)
+{
+    mse_kernel<<<1, 256, 0, s>>>(p, q, m, out);
+}
+
 }  // namespace gl

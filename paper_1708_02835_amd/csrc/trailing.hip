@@ -1,5 +1,5 @@
 // Trailing update of the right-looking tile Cholesky (the SYRK and GEMM tasks
-// of the tile algorithm, Sec. 4.2): after step k,
+// of the tile algorithm, Sec. 5.2): after step k,
 //   A_ij -= L_ik L_jkᵀ   for every tile k < j <= i < NT,
 // in FP64 on the matrix cores.
 //
@@ -7,7 +7,8 @@
 // Each workgroup (256 threads, 4 waves in a 2×2 arrangement) computes one
 // 128×128 block of one tile with K = b: the 128-row slices of L_ik and L_jk
 // are streamed through LDS in 16-column chunks, double-buffered, and every
-// wave accumulates a 64×64 block as 4×4 FP64 16x16x4 products.
+// wave accumulates a 64×64 block as 4×4 FP64 16x16x4 products, starting from
+// the block's current values.
 // Upper blocks of diagonal tiles are skipped (only the lower triangle of A_ii
 // is ever read).
 //
@@ -38,59 +39,65 @@ __device__ inline void trailing_tile(int64_t t, int64_t jbeg, int64_t nt, int64_
     i = j + (t - (c * m0 - c * (c - 1) / 2));
 }
 
-// One 128×128 block (rb, cb) of the update of tile (i, j) by panel column k.
-template <int B>
-__device__ __forceinline__ void trailing_block_body(double *__restrict__ tiles, int64_t k, int64_t i,
-                                                    int64_t j, int rb, int cb)
-{
-    const double *Ap = tiles + tile_offset(i, k, B) + rb * GB;
-    const double *Bp = tiles + tile_offset(j, k, B) + cb * GB;
-    double *C = tiles + tile_offset(i, j, B) + (int64_t)(cb * GB) * B + rb * GB;
+// One 128×128 block (rb, cb) of C -= A Bᵀ, all three b×b column-major (ld b).
+// The accumulators start from the negated C block and accumulate A Bᵀ - C;
+// the block is written once at the end, negated back (no read-modify-write
+// after the K loop).  Loader lanes 16·c .. 16·c+15 move 256
+// contiguous bytes of one column, so the LDS stores are conflict-free; LDS
+// rows are padded to 144 doubles so that the two 16-lane halves of an MFMA
+// operand read (rows k and k+1) fall in different banks.
+constexpr int GP = GB + 16;  // LDS row pitch (doubles)
 
-    __shared__ double As[2][GK][GB];
-    __shared__ double Bs[2][GK][GB];
+template <int B>
+__device__ __forceinline__ void trailing_core(const double *__restrict__ At, const double *__restrict__ Bt,
+                                              double *__restrict__ Ct, int rb, int cb)
+{
+    const double *Ap = At + rb * GB;
+    const double *Bp = Bt + cb * GB;
+    double *C = Ct + (int64_t)(cb * GB) * B + rb * GB;
+
+    __shared__ double As[2][GK][GP];
+    __shared__ double Bs[2][GK][GP];
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = tid >> 6;
     const int wm = wave >> 1, wn = wave & 1;
-    const int lc = tid >> 4;         // chunk column 0..15
-    const int lr = (tid & 15) * 8;   // chunk row 0..120, 8 consecutive rows
+    const int lc = tid >> 4;        // chunk column 0..15
+    const int le = (tid & 15) * 2;  // rows le + 32 q, le + 32 q + 1 (q = 0..3)
 
+    d2 ra[4], rbv[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        ra[q] = *reinterpret_cast<const d2 *>(Ap + (int64_t)lc * B + le + 32 * q);
+        rbv[q] = *reinterpret_cast<const d2 *>(Bp + (int64_t)lc * B + le + 32 * q);
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        *reinterpret_cast<d2 *>(&As[0][lc][le + 32 * q]) = ra[q];
+        *reinterpret_cast<d2 *>(&Bs[0][lc][le + 32 * q]) = rbv[q];
+    }
+    __syncthreads();
+    // the C block, loaded once the first chunk's staging registers are free
     d4 acc[4][4];
 #pragma unroll
     for (int a = 0; a < 4; ++a)
 #pragma unroll
-        for (int b = 0; b < 4; ++b) acc[a][b] = (d4){0.0, 0.0, 0.0, 0.0};
-
-    d2 ra[4], rbv[4];
-    {
-        const d2 *pa = reinterpret_cast<const d2 *>(Ap + (int64_t)lc * B + lr);
-        const d2 *pb = reinterpret_cast<const d2 *>(Bp + (int64_t)lc * B + lr);
+        for (int b = 0; b < 4; ++b) {
+            const int row = wm * 64 + a * 16 + mfma_col(lane);
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            ra[q] = pa[q];
-            rbv[q] = pb[q];
+            for (int r = 0; r < 4; ++r) acc[a][b][r] = -C[(int64_t)(wn * 64 + b * 16 + mfma_row(lane, r)) * B + row];
         }
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            *reinterpret_cast<d2 *>(&As[0][lc][lr + 2 * q]) = ra[q];
-            *reinterpret_cast<d2 *>(&Bs[0][lc][lr + 2 * q]) = rbv[q];
-        }
-    }
-    __syncthreads();
 
     constexpr int NK = B / GK;
     for (int kc = 0; kc < NK; ++kc) {
         const int cur = kc & 1;
         if (kc + 1 < NK) {
             const int64_t col = (int64_t)(kc + 1) * GK + lc;
-            const d2 *pa = reinterpret_cast<const d2 *>(Ap + col * B + lr);
-            const d2 *pb = reinterpret_cast<const d2 *>(Bp + col * B + lr);
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                ra[q] = pa[q];
-                rbv[q] = pb[q];
+                ra[q] = *reinterpret_cast<const d2 *>(Ap + col * B + le + 32 * q);
+                rbv[q] = *reinterpret_cast<const d2 *>(Bp + col * B + le + 32 * q);
             }
         }
 #pragma unroll
@@ -111,25 +118,30 @@ __device__ __forceinline__ void trailing_block_body(double *__restrict__ tiles, 
         if (kc + 1 < NK) {
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                *reinterpret_cast<d2 *>(&As[cur ^ 1][lc][lr + 2 * q]) = ra[q];
-                *reinterpret_cast<d2 *>(&Bs[cur ^ 1][lc][lr + 2 * q]) = rbv[q];
+                *reinterpret_cast<d2 *>(&As[cur ^ 1][lc][le + 32 * q]) = ra[q];
+                *reinterpret_cast<d2 *>(&Bs[cur ^ 1][lc][le + 32 * q]) = rbv[q];
             }
         }
         __syncthreads();
     }
 
 #pragma unroll
-    for (int a = 0; a < 4; ++a) {
+    for (int a = 0; a < 4; ++a)
 #pragma unroll
         for (int b = 0; b < 4; ++b) {
             const int row = wm * 64 + a * 16 + mfma_col(lane);
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int64_t col = wn * 64 + b * 16 + mfma_row(lane, r);
-                C[col * B + row] -= acc[a][b][r];
-            }
+            for (int r = 0; r < 4; ++r) C[(int64_t)(wn * 64 + b * 16 + mfma_row(lane, r)) * B + row] = -acc[a][b][r];
         }
-    }
+}
+
+// One 128×128 block (rb, cb) of the update of tile (i, j) by panel column k.
+template <int B>
+__device__ __forceinline__ void trailing_block_body(double *__restrict__ tiles, int64_t k, int64_t i,
+                                                    int64_t j, int rb, int cb)
+{
+    trailing_core<B>(tiles + tile_offset(i, k, B), tiles + tile_offset(j, k, B), tiles + tile_offset(i, j, B),
+                     rb, cb);
 }
 
 template <int B>
@@ -229,6 +241,43 @@ void launch_trailing_list(double *tiles, int b, int64_t k, const int2 *list, int
     case 256: trailing_f64_kernel<256><<<(unsigned)grid, 256, 0, s>>>(tiles, k, 0, 0, nblocks, info, crit, list); break;
     case 384: trailing_f64_kernel<384><<<(unsigned)grid, 256, 0, s>>>(tiles, k, 0, 0, nblocks, info, crit, list); break;
     default: trailing_f64_kernel<512><<<(unsigned)grid, 256, 0, s>>>(tiles, k, 0, 0, nblocks, info, crit, list); break;
+    }
+}
+
+// Many right-hand sides, update after diagonal step k (layout of st as for
+// the multi-RHS diagonal solve): S(c, i) -= U(c, k) L_ikᵀ for every chunk c
+// and tile row i > k.  Blocks of one tile row i (sharing L_ik) are adjacent.
+template <int B>
+__global__ __launch_bounds__(256, 2) void mrhs_update_kernel(const double *__restrict__ tiles, double *__restrict__ st,
+                                                             int64_t nt, int64_t k, int64_t chunks, int64_t nblocks)
+{
+    constexpr int SB = B / GB;
+    constexpr int SUB = SB * SB;
+    const int64_t G = gridDim.x;
+    const int64_t g = blockIdx.x;
+    const int64_t lid = (g & 7) * (G >> 3) + (g >> 3);
+    if (lid >= nblocks) return;
+    const int sub = (int)(lid % SUB);
+    const int64_t tc = lid / SUB;
+    const int64_t c = tc % chunks;
+    const int64_t i = k + 1 + tc / chunks;
+    const int64_t bb = (int64_t)B * B;
+    trailing_core<B>(st + (c * nt + k) * bb, tiles + tile_offset(i, k, B), st + (c * nt + i) * bb, sub / SB,
+                     sub % SB);
+}
+
+void launch_mrhs_update(const double *tiles, double *st, int b, int64_t nt, int64_t k, int64_t chunks,
+                        hipStream_t s)
+{
+    const int64_t m = nt - k - 1;
+    if (m <= 0) return;
+    const int64_t nblocks = m * chunks * (b / GB) * (b / GB);
+    const int64_t grid = ceil_div(nblocks, 8) * 8;
+    switch (b) {
+    case 128: mrhs_update_kernel<128><<<(unsigned)grid, 256, 0, s>>>(tiles, st, nt, k, chunks, nblocks); break;
+    case 256: mrhs_update_kernel<256><<<(unsigned)grid, 256, 0, s>>>(tiles, st, nt, k, chunks, nblocks); break;
+    case 384: mrhs_update_kernel<384><<<(unsigned)grid, 256, 0, s>>>(tiles, st, nt, k, chunks, nblocks); break;
+    default: mrhs_update_kernel<512><<<(unsigned)grid, 256, 0, s>>>(tiles, st, nt, k, chunks, nblocks); break;
     }
 }
 

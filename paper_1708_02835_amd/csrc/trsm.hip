@@ -1,4 +1,4 @@
-// Panel triangular solve (the TRSM task of the tile algorithm, Sec. 4.2):
+// Panel triangular solve (the TRSM task of the tile algorithm, Sec. 5.2):
 // L_ik = A_ik L_kk⁻ᵀ for every tile i > k of column k.
 //
 // Workgroup (i, strip) owns 64 rows of tile (i, k), the only writer of those
@@ -20,18 +20,13 @@ constexpr int TB = 64;  // column block and strip height
 constexpr int TC = 16;  // k chunk
 constexpr int TP = TB + 16;  // LDS row pitch (bank spread of the 16-lane groups)
 
-// Strip `strip` (64 rows) of tile i = k + 1 + tix.
+// Strip `strip` (64 rows) of X <- X L⁻ᵀ, X and L b×b column-major (ld b),
+// dinv the inverses of L's 64×64 diagonal blocks.
 template <int B>
-__device__ __forceinline__ void trsm_body(double *__restrict__ tiles, int64_t k,
-                                          const double *__restrict__ dinv,
-                                          const int64_t *__restrict__ info, int64_t tix, int strip)
+__device__ __forceinline__ void trsm_core(const double *__restrict__ L, double *__restrict__ X,
+                                          const double *__restrict__ dinv, int strip)
 {
-    if (*info != 0) return;
-    __builtin_amdgcn_s_setprio(3);  // critical path of the step schedule
-    const int64_t i = k + 1 + tix;
     const int r0 = strip * TB;
-    const double *L = tiles + tile_offset(k, k, B);
-    double *X = tiles + tile_offset(i, k, B);
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = tid >> 6;
@@ -126,6 +121,17 @@ __device__ __forceinline__ void trsm_body(double *__restrict__ tiles, int64_t k,
     }
 }
 
+// Strip `strip` of panel tile i = k + 1 + tix.
+template <int B>
+__device__ __forceinline__ void trsm_body(double *__restrict__ tiles, int64_t k,
+                                          const double *__restrict__ dinv,
+                                          const int64_t *__restrict__ info, int64_t tix, int strip)
+{
+    if (*info != 0) return;
+    __builtin_amdgcn_s_setprio(3);  // critical path of the step schedule
+    trsm_core<B>(tiles + tile_offset(k, k, B), tiles + tile_offset(k + 1 + tix, k, B), dinv, strip);
+}
+
 template <int B>
 __global__ __launch_bounds__(256) void trsm_kernel(double *__restrict__ tiles, int64_t k,
                                                    const double *__restrict__ dinv,
@@ -163,6 +169,30 @@ void launch_trsm_batched(int b, const BatchReq *d, int count, int64_t blocks, hi
     if (blocks <= 0) return;
     if (b == 128) trsm_batched_kernel<128><<<(unsigned)blocks, 256, 0, s>>>(d, count);
     else trsm_batched_kernel<256><<<(unsigned)blocks, 256, 0, s>>>(d, count);
+}
+
+// Many right-hand sides (kriging variances, Eq. 4): U = L⁻¹ S is solved in
+// the transposed form Uᵀ L_kkᵀ = Sᵀ, the panel form above.  st holds chunks
+// of b right-hand sides as nt tiles each (tile (c, i): b×b column-major, row
+// = right-hand side, column = location of tile i).  Diagonal step k solves
+// tile (c, k) of every chunk c.
+template <int B>
+__global__ __launch_bounds__(256) void mrhs_diag_kernel(const double *__restrict__ tiles, double *__restrict__ st,
+                                                        int64_t nt, int64_t k, const double *__restrict__ dinv)
+{
+    trsm_core<B>(tiles + tile_offset(k, k, B), st + ((int64_t)blockIdx.x * nt + k) * B * B, dinv, blockIdx.y);
+}
+
+void launch_mrhs_diag(const double *tiles, double *st, int b, int64_t nt, int64_t k, const double *dinv,
+                      int64_t chunks, hipStream_t s)
+{
+    dim3 grid((unsigned)chunks, (unsigned)(b / TB));
+    switch (b) {
+    case 128: mrhs_diag_kernel<128><<<grid, 256, 0, s>>>(tiles, st, nt, k, dinv); break;
+    case 256: mrhs_diag_kernel<256><<<grid, 256, 0, s>>>(tiles, st, nt, k, dinv); break;
+    case 384: mrhs_diag_kernel<384><<<grid, 256, 0, s>>>(tiles, st, nt, k, dinv); break;
+    default: mrhs_diag_kernel<512><<<grid, 256, 0, s>>>(tiles, st, nt, k, dinv); break;
+    }
 }
 
 }  // namespace gl

@@ -53,9 +53,20 @@ def test_status_strings_and_defaults():
         assert g.gl_status_string(st) != "unknown status"
     o = g.gl_opts_default()
     assert (o.precision, o.tile, o.keep_factor, o.band, o.reorder) == (g.GL_FP64, 0, 0, 2, -1)
-    assert o.tol_hi < 0 and o.tol_lo < 0
+    assert o.tol_hi < 0 and o.tol_lo < 0 and o.tol_64 < 0
+    assert o.metric == g.GL_EUCLIDEAN and o.radius == 6371.0
     c = g.lq_config_default()
     assert c.max_inflight >= 1 and 1 <= c.streams <= 8
+
+
+def test_opts_layout_matches_header():
+    """The ctypes struct mirrors gl_opts field by field (names and order)."""
+    import re
+    import paper_1708_02835_amd as g
+    hdr = open(os.path.join(ROOT, "include", "geolik.h")).read()
+    body = hdr[hdr.index("typedef struct {", hdr.index("GL_GREAT_CIRCLE")):hdr.index("} gl_opts;")]
+    names = re.findall(r"^\s*(?:int32_t|double)\s+(\w+);", body, re.M)
+    assert names == [f for f, _ in g.gl_opts._fields_]
 
 
 @pytest.mark.parametrize("n,tile", [(1, 128), (1600, 128), (40000, 512), (100000, 512), (100001, 256)])
@@ -67,7 +78,7 @@ def test_footprint_formula(n, tile):
     p2 = 1
     while p2 < n:
         p2 *= 2
-    vec = (3 * nt * tile + 2 * nt + nt * (nt + 1) // 2 + 64 * tile + 16 + p2 + 4) * 8
+    vec = (3 * nt * tile + 2 * nt + nt * (nt + 1) // 2 + 64 * nt * tile + 16 + p2 + 4) * 8
     assert g.gl_footprint_bytes(n, tile, g.GL_FP64) == tiles + vec
     # mixed modes add the double-buffered panel copies, the tile lists and the map
     tc = nt * (nt + 1) // 2

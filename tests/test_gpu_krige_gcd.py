@@ -1,0 +1,193 @@
+"""GPU parity of the great-circle distance (Sec. 7.4) and of the kriging
+prediction variances (Eq. 4) against the oracle, on seeded inputs.
+
+Great-circle inputs: a jittered grid mapped to a 15° x 15° longitude /
+latitude box, distances in km on a sphere of radius 6371, range θ2 in km.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import geoinputs
+import oracle
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+R = 6371.0
+
+
+@pytest.fixture(scope="module")
+def g():
+    import paper_1708_02835_amd as pkg
+    pkg.lib()
+    return pkg
+
+
+@pytest.fixture(scope="module")
+def ctx(g):
+    c = g.Context(0)
+    yield c
+    c.close()
+
+
+def dev(a):
+    return torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+
+
+def region(n, seed):
+    x, y = geoinputs.jittered_grid(n, seed)
+    return -100.0 + 15.0 * x, 30.0 + 15.0 * y
+
+
+def gc_opts(g, **kw):
+    return g.gl_opts_default(metric=g.GL_GREAT_CIRCLE, radius=R, **kw)
+
+
+@pytest.mark.parametrize("theta", [(1.0, 150.0, 0.5), (1.3, 90.0, 1.5), (0.7, 200.0, 0.8)])
+def test_gcd_matern_generate_elementwise(g, ctx, theta):
+    x1, y1 = region(300, 1)
+    x2, y2 = region(170, 2)
+    x2[:3], y2[:3] = x1[:3], y1[:3]  # zero distances
+    ref = oracle.cov_matrix(x1, y1, x2, y2, theta, metric=oracle.GREAT_CIRCLE, radius=R)
+    got = g.matern_generate(ctx, dev(x1), dev(y1), dev(x2), dev(y2), theta, gc_opts(g)).T.cpu().numpy()
+    assert np.max(np.abs(got - ref)) <= 1e-12 * theta[0]
+
+
+@pytest.mark.parametrize("n,tile", [(1600, 128), (1100, 256), (900, 512)])
+@pytest.mark.parametrize("theta", [(1.0, 150.0, 0.5), (1.2, 100.0, 1.5)])
+def test_gcd_loglik_parity(g, ctx, n, tile, theta):
+    x, y = region(n, 3)
+    z = geoinputs.normal_vector(n, 3)
+    ref = oracle.loglik(x, y, z, theta, metric=oracle.GREAT_CIRCLE, radius=R)
+    assert ref[3] == 0
+    r = g.loglik_eval(ctx, dev(x), dev(y), dev(z), theta, gc_opts(g, tile=tile))
+    assert r["status"] == g.GL_OK
+    assert abs(r["loglik"] - ref[0]) <= 1e-10 * abs(ref[0])
+    assert abs(r["logdet"] - ref[1]) <= 1e-10 * abs(ref[1])
+
+
+def test_gcd_synth_parity(g, ctx):
+    theta = (1.0, 150.0, 0.5)
+    x, y = region(700, 4)
+    e = geoinputs.normal_vector(700, 4)
+    ref, info = oracle.synth(x, y, e, theta, metric=oracle.GREAT_CIRCLE, radius=R)
+    assert info == 0
+    zg, ginfo = g.synth_generate(ctx, dev(x), dev(y), dev(e), theta, opts=gc_opts(g, tile=256))
+    assert ginfo == 0
+    assert np.max(np.abs(zg.cpu().numpy() - ref)) <= 1e-12 * np.max(np.abs(ref))
+
+
+def test_gcd_rejects_bad_radius(g, ctx):
+    x, y = region(50, 5)
+    for radius in (0.0, -1.0, math.inf):
+        with pytest.raises(g.GeolikError):
+            g.loglik_eval(ctx, dev(x), dev(y), dev(x), (1.0, 100.0, 0.5),
+                          g.gl_opts_default(metric=g.GL_GREAT_CIRCLE, radius=radius))
+
+
+CASES = [
+    # (metric, n, tile, m, theta)
+    (0, 1500, 128, 1061, (1.0, 0.1, 0.5)),   # two groups of 8 chunks of 128 right-hand sides
+    (0, 1300, 512, 300, (1.3, 0.07, 1.5)),   # ragged tile and chunk
+    (0, 1000, 384, 50, (0.9, 0.12, 1.0)),    # general ν (Bessel path), tile 384
+    (1, 1200, 256, 700, (1.0, 150.0, 0.5)),
+]
+
+
+@pytest.mark.parametrize("metric,n,tile,m,theta", CASES)
+def test_krige_variance_parity(g, ctx, metric, n, tile, m, theta):
+    if metric:
+        x, y = region(n, 6)
+        xn, yn = region(m, 7)
+    else:
+        x, y = geoinputs.jittered_grid(n, 6)
+        xn, yn = geoinputs.uniform_points(m, 7)
+    z = geoinputs.normal_vector(n, 6)
+    xn[:2], yn[:2] = x[[3, n - 1]], y[[3, n - 1]]  # observed locations: variance 0
+    ref, ref_var, info = oracle.krige(x, y, z, xn, yn, theta, return_variance=True, metric=metric, radius=R)
+    assert info == 0
+    opts = g.gl_opts_default(tile=tile, keep_factor=1, metric=metric, radius=R)
+    r = g.loglik_eval(ctx, dev(x), dev(y), dev(z), theta, opts)
+    try:
+        pred, var = g.krige_predict(ctx, r["factor"], dev(xn), dev(yn), return_variance=True)
+        pred_only = g.krige_predict(ctx, r["factor"], dev(xn), dev(yn))
+    finally:
+        g.gl_factor_release(ctx, r["factor"])
+    pred, var, pred_only = pred.cpu().numpy(), var.cpu().numpy(), pred_only.cpu().numpy()
+    cond = np.linalg.cond(oracle.cov_symmetric(x, y, theta, metric=metric, radius=R))
+    tol = max(1e-10, 1e-15 * cond)
+    assert np.array_equal(pred, pred_only)
+    assert np.max(np.abs(pred - ref)) <= tol * np.max(np.abs(z))
+    assert np.max(np.abs(var - ref_var)) <= tol * theta[0], np.max(np.abs(var - ref_var))
+    assert np.all(np.abs(var[:2]) <= tol * theta[0])
+
+
+def test_krige_variance_mixed_factor(g, ctx):
+    """Variances from a BF16-mode factor against the FP64 ones: the stated
+    mixed bound of 1e-4, relative to θ1."""
+    theta = (1.0, 0.1, 0.5)
+    n, m = 2048, 400
+    x, y = geoinputs.jittered_grid(n, 8)
+    z = geoinputs.normal_vector(n, 8)
+    xn, yn = geoinputs.uniform_points(m, 8)
+    out = {}
+    for prec in (0, 2):
+        r = g.loglik_eval(ctx, dev(x), dev(y), dev(z), theta, g.gl_opts_default(precision=prec, tile=256,
+                                                                                  keep_factor=1))
+        try:
+            out[prec] = [t.cpu().numpy() for t in g.krige_predict(ctx, r["factor"], dev(xn), dev(yn),
+                                                                  return_variance=True)]
+        finally:
+            g.gl_factor_release(ctx, r["factor"])
+    assert np.max(np.abs(out[2][1] - out[0][1])) <= 1e-4 * theta[0]
+    assert np.max(np.abs(out[2][0] - out[0][0])) <= 1e-4 * np.max(np.abs(z))
+
+
+def test_serve_gcd_bit_identical(g, ctx):
+    theta = (1.0, 150.0, 0.5)
+    x, y = region(900, 9)
+    z = geoinputs.normal_vector(900, 9)
+    ds = g.gl_dataset_register(ctx, dev(x), dev(y), dev(z))
+    q = g.lq_create(ctx)
+    try:
+        res = g.lq_wait(q, g.lq_submit(q, ds, theta, gc_opts(g)), int(60e6))
+    finally:
+        g.lq_destroy(q)
+        g.gl_dataset_release(ctx, ds)
+    ref = g.loglik_eval(ctx, dev(x), dev(y), dev(z), theta, gc_opts(g, tile=256))
+    assert res["status"] == g.GL_OK and res["loglik"] == ref["loglik"]
+
+
+@pytest.mark.parametrize("metric", [0, 1])
+def test_krige_cv_parity(g, ctx, metric):
+    """k-fold cross-validation (k = 5): per-fold MSE against the oracle's
+    kriging of the same folds; the fold assignment is an input."""
+    n, k = 600, 5
+    if metric:
+        x, y = region(n, 10)
+        theta = (1.0, 150.0, 0.5)
+    else:
+        x, y = geoinputs.jittered_grid(n, 10)
+        theta = (1.0, 0.1, 0.5)
+    e = geoinputs.normal_vector(n, 10)
+    z, info = oracle.synth(x, y, e, theta, metric=metric, radius=R)
+    assert info == 0
+    folds = np.random.Generator(np.random.PCG64(11)).permutation(np.arange(n) % k).astype(np.int32)
+    mse, st = g.krige_cv(ctx, dev(x), dev(y), dev(z), theta, folds,
+                         g.gl_opts_default(tile=128, metric=metric, radius=R))
+    assert st == g.GL_OK and len(mse) == k
+    for f in range(k):
+        known, miss = folds != f, folds == f
+        pred, info = oracle.krige(x[known], y[known], z[known], x[miss], y[miss], theta, metric=metric, radius=R)
+        ref = float(np.mean((pred - z[miss]) ** 2))
+        assert abs(mse[f] - ref) <= 1e-9 * ref, (f, mse[f], ref)
+
+
+def test_krige_cv_rejects_bad_folds(g, ctx):
+    x, y = geoinputs.jittered_grid(100, 12)
+    z = geoinputs.normal_vector(100, 12)
+    for folds in (np.zeros(100), np.r_[np.zeros(99), [5]], np.r_[np.zeros(50), np.full(50, 2)]):
+        with pytest.raises(g.GeolikError):
+            g.krige_cv(ctx, dev(x), dev(y), dev(z), (1.0, 0.1, 0.5), folds.astype(np.int32))

@@ -128,7 +128,7 @@ FORCED = [
 def test_mixed_forced_class(g, ctx, name, prec, thi, tlo, cls, bound):
     theta = (1.0, 0.1, 0.5)
     x, y, z, ref = _problem(theta)
-    opts = g.gl_opts_default(precision=prec, tile=256, band=1, tol_hi=thi, tol_lo=tlo)
+    opts = g.gl_opts_default(precision=prec, tile=256, band=1, tol_64=math.inf, tol_hi=thi, tol_lo=tlo)
     r = g.loglik_eval(ctx, dev(x), dev(y), dev(z), theta, opts)
     assert r["status"] == g.GL_OK
     st = g.gl_precision_stats(ctx)
@@ -159,7 +159,8 @@ def test_mixed_all_tile_sizes_ragged(g, ctx, tile, prec):
     # every off-band tile in the FP32-grade class of the mode (FP32, or BF16x6)
     thi = math.inf if prec == 1 else 0.0
     r = g.loglik_eval(ctx, dev(x), dev(y), dev(z), theta,
-                      g.gl_opts_default(precision=prec, tile=tile, band=1, tol_hi=thi, tol_lo=0.0))
+                      g.gl_opts_default(precision=prec, tile=tile, band=1, tol_64=math.inf, tol_hi=thi,
+                                        tol_lo=0.0))
     assert r["status"] == g.GL_OK
     assert rel(r["loglik"], ref[0]) <= 1e-5
 
@@ -173,7 +174,7 @@ def test_mixed_not_spd(g, ctx):
     bfloat16 is indefinite after rounding, and must fail."""
     x, y = geoinputs.jittered_grid(N_MIX, 5)
     z = geoinputs.normal_vector(N_MIX, 5)
-    opts = g.gl_opts_default(precision=2, tile=256, band=1, tol_hi=math.inf, tol_lo=math.inf)
+    opts = g.gl_opts_default(precision=2, tile=256, band=1, tol_64=math.inf, tol_hi=math.inf, tol_lo=math.inf)
     r = g.loglik_eval(ctx, dev(x), dev(y), dev(z), (1.0, 0.3, 2.5), opts)
     assert r["status"] == g.GL_NOT_SPD and r["loglik"] == -math.inf and r["info"] > 0
     # the context stays usable after a failure

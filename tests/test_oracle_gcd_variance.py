@@ -1,4 +1,4 @@
-"""Pins of the oracle's great-circle distance (Sec. 7, haversine formula) and
+"""Pins of the oracle's great-circle distance (Sec. 7.4, haversine formula) and
 prediction variance (Sec. 2.3, Eq. 4), each against something other than the
 oracle's own formula: exact arcs, the 3-D chord identity, closed forms for
 one observed point, dense linear algebra, and limits."""
