@@ -128,7 +128,8 @@ def mixed_legs(g, ctx, xd, yd, ed, zd, theta, theta_b, args, res64, t64, log):
                          "rel_err_loglik": abs(r["loglik"] - r64["loglik"]) / abs(r64["loglik"]),
                          "rel_err_logdet": abs(r["logdet"] - r64["logdet"]) / abs(r64["logdet"]),
                          "status": r["status"],
-                         "work_frac": {k: round(v["work_frac"], 4) for k, v in stats.items()}}
+                         "work_frac": {k: round(stats[k]["work_frac"], 4) for k in g.PRECISION_CLASSES},
+                         "thresholds": stats["thresholds"]}
             log(f"mixed {label} {name}: {dt:.3f} s, x{t64b / dt:.2f}, rel err {leg[name]['rel_err_loglik']:.2e}")
         out[label] = leg
     return out

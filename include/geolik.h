@@ -68,8 +68,13 @@ typedef enum {
  *   GL_MIXED_BF16: bfloat16 products with FP32 accumulation, operands split
  *                  in three parts (about FP32 accuracy) when ν_ij > tol_hi,
  *                  two parts when tol_lo < ν_ij <= tol_hi, one part below.
- * Negative thresholds take the defaults tol_64 = 0.3, tol_hi = 1e-2,
- * tol_lo = 1e-4.
+ * Thresholds left negative (the default) are adaptive: with the accuracy
+ * target ε (default 1e-4) and ρ = min_r L_rr² / θ1 over the first diagonal
+ * tile (its binary64 POTRF runs before any off-band update; ρ is the smallest
+ * conditional variance ratio of those locations, small when neighbours
+ * explain most of a value and the Schur complements cancel), a class with
+ * unit roundoff u is used for tile (i, j) only while ν_ij u <= ε ρ:
+ * tol_64 = ε ρ / 2⁻²⁴, tol_hi = ε ρ / 2⁻¹⁶, tol_lo = ε ρ / 2⁻⁸.
  * Tiles with i - j < band stay binary64.
  *
  * Distance (Sec. 2 and Sec. 7.4): metric GL_EUCLIDEAN uses r = ||s_i - s_j||
@@ -87,10 +92,11 @@ typedef struct {
                             GL_FP64); 0: input order; 1: Morton order.  l(θ) does not depend
                             on the order; kept factors are in the order used. */
     int32_t metric;      /* GL_EUCLIDEAN (default) or GL_GREAT_CIRCLE */
-    double tol_hi;       /* GL_MIXED_BF16: see above (negative: default) */
-    double tol_lo;       /* GL_MIXED_BF16: see above (negative: default) */
+    double tol_hi;       /* GL_MIXED_BF16: see above (negative: adaptive) */
+    double tol_lo;       /* GL_MIXED_BF16: see above (negative: adaptive) */
     double radius;       /* GL_GREAT_CIRCLE: sphere radius (> 0; default 6371, the Earth in km) */
-    double tol_64;       /* mixed modes: see above (negative: default) */
+    double tol_64;       /* mixed modes: see above (negative: adaptive) */
+    double accuracy;     /* mixed modes: ε of the adaptive thresholds (negative: 1e-4) */
 } gl_opts;
 
 /* Result of one likelihood evaluation, host memory. */
@@ -273,9 +279,10 @@ int gl_morton_order(gl_context *ctx, const double *x, const double *y, int64_t n
 
 /* Precision map of the last mixed-precision loglik_eval on this context:
  * tiles per class and work per class (Σ over tiles of the trailing updates
- * they receive), classes 0 FP64, 1 FP32, 2 BF16x6, 3 BF16x3, 4 BF16.  Either
- * pointer may be NULL; each receives 5 values. */
-int gl_precision_stats(gl_context *ctx, int64_t *tiles_h, double *work_h);
+ * they receive), classes 0 FP64, 1 FP32, 2 BF16x6, 3 BF16x3, 4 BF16 (5 values
+ * each), and thresholds_h = {ρ, tol_64, tol_hi, tol_lo} as used (4 values).
+ * Any pointer may be NULL. */
+int gl_precision_stats(gl_context *ctx, int64_t *tiles_h, double *work_h, double *thresholds_h);
 
 /* Runs a built-in device self-check `which` and writes up to `cap` doubles of
  * output to out_h: 0 = the lane layout of the FP64 16x16x4 matrix-core

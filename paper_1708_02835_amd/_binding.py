@@ -44,7 +44,7 @@ class gl_opts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("tile", ctypes.c_int32), ("keep_factor", ctypes.c_int32),
                 ("band", ctypes.c_int32), ("reorder", ctypes.c_int32), ("metric", ctypes.c_int32),
                 ("tol_hi", ctypes.c_double), ("tol_lo", ctypes.c_double), ("radius", ctypes.c_double),
-                ("tol_64", ctypes.c_double)]
+                ("tol_64", ctypes.c_double), ("accuracy", ctypes.c_double)]
 
 
 class gl_result(ctypes.Structure):
@@ -97,7 +97,7 @@ _SIGNATURES = {
     "gl_selftest": (_I32, [_P, _I32, ctypes.POINTER(_D), _I64]),
     "gl_profile_enable": (_I32, [_P, _I32]),
     "gl_morton_order": (_I32, [_P, _P, _P, _I64, _P, _P]),
-    "gl_precision_stats": (_I32, [_P, ctypes.POINTER(_I64), ctypes.POINTER(_D)]),
+    "gl_precision_stats": (_I32, [_P, ctypes.POINTER(_I64), ctypes.POINTER(_D), ctypes.POINTER(_D)]),
     "gl_profile_read": (_I32, [_P, ctypes.POINTER(_D), ctypes.POINTER(_D), ctypes.POINTER(_I64)]),
 }
 
@@ -395,6 +395,9 @@ def gl_precision_stats(ctx: Context) -> dict:
     """Tiles and trailing-update work per precision class of the last mixed evaluation."""
     tiles = (_I64 * 5)()
     work = (_D * 5)()
-    _check(lib().gl_precision_stats(ctx.handle, tiles, work), "gl_precision_stats")
+    thr = (_D * 4)()
+    _check(lib().gl_precision_stats(ctx.handle, tiles, work, thr), "gl_precision_stats")
     tot = sum(work) or 1.0
-    return {c: {"tiles": int(tiles[i]), "work_frac": work[i] / tot} for i, c in enumerate(PRECISION_CLASSES)}
+    out = {c: {"tiles": int(tiles[i]), "work_frac": work[i] / tot} for i, c in enumerate(PRECISION_CLASSES)}
+    out["thresholds"] = {"rho": thr[0], "tol_64": thr[1], "tol_hi": thr[2], "tol_lo": thr[3]}
+    return out

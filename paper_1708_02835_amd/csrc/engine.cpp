@@ -231,6 +231,7 @@ void gl_opts_default(gl_opts *o)
     o->tol_hi = -1.0;
     o->tol_lo = -1.0;
     o->tol_64 = -1.0;
+    o->accuracy = -1.0;
     o->radius = 6371.0;
 }
 
@@ -340,7 +341,7 @@ bool valid_opts(const gl_opts &o)
     if (o.tile != 0 && o.tile != 128 && o.tile != 256 && o.tile != 384 && o.tile != 512) return false;
     if (o.reorder < -1 || o.reorder > 1) return false;
     if (o.precision != GL_FP64 && o.band < 1) return false;
-    if (isnan(o.tol_hi) || isnan(o.tol_lo) || isnan(o.tol_64)) return false;
+    if (isnan(o.tol_hi) || isnan(o.tol_lo) || isnan(o.tol_64) || isnan(o.accuracy)) return false;
     return true;
 }
 
@@ -361,11 +362,7 @@ void stage_inputs(Work &w, const double *x, const double *y, const double *z, in
 gl_opts resolved_opts(const gl_opts &in)
 {
     gl_opts o = in;
-    if (o.precision != GL_FP64) {
-        if (o.tol_64 < 0) o.tol_64 = 0.3;
-        if (o.tol_hi < 0) o.tol_hi = 1e-2;
-        if (o.tol_lo < 0) o.tol_lo = 1e-4;
-    }
+    if (o.accuracy < 0) o.accuracy = 1e-4;
     if (o.reorder < 0) o.reorder = (o.precision == GL_FP64) ? 0 : 1;
     return o;
 }
@@ -667,13 +664,15 @@ int gl_morton_order(gl_context *ctx, const double *x, const double *y, int64_t n
     return GL_OK;
 }
 
-int gl_precision_stats(gl_context *ctx, int64_t *tiles_h, double *work_h)
+int gl_precision_stats(gl_context *ctx, int64_t *tiles_h, double *work_h, double *thresholds_h)
 {
     if (!ctx) return GL_EINVAL;
     for (int c = 0; c < 5; ++c) {
         if (tiles_h) tiles_h[c] = ctx->last_plan.tiles[c];
         if (work_h) work_h[c] = ctx->last_plan.work[c];
     }
+    for (int c = 0; c < 4; ++c)
+        if (thresholds_h) thresholds_h[c] = ctx->last_plan.thr[c];
     return GL_OK;
 }
 

@@ -17,6 +17,7 @@ struct MixedViews {
     int np = 0;                                  // parts written per panel element
     int2 *lists = nullptr;                       // per-class tile lists (device)
     uint8_t *map = nullptr;                      // per-tile precision class (device)
+    double *thr = nullptr;                       // ρ and the effective thresholds (device, 4 doubles)
 };
 
 // Host-side plan of one mixed evaluation: per class, the offset of its list
@@ -25,6 +26,7 @@ struct MixedPlan {
     int64_t base[5] = {0, 0, 0, 0, 0};
     int64_t tiles[5] = {0, 0, 0, 0, 0};
     double work[5] = {0, 0, 0, 0, 0};  // Σ over tiles of the number of trailing updates they receive
+    double thr[4] = {0, 0, 0, 0};      // ρ, tol_64, tol_hi, tol_lo as used
     std::vector<std::vector<int64_t>> start;
 };
 

@@ -8,6 +8,8 @@
 // measured when Σ is generated:
 //   class 0  FP64    diagonal tiles, tiles with i - j < band, and tiles
 //                    with ν_ij > tol_64 (both modes);
+// Thresholds left negative in the options follow from an accuracy target
+// and the first diagonal tile's pivots (thresholds_kernel below).
 //   class 1  FP32    FP32 matrix-core products (GL_MIXED_FP32);
 //   class 2  BF16x6  operands split into three bfloat16 parts a = h + m + l,
 //                    products hh + hm + mh + hl + lh + mm: about FP32 accuracy
@@ -36,8 +38,42 @@ enum { C64 = 0, C32 = 1, CB6 = 2, CB3 = 3, CB1 = 4, NCLASS = 5 };
 
 // ------------------------------------------------------------ precision map --
 
+// Smallest pivot ratio ρ = min_r L_rr² / θ1 of the first diagonal tile,
+// factored in binary64 before any off-band update (Σ_rr = θ1).  It measures
+// how much of a variance the neighbouring locations explain, i.e. how much
+// the Schur complements cancel; a non-positive or NaN ρ (failed POTRF) makes
+// every adaptive threshold zero, so every tile stays binary64.  Then the
+// effective thresholds: a negative option is replaced by ε ρ / u for the
+// class it bounds (u = 2⁻²⁴ for FP32 and the three-part split, 2⁻¹⁶ for two
+// parts, 2⁻⁸ for one part), i.e. a class is used for tile (i, j) only while
+// ν_ij u <= ε ρ.  thr = {ρ, tol_64, tol_hi, tol_lo}.
+__global__ __launch_bounds__(256) void thresholds_kernel(const double *__restrict__ tile0, int b, int64_t n,
+                                                         double theta1, double eps, double tol_64, double tol_hi,
+                                                         double tol_lo, double *__restrict__ thr)
+{
+    const int m = (int)(n < b ? n : b);
+    double lo = INFINITY;
+    for (int r = threadIdx.x; r < m; r += 256) {
+        const double d = tile0[(int64_t)r * b + r];
+        lo = fmin(lo, d * d / theta1);
+    }
+    for (int off = 32; off >= 1; off >>= 1) lo = fmin(lo, __shfl_xor(lo, off, 64));
+    __shared__ double red[4];
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = lo;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double rho = fmin(fmin(red[0], red[1]), fmin(red[2], red[3]));
+        if (!(rho > 0.0) || !(rho <= 1.0)) rho = 0.0;
+        const double er = eps * rho;
+        thr[0] = rho;
+        thr[1] = tol_64 >= 0.0 ? tol_64 : er * 16777216.0;  // / 2^-24
+        thr[2] = tol_hi >= 0.0 ? tol_hi : er * 65536.0;     // / 2^-16
+        thr[3] = tol_lo >= 0.0 ? tol_lo : er * 256.0;       // / 2^-8
+    }
+}
+
 __global__ void classify_kernel(const double *__restrict__ norm2, int64_t nt, int band, int mode,
-                                double tol_64, double tol_hi, double tol_lo, uint8_t *__restrict__ map)
+                                const double *__restrict__ thr, uint8_t *__restrict__ map)
 {
     const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (t >= tile_count(nt)) return;
@@ -45,6 +81,7 @@ __global__ void classify_kernel(const double *__restrict__ norm2, int64_t nt, in
     while (i * (i + 1) / 2 > t) --i;
     while ((i + 1) * (i + 2) / 2 <= t) ++i;
     const int64_t j = t - i * (i + 1) / 2;
+    const double tol_64 = thr[1], tol_hi = thr[2], tol_lo = thr[3];
     uint8_t c;
     if (i - j < band) {
         c = C64;
@@ -53,7 +90,7 @@ __global__ void classify_kernel(const double *__restrict__ norm2, int64_t nt, in
         const double nii = sqrt(norm2[tile_index(i, i)]);
         const double njj = sqrt(norm2[tile_index(j, j)]);
         const double v = nij / sqrt(nii * njj);
-        if (v > tol_64) c = C64;
+        if (!(v <= tol_64)) c = C64;
         else if (mode == GL_MIXED_FP32) c = C32;
         else c = (v > tol_hi) ? CB6 : (v > tol_lo) ? CB3 : CB1;
     }
@@ -436,6 +473,8 @@ void mixed_views(Work &w)
     mv.lists = reinterpret_cast<int2 *>(p);
     p += tc * sizeof(int2);
     mv.map = reinterpret_cast<uint8_t *>(p);
+    p += ((tc + 255) / 256) * 256;
+    mv.thr = reinterpret_cast<double *>(p);  // 4 doubles in the 1024-byte tail
 }
 
 // Classify the tiles on the device, bring the map to the host, build the
@@ -445,11 +484,11 @@ static int build_lists(Work &w, const gl_opts &o, hipStream_t s, MixedPlan &plan
     const int64_t nt = w.nt;
     const int64_t tc = tile_count(nt);
     const int mode = w.precision;
-    classify_kernel<<<(unsigned)ceil_div(tc, 256), 256, 0, s>>>(w.norm2, nt, o.band, mode, o.tol_64, o.tol_hi,
-                                                                o.tol_lo, w.mv.map);
+    classify_kernel<<<(unsigned)ceil_div(tc, 256), 256, 0, s>>>(w.norm2, nt, o.band, mode, w.mv.thr, w.mv.map);
     GL_HIP_TRY(hipGetLastError());
     std::vector<uint8_t> map((size_t)tc);
     GL_HIP_TRY(hipMemcpyAsync(map.data(), w.mv.map, (size_t)tc, hipMemcpyDeviceToHost, s));
+    GL_HIP_TRY(hipMemcpyAsync(plan.thr, w.mv.thr, sizeof(plan.thr), hipMemcpyDeviceToHost, s));
     GL_HIP_TRY(hipStreamSynchronize(s));
     plan.start.assign(NCLASS, std::vector<int64_t>(nt + 2, 0));
     std::vector<int2> all;
@@ -489,6 +528,10 @@ static void class_updates(Work &w, int64_t k, int64_t j0, int64_t j1, const Mixe
 int mixed_factorize(Lanes &ln, Work &w, gl_theta th, const gl_opts &o, hipStream_t s, MixedPlan *plan_out)
 {
     launch_gen_tiles(w.tiles, w.x, w.y, w.n, w.b, w.nt, th, geom_of(o), w.norm2, s);
+    // step 0's POTRF first: its pivots set the adaptive thresholds
+    launch_potrf(w.tiles, w.b, 0, w.n, w.info, w.logsum, w.dinv_k(0), s);
+    thresholds_kernel<<<1, 256, 0, s>>>(w.tiles, w.b, w.n, th.theta1, o.accuracy, o.tol_64, o.tol_hi, o.tol_lo,
+                                        w.mv.thr);
     MixedPlan plan;
     int rc = build_lists(w, o, s, plan);
     if (rc != GL_OK) return rc;
@@ -497,7 +540,7 @@ int mixed_factorize(Lanes &ln, Work &w, gl_theta th, const gl_opts &o, hipStream
     GL_HIP_TRY(hipEventRecord(ln.fork, s));
     GL_HIP_TRY(hipStreamWaitEvent(la, ln.fork, 0));
     for (int64_t k = 0; k < w.nt; ++k) {
-        launch_potrf(w.tiles, w.b, k, w.n, w.info, w.logsum, w.dinv_k(k), s);
+        if (k > 0) launch_potrf(w.tiles, w.b, k, w.n, w.info, w.logsum, w.dinv_k(k), s);
         launch_fwd_diag(w.tiles, w.b, k, w.n, w.v, w.quad, w.dinv_k(k), w.info, s);
         launch_trsm(w.tiles, w.b, w.nt, k, w.dinv_k(k), w.info, s);
         launch_fwd_update(w.tiles, w.b, w.nt, k, w.v, w.info, s);

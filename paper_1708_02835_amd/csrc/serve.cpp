@@ -8,9 +8,10 @@
 // one step of its tiled factorisation through one fused launch per kernel
 // (staging and Σ generation for newcomers, POTRF, forward diagonal solve,
 // TRSM, forward update, trailing update, final reduction for those whose last
-// step it is).  A launch covers all residents, each at its own step, so
-// requests that arrive while others are on the device join at the next tick
-// and leave when done.  Two ticks may be in flight.  Each request runs the
+// step it is).  A launch covers all residents of a cohort, each at its own
+// step, so requests that arrive while others are on the device join at the
+// next tick and leave when done.  Residents are spread over two cohorts with
+// their own streams; each cohort may have two ticks in flight.  Each request runs the
 // same per-request code as a single evaluation with tile 256, so its result
 // does not depend on the batch it rides in.
 //
@@ -126,6 +127,19 @@ struct TickBuf {
     std::vector<Resident> finishing;
 };
 
+// Residents are split into cohorts that tick independently on their own
+// streams, so one cohort's short, narrow launches (POTRF, TRSM, solves)
+// overlap another cohort's wide trailing update.
+constexpr int NCOHORT = 2;
+
+struct Cohort {
+    hipStream_t s = nullptr;
+    std::vector<Resident> residents;
+    TickBuf ring[TICK_RING];
+    int ring_next = 0;
+    std::deque<int> ticks;  // ring indices in flight, oldest first
+};
+
 }  // namespace
 
 struct lq_queue {
@@ -140,12 +154,8 @@ struct lq_queue {
     bool stop = false;
     std::vector<Slot> slots;
     // continuous batching
-    hipStream_t ts = nullptr;
-    std::vector<Resident> residents;
+    Cohort co[NCOHORT];
     std::vector<Work *> pool;  // idle workspaces of the batched engine
-    TickBuf ring[TICK_RING];
-    int ring_next = 0;
-    std::deque<int> ticks;     // ring indices in flight, oldest first
     int inflight = 0, peak_inflight = 0;
     size_t peak_bytes = 0;
     uint64_t completed = 0, fused = 0;
@@ -171,9 +181,11 @@ size_t held_bytes(const lq_queue *q)
     size_t t = 0;
     for (const Slot &sl : q->slots) t += slot_bytes(sl);
     for (const Work *w : q->pool) t += w->bytes();
-    for (const Resident &r : q->residents) t += r.w->bytes();
-    for (int i = 0; i < TICK_RING; ++i)
-        for (const Resident &r : q->ring[i].finishing) t += r.w->bytes();
+    for (const Cohort &c : q->co) {
+        for (const Resident &r : c.residents) t += r.w->bytes();
+        for (const TickBuf &tb : c.ring)
+            for (const Resident &r : tb.finishing) t += r.w->bytes();
+    }
     return t;
 }
 
@@ -211,17 +223,17 @@ int take_work(lq_queue *q, int64_t n, Work *&out)
     return GL_OK;
 }
 
-// Enqueue one tick: every resident advances by one step.
-int build_tick(lq_queue *q)
+// Enqueue one tick of cohort c: every resident advances by one step.
+int build_tick(lq_queue *q, Cohort &co)
 {
-    TickBuf &tb = q->ring[q->ring_next];
+    TickBuf &tb = co.ring[co.ring_next];
     if (tb.busy) return GL_EBUSY;
-    const int count = (int)q->residents.size();
+    const int count = (int)co.residents.size();
     int64_t o_stage = 0, o_gen = 0, o_trsm = 0, o_tr = 0;
     const int64_t sub = (TICK_B / 128) * (TICK_B / 128);
     bool any_new = false, any_fin = false;
     for (int i = 0; i < count; ++i) {
-        Resident &r = q->residents[i];
+        Resident &r = co.residents[i];
         Work &w = *r.w;
         BatchReq &d = tb.host[i];
         d.tiles = w.tiles;
@@ -259,7 +271,7 @@ int build_tick(lq_queue *q)
         o_tr += m * (m + 1) / 2 * sub;
         any_fin = any_fin || d.finishing;
     }
-    hipStream_t s = q->ts;
+    hipStream_t s = co.s;
     GL_HIP_TRY(hipMemcpyAsync(tb.dev, tb.host, count * sizeof(BatchReq), hipMemcpyHostToDevice, s));
     int launches = 0;
     if (any_new) {
@@ -280,9 +292,9 @@ int build_tick(lq_queue *q)
     }
     GL_HIP_TRY(hipGetLastError());
     std::vector<Resident> keep;
-    keep.reserve(q->residents.size());
+    keep.reserve(co.residents.size());
     for (int i = 0; i < count; ++i) {
-        Resident r = q->residents[i];
+        Resident r = co.residents[i];
         r.is_new = false;
         if (tb.host[i].finishing) {
             GL_HIP_TRY(hipMemcpyAsync(&tb.res_h[tb.finishing.size()], r.w->res, sizeof(DevResult),
@@ -293,20 +305,20 @@ int build_tick(lq_queue *q)
             keep.push_back(r);
         }
     }
-    q->residents.swap(keep);
+    co.residents.swap(keep);
     GL_HIP_TRY(hipEventRecord(tb.done, s));
     tb.busy = true;
-    q->ticks.push_back(q->ring_next);
-    q->ring_next = (q->ring_next + 1) % TICK_RING;
+    co.ticks.push_back(co.ring_next);
+    co.ring_next = (co.ring_next + 1) % TICK_RING;
     q->fused += launches;
     return GL_OK;
 }
 
-// Deliver the results of completed ticks (oldest first).
-void retire_ticks(lq_queue *q)
+// Deliver the results of completed ticks of cohort c (oldest first).
+void retire_ticks(lq_queue *q, Cohort &co)
 {
-    while (!q->ticks.empty()) {
-        TickBuf &tb = q->ring[q->ticks.front()];
+    while (!co.ticks.empty()) {
+        TickBuf &tb = co.ring[co.ticks.front()];
         hipError_t e = hipEventQuery(tb.done);
         if (e == hipErrorNotReady) return;
         for (size_t i = 0; i < tb.finishing.size(); ++i) {
@@ -330,7 +342,7 @@ void retire_ticks(lq_queue *q)
         }
         tb.finishing.clear();
         tb.busy = false;
-        q->ticks.pop_front();
+        co.ticks.pop_front();
     }
 }
 
@@ -376,12 +388,15 @@ void scheduler(lq_queue *q)
             r->res.factor = nullptr;
             finish(q, r, sl.res_h->info ? GL_NOT_SPD : GL_OK);
         }
-        retire_ticks(q);
+        for (Cohort &c : q->co) retire_ticks(q, c);
         // admit queued requests in arrival order: batched residents or free slots
         while (!q->queue.empty()) {
             Request *head = q->queue.front();
             if (batch_eligible(q, head)) {
-                if (q->inflight >= q->cfg.max_inflight || (int)q->residents.size() >= TICK_MAX) break;
+                Cohort *dst = &q->co[0];
+                for (Cohort &c : q->co)
+                    if (c.residents.size() < dst->residents.size()) dst = &c;
+                if (q->inflight >= q->cfg.max_inflight || (int)dst->residents.size() >= TICK_MAX) break;
                 const size_t need = work_bytes(head->ds->n, TICK_B, GL_FP64);
                 bool have = false;
                 for (Work *w : q->pool) have = have || w->bytes() >= need;
@@ -416,7 +431,7 @@ void scheduler(lq_queue *q)
                 Resident res;
                 res.req = head;
                 res.w = w;
-                q->residents.push_back(res);
+                dst->residents.push_back(res);
                 ++q->inflight;
                 if (q->inflight > q->peak_inflight) q->peak_inflight = q->inflight;
                 continue;
@@ -465,16 +480,21 @@ void scheduler(lq_queue *q)
             const size_t h = held_bytes(q);
             if (h > q->peak_bytes) q->peak_bytes = h;
         }
-        if (!q->residents.empty() && (int)q->ticks.size() < TICK_DEPTH) {
-            const int rc = build_tick(q);
+        bool ticked = false;
+        for (Cohort &c : q->co) {
+            if (c.residents.empty() || (int)c.ticks.size() >= TICK_DEPTH) continue;
+            const int rc = build_tick(q, c);
             if (rc != GL_OK && rc != GL_EBUSY) {
-                for (Resident &r : q->residents) {
+                for (Resident &r : c.residents) {
                     --q->inflight;
                     finish(q, r.req, rc);
                     q->pool.push_back(r.w);
                 }
-                q->residents.clear();
+                c.residents.clear();
             }
+            ticked = ticked || rc == GL_OK;
+        }
+        if (ticked) {
             const size_t h = held_bytes(q);
             if (h > q->peak_bytes) q->peak_bytes = h;
             continue;
@@ -594,18 +614,17 @@ int lq_create(gl_context *ctx, const lq_config *cfg, lq_queue **out)
             return GL_EHIP;
         }
     }
-    if (hipStreamCreateWithFlags(&q->ts, hipStreamNonBlocking) != hipSuccess) {
-        q->stop = true;
-        lq_destroy(q);
-        return GL_EHIP;
-    }
-    for (TickBuf &tb : q->ring) {
-        if (hipHostMalloc(reinterpret_cast<void **>(&tb.host), TICK_MAX * sizeof(BatchReq), hipHostMallocDefault) !=
-                hipSuccess ||
-            hipMalloc(reinterpret_cast<void **>(&tb.dev), TICK_MAX * sizeof(BatchReq)) != hipSuccess ||
-            hipHostMalloc(reinterpret_cast<void **>(&tb.res_h), TICK_MAX * sizeof(DevResult), hipHostMallocDefault) !=
-                hipSuccess ||
-            hipEventCreateWithFlags(&tb.done, hipEventDisableTiming) != hipSuccess) {
+    for (Cohort &c : q->co) {
+        bool ok = hipStreamCreateWithFlags(&c.s, hipStreamNonBlocking) == hipSuccess;
+        for (TickBuf &tb : c.ring)
+            ok = ok &&
+                 hipHostMalloc(reinterpret_cast<void **>(&tb.host), TICK_MAX * sizeof(BatchReq),
+                               hipHostMallocDefault) == hipSuccess &&
+                 hipMalloc(reinterpret_cast<void **>(&tb.dev), TICK_MAX * sizeof(BatchReq)) == hipSuccess &&
+                 hipHostMalloc(reinterpret_cast<void **>(&tb.res_h), TICK_MAX * sizeof(DevResult),
+                               hipHostMallocDefault) == hipSuccess &&
+                 hipEventCreateWithFlags(&tb.done, hipEventDisableTiming) == hipSuccess;
+        if (!ok) {
             q->stop = true;
             lq_destroy(q);
             return GL_EHIP;
@@ -749,20 +768,23 @@ int lq_destroy(lq_queue *q)
             }
     }
     hipSetDevice(q->ctx->device);
-    if (q->ts) hipStreamSynchronize(q->ts);
+    for (Cohort &c : q->co)
+        if (c.s) hipStreamSynchronize(c.s);
     for (Work *w : q->pool) {
         q->ctx->used -= w->bytes();
         w->release();
         delete w;
     }
     q->pool.clear();
-    for (TickBuf &tb : q->ring) {
-        if (tb.host) hipHostFree(tb.host);
-        if (tb.dev) hipFree(tb.dev);
-        if (tb.res_h) hipHostFree(tb.res_h);
-        if (tb.done) hipEventDestroy(tb.done);
+    for (Cohort &c : q->co) {
+        for (TickBuf &tb : c.ring) {
+            if (tb.host) hipHostFree(tb.host);
+            if (tb.dev) hipFree(tb.dev);
+            if (tb.res_h) hipHostFree(tb.res_h);
+            if (tb.done) hipEventDestroy(tb.done);
+        }
+        if (c.s) hipStreamDestroy(c.s);
     }
-    if (q->ts) hipStreamDestroy(q->ts);
     for (Slot &sl : q->slots) {
         if (sl.s) hipStreamSynchronize(sl.s);
         q->ctx->used -= slot_bytes(sl);

@@ -194,3 +194,21 @@ def test_mixed_factor_kriging(g, ctx):
         g.gl_factor_release(ctx, r["factor"])
     # prediction error against exact kriging, relative to the field's scale
     assert np.max(np.abs(out - ref)) <= 1e-4 * np.max(np.abs(z))
+
+
+def test_adaptive_thresholds_follow_first_tile_pivots(g, ctx):
+    """Default thresholds: ρ = min_r L_rr² / θ1 over the first diagonal tile in
+    the factorisation order (Morton), from its binary64 factor, and
+    tol = 1e-4 ρ / u for u = 2⁻²⁴, 2⁻¹⁶, 2⁻⁸."""
+    for theta in [(1.0, 0.1, 0.5), (1.0, 0.3, 1.0)]:
+        x, y, z, _ = _problem(theta)
+        r = g.loglik_eval(ctx, dev(x), dev(y), dev(z), theta, g.gl_opts_default(precision=2, tile=256))
+        assert r["status"] == g.GL_OK
+        thr = g.gl_precision_stats(ctx)["thresholds"]
+        first = morton_reference(x, y)[:256]
+        lfac, info = oracle.cholesky(oracle.cov_symmetric(x[first], y[first], theta))
+        assert info == 0
+        rho = float(np.min(np.diag(lfac) ** 2)) / theta[0]
+        assert thr["rho"] == pytest.approx(rho, rel=1e-9)
+        er = 1e-4 * thr["rho"]
+        assert thr["tol_64"] == er * 2.0 ** 24 and thr["tol_hi"] == er * 2.0 ** 16 and thr["tol_lo"] == er * 2.0 ** 8
