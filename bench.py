@@ -93,6 +93,21 @@ def cpu_baseline(n_target: int, theta) -> dict:
             "seconds_timed": t1 + t2}
 
 
+def measured_traffic(n: int, tile: int):
+    """HBM bytes per trailing-update launch from the committed FETCH_SIZE /
+    WRITE_SIZE counter runs of this workload, or None when the kernel source
+    has changed since they were taken (or they cover another workload)."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"trailing_f64_n{n}_hbm_traffic.json")
+    if tile != 512 or not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    src = open(os.path.join(ROOT, rec["source"]), "rb").read()
+    if hashlib.sha256(src).hexdigest() != rec["source_sha256"]:
+        return None
+    return rec["hbm_bytes_per_launch"]
+
+
 def mixed_legs(g, ctx, xd, yd, ed, zd, theta, theta_b, args, res64, t64, log):
     """Time-to-l(θ) of the mixed-precision modes against FP64 at the same
     size, with the relative error of l and log|Σ| against the FP64 result,
@@ -324,7 +339,8 @@ def main():
         "loglik": res["loglik"], "logdet": res["logdet"],
         "roofline": {"bound": "mfma", "kernel": "trailing_f64_kernel (SYRK/GEMM trailing update)",
                      "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None,
+                     "frac": achieved / PEAK_FP64_TFLOPS, "traffic": measured_traffic(n, args.tile),
+                     "traffic_unit": "bytes per launch (HBM, rocprofv3 FETCH_SIZE x2.0 + WRITE_SIZE x1.0)",
                      "launches": prof["launches"], "avg_launch_ms": avg_ms,
                      "flops_per_launch": avg_flops},
     }
