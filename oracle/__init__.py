@@ -18,6 +18,8 @@ Functions (each follows the passage named in ``oracle.c``):
 * ``loglik`` — Alg. 2 / Eq. (1), returns (l, logdet, quad, info).
 * ``krige`` — Alg. 3 / Eq. (5), optionally the variances of Eq. (4).
 * ``synth`` — Alg. 1, Z = L e.
+* ``loglik_ind`` — the IND approximation of Sec. 6.8 (blocks of consecutive
+  locations, off-block covariances annihilated).
 """
 from __future__ import annotations
 
@@ -68,6 +70,7 @@ def _load():
         "oracle_loglik": (I64, [P, P, P, I64, D, D, D, ctypes.c_int, D, P, P]),
         "oracle_krige": (I64, [P, P, P, I64, P, P, I64, D, D, D, ctypes.c_int, D, P, P]),
         "oracle_synth": (I64, [P, P, P, I64, D, D, D, ctypes.c_int, D, P]),
+        "oracle_loglik_ind": (I64, [P, P, P, I64, D, D, D, ctypes.c_int, D, I64, P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -192,3 +195,13 @@ def synth(x, y, e, theta, metric: int = EUCLIDEAN, radius: float = EARTH_RADIUS_
     info = _load().oracle_synth(_p(x), _p(y), _p(e), x.size, *map(float, theta), int(metric), float(radius),
                                 _p(z))
     return z, int(info)
+
+
+def loglik_ind(x, y, z, theta, block: int, metric: int = EUCLIDEAN, radius: float = EARTH_RADIUS_KM):
+    """IND approximation (Sec. 6.8): returns (l, logdet, quad, info) summed over
+    diagonal blocks of `block` consecutive locations."""
+    x, y, z = map(_f64, (x, y, z))
+    out = np.zeros(3, dtype=np.float64)
+    info = _load().oracle_loglik_ind(_p(x), _p(y), _p(z), x.size, *map(float, theta), int(metric), float(radius),
+                                     int(block), _p(out))
+    return float(out[0]), float(out[1]), float(out[2]), int(info)

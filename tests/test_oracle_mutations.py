@@ -41,6 +41,8 @@ MUTANTS = {
     "gcd_no_factor_two": ("return 2.0 * radius * asin(sqrt(h));", "return radius * asin(sqrt(h));"),
     "variance_sign": ("var[k] = theta1 - oracle_dot(w, n);", "var[k] = theta1 + oracle_dot(w, n);"),
     "variance_backward": ("oracle_forward(a, n, sk, w);", "oracle_backward(a, n, sk, w);"),
+    "ind_stride": ("for (int64_t s = 0; s < n; s += block) {", "for (int64_t s = 0; s < n; s += block + 1) {"),
+    "ind_sum_sign": ("        l += part[0];", "        l -= part[0];"),
 }
 
 
@@ -68,6 +70,8 @@ def _build(tmp_path, name, mutation):
     lib.oracle_krige.argtypes = [P, P, P, I64, P, P, I64, D, D, D, INT, D, P, P]
     lib.oracle_synth.restype = I64
     lib.oracle_synth.argtypes = [P, P, P, I64, D, D, D, INT, D, P]
+    lib.oracle_loglik_ind.restype = I64
+    lib.oracle_loglik_ind.argtypes = [P, P, P, I64, D, D, D, INT, D, I64, P]
     return lib
 
 
@@ -133,6 +137,16 @@ def _pins(lib):
         want = 2 * R * math.asin(np.linalg.norm(u[0] - u[1]) / 2)
         if abs(lib.oracle_distance(1, R, l1, p1, l2, p2) - want) > 1e-9 * want:
             failed.append("gcd_chord")
+    # IND (Sec. 6.8) vs the block-masked dense covariance
+    blk = np.arange(n) // 15
+    am = np.where(blk[:, None] == blk[None, :], a, 0.0)
+    lam_m, u_m = np.linalg.eigh(am)
+    ref_ind = -0.5 * n * math.log(2 * math.pi) - 0.5 * float(np.sum(np.log(lam_m))) \
+        - 0.5 * float(np.sum((u_m.T @ z) ** 2 / lam_m))
+    out_ind = np.zeros(3)
+    lib.oracle_loglik_ind(_p(x), _p(y), _p(z), n, *theta, 0, 1.0, 15, _p(out_ind))
+    if not abs(out_ind[0] - ref_ind) <= 1e-9 * abs(ref_ind):
+        failed.append("ind_masked")
     # synth vs LAPACK factor
     e = geoinputs.normal_vector(n, 8)
     zs = np.zeros(n)
