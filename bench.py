@@ -43,6 +43,7 @@ def parse():
     p.add_argument("--theta-b", type=float, nargs=3, default=(1.0, 0.3, 1.0),
                    help="second parameter vector of the mixed-precision comparison")
     p.add_argument("--no-serve", action="store_true", help="skip the serving leg")
+    p.add_argument("--no-ind", action="store_true", help="skip the independent-blocks leg")
     p.add_argument("--serve-clients", type=int, default=64)
     p.add_argument("--serve-evals", type=int, default=5, help="l(theta) requests per client")
     p.add_argument("--serve-rate", type=float, default=400.0, help="client arrivals per second (Poisson)")
@@ -147,6 +148,27 @@ def mixed_legs(g, ctx, xd, yd, ed, zd, theta, theta_b, args, res64, t64, log):
                          "thresholds": stats["thresholds"]}
             log(f"mixed {label} {name}: {dt:.3f} s, x{t64b / dt:.2f}, rel err {leg[name]['rel_err_loglik']:.2e}")
         out[label] = leg
+    return out
+
+
+def ind_legs(g, ctx, xd, yd, zd, theta, args, res64, t64, log):
+    """Independent-blocks approximation (diagonal super tiles of s tiles) at
+    the benchmark size: time and l against the exact FP64 l."""
+    import torch
+    out = []
+    for s in (1, 2, 4, 8, 16):
+        opts = g.gl_opts_default(tile=args.tile, ind_tiles=s)
+        g.loglik_eval(ctx, xd, yd, zd, theta, opts)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        reps = 3
+        for _ in range(reps):
+            r = g.loglik_eval(ctx, xd, yd, zd, theta, opts)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / reps
+        out.append({"super_tile": s, "block_points": s * args.tile, "ms": dt * 1e3, "speedup_vs_exact": t64 / dt,
+                    "loglik": r["loglik"], "rel_diff_vs_exact": abs(r["loglik"] - res64["loglik"]) / abs(res64["loglik"])})
+        log(f"IND s={s}: {dt * 1e3:.1f} ms, l={r['loglik']:.6f}")
     return out
 
 
@@ -346,6 +368,8 @@ def main():
     }
     if not args.no_mixed:
         out["mixed"] = mixed_legs(g, ctx, xd, yd, ed, zd, theta, tuple(args.theta_b), args, res, step_s, log)
+    if not args.no_ind:
+        out["ind"] = ind_legs(g, ctx, xd, yd, zd, theta, args, res, step_s, log)
     if not args.no_serve:
         out["serving"] = serving_leg(g, ctx, args, log)
     ctx.close()

@@ -97,6 +97,12 @@ typedef struct {
     double radius;       /* GL_GREAT_CIRCLE: sphere radius (> 0; default 6371, the Earth in km) */
     double tol_64;       /* mixed modes: see above (negative: adaptive) */
     double accuracy;     /* mixed modes: ε of the adaptive thresholds (negative: 1e-4) */
+    int32_t ind_tiles;   /* 0: exact l(θ).  s >= 1: independent-blocks approximation (Sec. 6.8):
+                            every tile outside the diagonal super tiles of s×s tiles is
+                            annihilated, i.e. l is summed over blocks of s·b consecutive
+                            locations (after reordering, if on), each factored on its own;
+                            GL_FP64 only, no kept factor */
+    int32_t reserved;    /* 0 */
 } gl_opts;
 
 /* Result of one likelihood evaluation, host memory. */

@@ -44,7 +44,8 @@ class gl_opts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("tile", ctypes.c_int32), ("keep_factor", ctypes.c_int32),
                 ("band", ctypes.c_int32), ("reorder", ctypes.c_int32), ("metric", ctypes.c_int32),
                 ("tol_hi", ctypes.c_double), ("tol_lo", ctypes.c_double), ("radius", ctypes.c_double),
-                ("tol_64", ctypes.c_double), ("accuracy", ctypes.c_double)]
+                ("tol_64", ctypes.c_double), ("accuracy", ctypes.c_double), ("ind_tiles", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 class gl_result(ctypes.Structure):

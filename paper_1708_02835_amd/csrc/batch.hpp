@@ -30,7 +30,8 @@ struct BatchReq {
         return r_;                                           \
     }())
 
-// Launchers (b = 256 only); grids come from the totals of the prefix offsets.
+// Launchers (b = 128, 256, 384, 512); grids come from the totals of the prefix
+// offsets.
 void launch_stage_batched(const BatchReq *d, int count, int64_t blocks, hipStream_t s);
 void launch_gen_batched(int b, const BatchReq *d, int count, int64_t tiles, hipStream_t s);
 void launch_potrf_batched(int b, const BatchReq *d, int count, hipStream_t s);
@@ -39,5 +40,12 @@ void launch_trsm_batched(int b, const BatchReq *d, int count, int64_t blocks, hi
 void launch_fwd_update_batched(int b, const BatchReq *d, int count, int64_t blocks, hipStream_t s);
 void launch_trailing_batched(int b, const BatchReq *d, int count, int64_t blocks, hipStream_t s);
 void launch_final_batched(const BatchReq *d, int count, hipStream_t s);
+
+// One step for d[0..count): the caller sets every field but the offsets
+// (k, is_new and finishing included); the offsets are filled in, the array is
+// copied to dev (device, count entries) on s and the fused launches follow.
+// d must stay valid until the copy has been consumed (pinned memory: until
+// the stream passes it).
+int enqueue_step(BatchReq *d, BatchReq *dev, int count, int b, hipStream_t s, int *launches);
 
 }  // namespace gl

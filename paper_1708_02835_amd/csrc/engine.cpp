@@ -232,6 +232,8 @@ void gl_opts_default(gl_opts *o)
     o->tol_lo = -1.0;
     o->tol_64 = -1.0;
     o->accuracy = -1.0;
+    o->ind_tiles = 0;
+    o->reserved = 0;
     o->radius = 6371.0;
 }
 
@@ -273,6 +275,7 @@ void gl_context_destroy(gl_context *c)
     hipSetDevice(c->device);
     hipDeviceSynchronize();
     c->ws.release();
+    if (c->ind_buf) hipFree(c->ind_buf);
     for (gl_factor *f : c->factors) {
         f->w.release();
         delete f;
@@ -337,6 +340,7 @@ bool valid_metric(const gl_opts &o)
 bool valid_opts(const gl_opts &o)
 {
     if (!valid_metric(o)) return false;
+    if (o.ind_tiles < 0 || (o.ind_tiles > 0 && (o.precision != GL_FP64 || o.keep_factor))) return false;
     if (o.precision < GL_FP64 || o.precision > GL_MIXED_BF16) return false;
     if (o.tile != 0 && o.tile != 128 && o.tile != 256 && o.tile != 384 && o.tile != 512) return false;
     if (o.reorder < -1 || o.reorder > 1) return false;
@@ -367,7 +371,7 @@ gl_opts resolved_opts(const gl_opts &in)
     return o;
 }
 
-static void fill_result(gl_result *res, const DevResult &d, int b)
+void fill_result(gl_result *res, const DevResult &d, int b)
 {
     res->loglik = d.loglik;
     res->logdet = d.logdet;
@@ -397,6 +401,7 @@ int loglik_eval(gl_context *ctx, const double *x, const double *y, const double 
     o = resolved_opts(o);
     GL_HIP_TRY(hipSetDevice(ctx->device));
     hipStream_t s = static_cast<hipStream_t>(stream);
+    if (o.ind_tiles > 0) return ind_eval(ctx, x, y, z, n, th, o, res, s);
     const int b = pick_tile(n, o.tile);
     gl_factor *f = nullptr;
     Work *w = &ctx->ws;

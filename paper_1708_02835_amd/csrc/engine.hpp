@@ -108,6 +108,12 @@ void launch_morton_order(const double *x, const double *y, const double *z, int6
 struct ServeState;
 void serve_context_cleanup(gl_context *ctx);
 
+void fill_result(gl_result *res, const DevResult &d, int b);
+
+// Independent-blocks approximation (ind.cpp); o resolved and validated.
+int ind_eval(gl_context *ctx, const double *x, const double *y, const double *z, int64_t n, gl_theta th,
+             const gl_opts &o, gl_result *res, hipStream_t s);
+
 }  // namespace gl
 
 struct gl_factor {
@@ -129,4 +135,6 @@ struct gl_context {
     std::mutex mu;                   // guards factors and datasets
     std::vector<gl_factor *> factors;
     gl::ServeState *serve = nullptr;
+    void *ind_buf = nullptr;  // workspace of the independent-blocks evaluations
+    size_t ind_cap = 0;
 };

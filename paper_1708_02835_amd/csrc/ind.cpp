@@ -1,0 +1,138 @@
+// Independent-blocks (IND) approximation, Sec. 6.8: the tiles outside the
+// diagonal super tiles of s×s tiles are annihilated, so Σ is block diagonal
+// with blocks of s·b consecutive locations and l(θ) is the sum of the exact
+// log-likelihoods of the blocks.  Nothing outside the blocks is generated or
+// factored: the blocks are independent factorisations of s tile columns each
+// (the last one possibly shorter), advanced together through the fused
+// multi-factorisation launches, one tile step per launch group.
+#include <algorithm>
+#include <vector>
+
+#include "batch.hpp"
+#include "engine.hpp"
+
+namespace gl {
+
+// Sums the per-block results in block order; info of the first failing block,
+// as a global 1-based column.
+__global__ void ind_total_kernel(const DevResult *__restrict__ r, int64_t nblk, int64_t block,
+                                 DevResult *__restrict__ out)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    double l = 0.0, ld = 0.0, q = 0.0;
+    int64_t info = 0;
+    for (int64_t i = 0; i < nblk; ++i) {
+        if (info == 0 && r[i].info != 0) info = i * block + r[i].info;
+        l += r[i].loglik;
+        ld += r[i].logdet;
+        q += r[i].quad;
+    }
+    out->info = info;
+    out->loglik = info ? -INFINITY : l;
+    out->logdet = info ? NAN : ld;
+    out->quad = info ? NAN : q;
+}
+
+int ind_eval(gl_context *ctx, const double *x, const double *y, const double *z, int64_t n, gl_theta th,
+             const gl_opts &o, gl_result *res, hipStream_t s)
+{
+    const int b = pick_tile(n, o.tile);
+    const int64_t bt = o.ind_tiles;          // tiles per super tile
+    const int64_t block = bt * b;            // locations per block
+    const int64_t nblk = ceil_div(n, block);
+    // layout (in doubles): descriptors | totals | per-block results, info |
+    // per block: tiles, x, y, v, logsum, quad, dinv | reordered inputs, keys
+    const size_t desc_d = ((size_t)nblk * sizeof(BatchReq) + 15) / 16 * 2;
+    size_t off = desc_d + 8 + 8 * (size_t)nblk + 8 * (size_t)nblk;
+    std::vector<size_t> boff(nblk);
+    std::vector<int64_t> nb(nblk), ntb(nblk);
+    for (int64_t i = 0; i < nblk; ++i) {
+        nb[i] = std::min(block, n - i * block);
+        ntb[i] = ceil_div(nb[i], b);
+        const int64_t npb = ntb[i] * b;
+        boff[i] = off;
+        off += (size_t)tile_count(ntb[i]) * b * b + 3 * npb + 2 * ntb[i] + (ntb[i] & 1) + 64 * npb;
+    }
+    const size_t morton_off = off;
+    if (o.reorder) off += 3 * (size_t)n + (n & 1) + (size_t)npow2_of(n) + 4;
+    const size_t bytes = off * sizeof(double);
+    if (bytes > ctx->ind_cap) {
+        const size_t old = ctx->ind_cap;
+        if (ctx->used.load() - old + bytes > ctx->budget) return res->status = GL_ENOMEM;
+        if (ctx->ind_buf) hipFree(ctx->ind_buf);
+        ctx->ind_buf = nullptr;
+        ctx->ind_cap = 0;
+        ctx->used -= old;
+        if (hipMalloc(&ctx->ind_buf, bytes) != hipSuccess) {
+            (void)hipGetLastError();
+            return res->status = GL_ENOMEM;
+        }
+        ctx->ind_cap = bytes;
+        ctx->used += bytes;
+    }
+    double *base = static_cast<double *>(ctx->ind_buf);
+    BatchReq *ddesc = reinterpret_cast<BatchReq *>(base);
+    DevResult *total = reinterpret_cast<DevResult *>(base + desc_d);
+    DevResult *bres = reinterpret_cast<DevResult *>(base + desc_d + 8);
+    int64_t *binfo = reinterpret_cast<int64_t *>(base + desc_d + 8 + 8 * nblk);
+    const double *sx = x, *sy = y, *sz = z;
+    if (o.reorder) {
+        double *xo = base + morton_off, *yo = xo + n, *zo = yo + n;
+        uint64_t *keys = reinterpret_cast<uint64_t *>(zo + n + (n & 1));
+        launch_morton_order(x, y, z, n, n, keys, xo, yo, zo, nullptr, s);  // unpadded output
+        sx = xo;
+        sy = yo;
+        sz = zo;
+    }
+    std::vector<BatchReq> proto(nblk);
+    for (int64_t i = 0; i < nblk; ++i) {
+        BatchReq &d = proto[i];
+        const int64_t npb = ntb[i] * b;
+        double *p = base + boff[i];
+        d.tiles = p;
+        p += (size_t)tile_count(ntb[i]) * b * b;
+        d.x = p;
+        d.y = p + npb;
+        d.v = p + 2 * npb;
+        p += 3 * npb;
+        d.logsum = p;
+        d.quad = p + ntb[i];
+        p += 2 * ntb[i] + (ntb[i] & 1);
+        d.dinv = p;
+        d.info = binfo + 8 * i;
+        d.res = bres + i;
+        d.sx = sx + i * block;
+        d.sy = sy + i * block;
+        d.sz = sz + i * block;
+        d.th = th;
+        d.geo = geom_of(o);
+        d.n = nb[i];
+        d.nt = ntb[i];
+        d.npad = npb;
+    }
+    // one host array per step: each must outlive its asynchronous copy
+    std::vector<std::vector<BatchReq>> steps((size_t)bt);
+    for (int64_t k = 0; k < bt; ++k) {
+        std::vector<BatchReq> &h = steps[k];
+        for (int64_t i = 0; i < nblk; ++i) {
+            if (k >= ntb[i]) continue;  // the last block may have fewer tile columns
+            BatchReq d = proto[i];
+            d.dinv = proto[i].dinv + k * 64 * (int64_t)b;
+            d.k = k;
+            d.is_new = k == 0;
+            d.finishing = k == ntb[i] - 1;
+            h.push_back(d);
+        }
+        if (h.empty()) break;
+        const int rc = enqueue_step(h.data(), ddesc, (int)h.size(), b, s, nullptr);
+        if (rc != GL_OK) return res->status = rc;
+    }
+    ind_total_kernel<<<1, 64, 0, s>>>(bres, nblk, block, total);
+    GL_HIP_TRY(hipGetLastError());
+    GL_HIP_TRY(hipMemcpyAsync(ctx->res_h, total, sizeof(DevResult), hipMemcpyDeviceToHost, s));
+    GL_HIP_TRY(hipStreamSynchronize(s));
+    fill_result(res, *ctx->res_h, b);
+    return res->status;
+}
+
+}  // namespace gl

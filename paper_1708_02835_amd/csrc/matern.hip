@@ -105,8 +105,12 @@ __global__ __launch_bounds__(256) void gen_batched_kernel(const BatchReq *__rest
 void launch_gen_batched(int b, const BatchReq *d, int count, int64_t tiles, hipStream_t s)
 {
     if (tiles <= 0) return;
-    if (b == 128) gen_batched_kernel<128><<<(unsigned)tiles, 256, 0, s>>>(d, count);
-    else gen_batched_kernel<256><<<(unsigned)tiles, 256, 0, s>>>(d, count);
+    switch (b) {
+    case 128: gen_batched_kernel<128><<<(unsigned)tiles, 256, 0, s>>>(d, count); break;
+    case 256: gen_batched_kernel<256><<<(unsigned)tiles, 256, 0, s>>>(d, count); break;
+    case 384: gen_batched_kernel<384><<<(unsigned)tiles, 256, 0, s>>>(d, count); break;
+    default: gen_batched_kernel<512><<<(unsigned)tiles, 256, 0, s>>>(d, count); break;
+    }
 }
 
 // Dense column-major n1×n2 covariance between two point sets: out[i + j*ld].

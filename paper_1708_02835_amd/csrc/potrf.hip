@@ -215,8 +215,12 @@ __global__ __launch_bounds__(256) void potrf_batched_kernel(const BatchReq *__re
 
 void launch_potrf_batched(int b, const BatchReq *d, int count, hipStream_t s)
 {
-    if (b == 128) potrf_batched_kernel<128><<<count, 256, 0, s>>>(d);
-    else potrf_batched_kernel<256><<<count, 256, 0, s>>>(d);
+    switch (b) {
+    case 128: potrf_batched_kernel<128><<<count, 256, 0, s>>>(d); break;
+    case 256: potrf_batched_kernel<256><<<count, 256, 0, s>>>(d); break;
+    case 384: potrf_batched_kernel<384><<<count, 256, 0, s>>>(d); break;
+    default: potrf_batched_kernel<512><<<count, 256, 0, s>>>(d); break;
+    }
 }
 
 }  // namespace gl

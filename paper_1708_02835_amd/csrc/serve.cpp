@@ -229,9 +229,6 @@ int build_tick(lq_queue *q, Cohort &co)
     TickBuf &tb = co.ring[co.ring_next];
     if (tb.busy) return GL_EBUSY;
     const int count = (int)co.residents.size();
-    int64_t o_stage = 0, o_gen = 0, o_trsm = 0, o_tr = 0;
-    const int64_t sub = (TICK_B / 128) * (TICK_B / 128);
-    bool any_new = false, any_fin = false;
     for (int i = 0; i < count; ++i) {
         Resident &r = co.residents[i];
         Work &w = *r.w;
@@ -255,41 +252,14 @@ int build_tick(lq_queue *q, Cohort &co)
         d.nt = w.nt;
         d.npad = w.npad;
         d.k = r.k;
-        d.o_stage = o_stage;
-        d.o_gen = o_gen;
-        d.o_trsm = o_trsm;
-        d.o_tr = o_tr;
         d.is_new = r.is_new ? 1 : 0;
         d.finishing = (r.k == w.nt - 1) ? 1 : 0;
-        if (r.is_new) {
-            o_stage += ceil_div(w.npad, 256);
-            o_gen += tile_count(w.nt);
-            any_new = true;
-        }
-        const int64_t m = w.nt - r.k - 1;
-        o_trsm += m * (TICK_B / 64);
-        o_tr += m * (m + 1) / 2 * sub;
-        any_fin = any_fin || d.finishing;
     }
     hipStream_t s = co.s;
-    GL_HIP_TRY(hipMemcpyAsync(tb.dev, tb.host, count * sizeof(BatchReq), hipMemcpyHostToDevice, s));
     int launches = 0;
-    if (any_new) {
-        launch_stage_batched(tb.dev, count, o_stage, s);
-        launch_gen_batched(TICK_B, tb.dev, count, o_gen, s);
-        launches += 2;
-    }
-    launch_potrf_batched(TICK_B, tb.dev, count, s);
-    launch_fwd_diag_batched(TICK_B, tb.dev, count, s);
-    launch_trsm_batched(TICK_B, tb.dev, count, o_trsm, s);
-    launch_fwd_update_batched(TICK_B, tb.dev, count, o_trsm, s);
-    launch_trailing_batched(TICK_B, tb.dev, count, o_tr, s);
-    launches += 5;
+    const int rc = enqueue_step(tb.host, tb.dev, count, TICK_B, s, &launches);
+    if (rc != GL_OK) return rc;
     tb.finishing.clear();
-    if (any_fin) {
-        launch_final_batched(tb.dev, count, s);
-        ++launches;
-    }
     GL_HIP_TRY(hipGetLastError());
     std::vector<Resident> keep;
     keep.reserve(co.residents.size());

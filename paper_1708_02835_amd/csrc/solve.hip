@@ -308,15 +308,23 @@ __global__ void stage_batched_kernel(const BatchReq *__restrict__ d, int count)
 
 void launch_fwd_diag_batched(int b, const BatchReq *d, int count, hipStream_t s)
 {
-    if (b == 128) fwd_diag_batched_kernel<128><<<count, 256, 0, s>>>(d);
-    else fwd_diag_batched_kernel<256><<<count, 256, 0, s>>>(d);
+    switch (b) {
+    case 128: fwd_diag_batched_kernel<128><<<count, 256, 0, s>>>(d); break;
+    case 256: fwd_diag_batched_kernel<256><<<count, 256, 0, s>>>(d); break;
+    case 384: fwd_diag_batched_kernel<384><<<count, 256, 0, s>>>(d); break;
+    default: fwd_diag_batched_kernel<512><<<count, 256, 0, s>>>(d); break;
+    }
 }
 
 void launch_fwd_update_batched(int b, const BatchReq *d, int count, int64_t blocks, hipStream_t s)
 {
     if (blocks <= 0) return;
-    if (b == 128) fwd_update_batched_kernel<128><<<(unsigned)blocks, 256, 0, s>>>(d, count);
-    else fwd_update_batched_kernel<256><<<(unsigned)blocks, 256, 0, s>>>(d, count);
+    switch (b) {
+    case 128: fwd_update_batched_kernel<128><<<(unsigned)blocks, 256, 0, s>>>(d, count); break;
+    case 256: fwd_update_batched_kernel<256><<<(unsigned)blocks, 256, 0, s>>>(d, count); break;
+    case 384: fwd_update_batched_kernel<384><<<(unsigned)blocks, 256, 0, s>>>(d, count); break;
+    default: fwd_update_batched_kernel<512><<<(unsigned)blocks, 256, 0, s>>>(d, count); break;
+    }
 }
 
 void launch_final_batched(const BatchReq *d, int count, hipStream_t s)

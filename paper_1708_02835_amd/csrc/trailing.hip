@@ -223,8 +223,12 @@ void launch_trailing_batched(int b, const BatchReq *d, int count, int64_t blocks
 {
     if (blocks <= 0) return;
     const int64_t grid = ceil_div(blocks, 8) * 8;
-    if (b == 128) trailing_batched_kernel<128><<<(unsigned)grid, 256, 0, s>>>(d, count, blocks);
-    else trailing_batched_kernel<256><<<(unsigned)grid, 256, 0, s>>>(d, count, blocks);
+    switch (b) {
+    case 128: trailing_batched_kernel<128><<<(unsigned)grid, 256, 0, s>>>(d, count, blocks); break;
+    case 256: trailing_batched_kernel<256><<<(unsigned)grid, 256, 0, s>>>(d, count, blocks); break;
+    case 384: trailing_batched_kernel<384><<<(unsigned)grid, 256, 0, s>>>(d, count, blocks); break;
+    default: trailing_batched_kernel<512><<<(unsigned)grid, 256, 0, s>>>(d, count, blocks); break;
+    }
 }
 
 // Trailing updates of the tiles listed in `list` (count tiles, (i, j) pairs).

@@ -167,8 +167,12 @@ __global__ __launch_bounds__(256) void trsm_batched_kernel(const BatchReq *__res
 void launch_trsm_batched(int b, const BatchReq *d, int count, int64_t blocks, hipStream_t s)
 {
     if (blocks <= 0) return;
-    if (b == 128) trsm_batched_kernel<128><<<(unsigned)blocks, 256, 0, s>>>(d, count);
-    else trsm_batched_kernel<256><<<(unsigned)blocks, 256, 0, s>>>(d, count);
+    switch (b) {
+    case 128: trsm_batched_kernel<128><<<(unsigned)blocks, 256, 0, s>>>(d, count); break;
+    case 256: trsm_batched_kernel<256><<<(unsigned)blocks, 256, 0, s>>>(d, count); break;
+    case 384: trsm_batched_kernel<384><<<(unsigned)blocks, 256, 0, s>>>(d, count); break;
+    default: trsm_batched_kernel<512><<<(unsigned)blocks, 256, 0, s>>>(d, count); break;
+    }
 }
 
 // Many right-hand sides (kriging variances, Eq. 4): U = L⁻¹ S is solved in

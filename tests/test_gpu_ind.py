@@ -1,0 +1,115 @@
+"""GPU parity of the independent-blocks (IND) approximation (Sec. 6.8)
+against the oracle, and its relation to the exact path."""
+import math
+
+import numpy as np
+import pytest
+
+import geoinputs
+import oracle
+from morton_ref import morton_reference
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def g():
+    import paper_1708_02835_amd as pkg
+    pkg.lib()
+    return pkg
+
+
+@pytest.fixture(scope="module")
+def ctx(g):
+    c = g.Context(0)
+    yield c
+    c.close()
+
+
+def dev(a):
+    return torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+
+
+@pytest.mark.parametrize("n,tile,s", [(1600, 128, 1), (1600, 128, 2), (1600, 128, 3), (1100, 256, 2),
+                                      (1300, 512, 1), (1000, 384, 2), (700, 128, 40)])
+@pytest.mark.parametrize("theta", [(1.0, 0.1, 0.5), (1.3, 0.07, 1.0)])
+def test_ind_parity(g, ctx, n, tile, s, theta):
+    x, y = geoinputs.jittered_grid(n, 13)
+    z = geoinputs.normal_vector(n, 13)
+    ref = oracle.loglik_ind(x, y, z, theta, s * tile)
+    assert ref[3] == 0
+    r = g.loglik_eval(ctx, dev(x), dev(y), dev(z), theta, g.gl_opts_default(tile=tile, ind_tiles=s))
+    assert r["status"] == g.GL_OK and r["tile"] == tile
+    assert abs(r["loglik"] - ref[0]) <= 1e-10 * abs(ref[0])
+    assert abs(r["logdet"] - ref[1]) <= 1e-10 * abs(ref[1])
+    assert abs(r["quad"] - ref[2]) <= 1e-10 * abs(ref[2])
+
+
+def test_ind_covering_block_equals_exact(g, ctx):
+    n, theta = 1500, (1.0, 0.1, 0.5)
+    x, y = geoinputs.jittered_grid(n, 14)
+    z = geoinputs.normal_vector(n, 14)
+    exact = g.loglik_eval(ctx, dev(x), dev(y), dev(z), theta, g.gl_opts_default(tile=256))
+    ind = g.loglik_eval(ctx, dev(x), dev(y), dev(z), theta, g.gl_opts_default(tile=256, ind_tiles=6))
+    assert ind["loglik"] == exact["loglik"] and ind["logdet"] == exact["logdet"]
+
+
+def test_ind_morton_order_and_great_circle(g, ctx):
+    n, theta = 1200, (1.0, 150.0, 0.5)
+    x, y = geoinputs.jittered_grid(n, 15)
+    x, y = -100.0 + 15.0 * x, 30.0 + 15.0 * y
+    z = geoinputs.normal_vector(n, 15)
+    p = morton_reference(x, y)
+    ref = oracle.loglik_ind(x[p], y[p], z[p], theta, 256, metric=oracle.GREAT_CIRCLE, radius=6371.0)
+    r = g.loglik_eval(ctx, dev(x), dev(y), dev(z), theta,
+                      g.gl_opts_default(tile=128, ind_tiles=2, reorder=1, metric=g.GL_GREAT_CIRCLE, radius=6371.0))
+    assert r["status"] == g.GL_OK
+    assert abs(r["loglik"] - ref[0]) <= 1e-10 * abs(ref[0])
+
+
+def test_ind_not_spd_reports_global_column(g, ctx):
+    n = 900
+    x, y = geoinputs.jittered_grid(n, 16)
+    x[600], y[600] = x[599], y[599]  # inside the third block of 256
+    z = geoinputs.normal_vector(n, 16)
+    ref = oracle.loglik_ind(x, y, z, (1.0, 0.1, 0.5), 256)
+    r = g.loglik_eval(ctx, dev(x), dev(y), dev(z), (1.0, 0.1, 0.5), g.gl_opts_default(tile=128, ind_tiles=2))
+    assert (r["status"] == g.GL_NOT_SPD) == (ref[3] != 0)
+    if ref[3] != 0:
+        assert r["info"] == ref[3] and r["loglik"] == -math.inf
+    # the other blocks are unaffected: the sum without the failing block matches
+    ok = g.loglik_eval(ctx, dev(x[:512]), dev(y[:512]), dev(z[:512]), (1.0, 0.1, 0.5),
+                       g.gl_opts_default(tile=128, ind_tiles=2))
+    assert abs(ok["loglik"] - oracle.loglik_ind(x[:512], y[:512], z[:512], (1.0, 0.1, 0.5), 256)[0]) <= 1e-10 * abs(ok["loglik"])
+
+
+def test_ind_rejects_unsupported_options(g, ctx):
+    x, y = geoinputs.jittered_grid(300, 17)
+    for kw in ({"precision": 2}, {"keep_factor": 1}, {"ind_tiles": -1}):
+        with pytest.raises(g.GeolikError):
+            g.loglik_eval(ctx, dev(x), dev(y), dev(x), (1.0, 0.1, 0.5), g.gl_opts_default(ind_tiles=2, **kw) if "ind_tiles" not in kw else g.gl_opts_default(**kw))
+
+
+def test_ind_n100000_is_the_sum_of_exact_block_evaluations(g):
+    """At the benchmark size the oracle cannot run every block; the exact path
+    (itself pinned to the oracle) evaluates the 49 blocks one by one."""
+    n, theta, tile, s = 100000, (1.0, 0.1, 0.5), 512, 4
+    x, y = geoinputs.jittered_grid(n, 3000)
+    e = geoinputs.normal_vector(n, 3000)
+    ctx = g.Context(0)
+    try:
+        xd, yd, ed = dev(x), dev(y), dev(e)
+        zd, info = g.synth_generate(ctx, xd, yd, ed, theta, tile)
+        assert info == 0
+        r = g.loglik_eval(ctx, xd, yd, zd, theta, g.gl_opts_default(tile=tile, ind_tiles=s))
+        assert r["status"] == g.GL_OK
+        blk = s * tile
+        parts = [g.loglik_eval(ctx, xd[a:a + blk].contiguous(), yd[a:a + blk].contiguous(), zd[a:a + blk].contiguous(),
+                               theta, g.gl_opts_default(tile=tile)) for a in range(0, n, blk)]
+        total = math.fsum(p["loglik"] for p in parts)
+        assert abs(r["loglik"] - total) <= 1e-12 * abs(total)
+        exact = g.loglik_eval(ctx, xd, yd, zd, theta, g.gl_opts_default(tile=tile))
+        print(f"n=100000 IND s={s}: l_IND={r['loglik']:.6f} exact={exact['loglik']:.6f}")
+    finally:
+        ctx.close()

@@ -19,6 +19,7 @@ import pytest
 
 import geoinputs
 import oracle
+from morton_ref import morton_reference
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
@@ -44,28 +45,6 @@ def dev(a):
 
 def rel(a, b):
     return abs(a - b) / abs(b)
-
-
-def morton_reference(x, y):
-    """Permutation of the documented keys: 16-bit quantisation over the bounding
-    box, x in the even bits, ties broken by the input index."""
-    def q(v):
-        lo, hi = v.min(), v.max()
-        span = hi - lo
-        if not span > 0:
-            return np.zeros(v.size, dtype=np.uint64)
-        f = np.floor((v - lo) / span * 65535.0)
-        return np.clip(f, 0, 65535).astype(np.uint64)
-
-    def spread(v):
-        v = (v | (v << np.uint64(8))) & np.uint64(0x00FF00FF)
-        v = (v | (v << np.uint64(4))) & np.uint64(0x0F0F0F0F)
-        v = (v | (v << np.uint64(2))) & np.uint64(0x33333333)
-        v = (v | (v << np.uint64(1))) & np.uint64(0x55555555)
-        return v
-    code = spread(q(x)) | (spread(q(y)) << np.uint64(1))
-    keys = (code << np.uint64(32)) | np.arange(x.size, dtype=np.uint64)
-    return np.argsort(keys, kind="stable")
 
 
 @pytest.mark.parametrize("case", ["grid", "uniform", "duplicates", "tiny", "line"])
