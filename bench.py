@@ -44,6 +44,7 @@ def parse():
                    help="second parameter vector of the mixed-precision comparison")
     p.add_argument("--no-serve", action="store_true", help="skip the serving leg")
     p.add_argument("--no-ind", action="store_true", help="skip the independent-blocks leg")
+    p.add_argument("--no-graph", action="store_true", help="skip the small-n graph-replay latency leg")
     p.add_argument("--serve-clients", type=int, default=64)
     p.add_argument("--serve-evals", type=int, default=5, help="l(theta) requests per client")
     p.add_argument("--serve-rate", type=float, default=400.0, help="client arrivals per second (Poisson)")
@@ -169,6 +170,35 @@ def ind_legs(g, ctx, xd, yd, zd, theta, args, res64, t64, log):
         out.append({"super_tile": s, "block_points": s * args.tile, "ms": dt * 1e3, "speedup_vs_exact": t64 / dt,
                     "loglik": r["loglik"], "rel_diff_vs_exact": abs(r["loglik"] - res64["loglik"]) / abs(res64["loglik"])})
         log(f"IND s={s}: {dt * 1e3:.1f} ms, l={r['loglik']:.6f}")
+    return out
+
+
+def graph_leg(g, ctx, args, log):
+    """Latency of repeated small evaluations (an optimiser on one dataset):
+    direct launches against the replayed hipGraph, same inputs and θ walk."""
+    import numpy as np
+    import torch
+
+    import geoinputs
+    out = []
+    for n in (1000, 2000, 4000):
+        x, y = geoinputs.jittered_grid(n, args.seed + n)
+        z = geoinputs.normal_vector(n, args.seed + n)
+        xd, yd, zd = (torch.as_tensor(a).cuda() for a in (x, y, z))
+        thetas = [(1.0, 0.1 * (1 + 0.01 * i), 0.5) for i in range(40)]
+        row = {"n": n}
+        for mode in (0, 1):
+            opts = g.gl_opts_default(graph=mode)
+            g.loglik_eval(ctx, xd, yd, zd, thetas[0], opts)
+            lat = []
+            for th in thetas:
+                t0 = time.perf_counter()
+                g.loglik_eval(ctx, xd, yd, zd, th, opts)
+                lat.append(time.perf_counter() - t0)
+            row["graph_ms" if mode else "direct_ms"] = float(np.median(lat) * 1e3)
+        row["speedup"] = row["direct_ms"] / row["graph_ms"]
+        log(f"graph n={n}: direct {row['direct_ms']:.3f} ms, graph {row['graph_ms']:.3f} ms")
+        out.append(row)
     return out
 
 
@@ -370,6 +400,8 @@ def main():
         out["mixed"] = mixed_legs(g, ctx, xd, yd, ed, zd, theta, tuple(args.theta_b), args, res, step_s, log)
     if not args.no_ind:
         out["ind"] = ind_legs(g, ctx, xd, yd, zd, theta, args, res, step_s, log)
+    if not args.no_graph:
+        out["graph_replay"] = graph_leg(g, ctx, args, log)
     if not args.no_serve:
         out["serving"] = serving_leg(g, ctx, args, log)
     ctx.close()

@@ -102,7 +102,10 @@ typedef struct {
                             annihilated, i.e. l is summed over blocks of s·b consecutive
                             locations (after reordering, if on), each factored on its own;
                             GL_FP64 only, no kept factor */
-    int32_t reserved;    /* 0 */
+    int32_t graph;       /* 1: GL_FP64 without a kept factor runs everything after staging the
+                            inputs as a replayed hipGraph, captured on the first call for a
+                            workspace geometry (n, tile) and distance and replayed while they
+                            stay the same (θ is read from device memory); 0: direct launches */
 } gl_opts;
 
 /* Result of one likelihood evaluation, host memory. */

@@ -49,6 +49,8 @@ inline Geom geom_of(const gl_opts &o) { return Geom{o.metric, o.radius}; }
 // Matérn generation
 void launch_gen_tiles(double *tiles, const double *x, const double *y, int64_t n, int b, int64_t nt,
                       gl_theta th, Geom geo, double *tile_norm2, hipStream_t s);
+void launch_gen_tiles_dev(double *tiles, const double *x, const double *y, int64_t n, int b, int64_t nt,
+                          const gl_theta *thp, Geom geo, hipStream_t s);
 void launch_gen_dense(const double *x1, const double *y1, int64_t n1, const double *x2,
                       const double *y2, int64_t n2, gl_theta th, Geom geo, double *out, int64_t ld,
                       hipStream_t s);

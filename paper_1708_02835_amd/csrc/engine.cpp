@@ -22,6 +22,8 @@ int gl_hip_fail(hipError_t e, const char *what)
 
 namespace gl {
 
+static void graph_drop(gl_context *ctx);
+
 int pick_tile(int64_t n, int32_t requested)
 {
     if (requested == 128 || requested == 256 || requested == 384 || requested == 512) return requested;
@@ -233,7 +235,7 @@ void gl_opts_default(gl_opts *o)
     o->tol_64 = -1.0;
     o->accuracy = -1.0;
     o->ind_tiles = 0;
-    o->reserved = 0;
+    o->graph = 0;
     o->radius = 6371.0;
 }
 
@@ -276,6 +278,12 @@ void gl_context_destroy(gl_context *c)
     hipDeviceSynchronize();
     c->ws.release();
     if (c->ind_buf) hipFree(c->ind_buf);
+    graph_drop(c);
+    if (c->gs) hipStreamDestroy(c->gs);
+    for (hipEvent_t e : c->gev)
+        if (e) hipEventDestroy(e);
+    if (c->theta_h) hipHostFree(c->theta_h);
+    if (c->theta_d) hipFree(c->theta_d);
     for (gl_factor *f : c->factors) {
         f->w.release();
         delete f;
@@ -341,6 +349,7 @@ bool valid_opts(const gl_opts &o)
 {
     if (!valid_metric(o)) return false;
     if (o.ind_tiles < 0 || (o.ind_tiles > 0 && (o.precision != GL_FP64 || o.keep_factor))) return false;
+    if (o.graph < 0 || o.graph > 1) return false;
     if (o.precision < GL_FP64 || o.precision > GL_MIXED_BF16) return false;
     if (o.tile != 0 && o.tile != 128 && o.tile != 256 && o.tile != 384 && o.tile != 512) return false;
     if (o.reorder < -1 || o.reorder > 1) return false;
@@ -369,6 +378,73 @@ gl_opts resolved_opts(const gl_opts &in)
     if (o.accuracy < 0) o.accuracy = 1e-4;
     if (o.reorder < 0) o.reorder = (o.precision == GL_FP64) ? 0 : 1;
     return o;
+}
+
+// FP64 evaluation through a captured hipGraph of everything after staging:
+// fill, Σ(θ) generation with θ read from device memory, the tiled
+// factorisation with its lookahead lane, the final reduction.  The graph is
+// captured on the first call for a workspace geometry and distance and
+// replayed afterwards; the staging copies and θ's upload run outside it, on
+// the same internal stream, ordered after the caller's stream.
+static void graph_drop(gl_context *ctx)
+{
+    if (ctx->gexec) hipGraphExecDestroy(ctx->gexec);
+    ctx->gexec = nullptr;
+    ctx->gkey_tiles = nullptr;
+}
+
+static int graph_eval(gl_context *ctx, Work &w, const double *x, const double *y, const double *z, gl_theta th,
+                      const gl_opts &o, hipStream_t s)
+{
+    if (!ctx->gs) {
+        GL_HIP_TRY(hipStreamCreateWithFlags(&ctx->gs, hipStreamNonBlocking));
+        GL_HIP_TRY(hipEventCreateWithFlags(&ctx->gev[0], hipEventDisableTiming));
+        GL_HIP_TRY(hipEventCreateWithFlags(&ctx->gev[1], hipEventDisableTiming));
+        GL_HIP_TRY(hipHostMalloc(reinterpret_cast<void **>(&ctx->theta_h), sizeof(gl_theta), hipHostMallocDefault));
+        GL_HIP_TRY(hipMalloc(reinterpret_cast<void **>(&ctx->theta_d), sizeof(gl_theta)));
+    }
+    hipStream_t g = ctx->gs;
+    const Geom geo = geom_of(o);
+    GL_HIP_TRY(hipEventRecord(ctx->gev[0], s));
+    GL_HIP_TRY(hipStreamWaitEvent(g, ctx->gev[0], 0));
+    stage_inputs(w, x, y, z, o.reorder, g);
+    *ctx->theta_h = th;  // the previous call synchronised, so the last upload is done
+    GL_HIP_TRY(hipMemcpyAsync(ctx->theta_d, ctx->theta_h, sizeof(gl_theta), hipMemcpyHostToDevice, g));
+    const bool hit = ctx->gexec && ctx->gkey_tiles == w.tiles && ctx->gkey_n == w.n && ctx->gkey_b == w.b &&
+                     ctx->gkey_geo.metric == geo.metric && ctx->gkey_geo.radius == geo.radius;
+    if (!hit) {
+        graph_drop(ctx);
+        Lanes ln = ctx->lanes;
+        ln.prof = nullptr;  // no timing events inside a graph
+        GL_HIP_TRY(hipStreamBeginCapture(g, hipStreamCaptureModeThreadLocal));
+        launch_fill(reinterpret_cast<double *>(w.info), 1, 0.0, g);
+        launch_gen_tiles_dev(w.tiles, w.x, w.y, w.n, w.b, w.nt, ctx->theta_d, geo, g);
+        int rc = factorize(ln, w, g, true);
+        launch_final_reduce(w.logsum, w.quad, w.nt, w.n, w.info, w.res, g);
+        hipGraph_t graph = nullptr;
+        const hipError_t ec = hipStreamEndCapture(g, &graph);
+        if (rc != GL_OK || ec != hipSuccess) {
+            if (graph) hipGraphDestroy(graph);
+            (void)hipGetLastError();
+            return rc != GL_OK ? rc : GL_EHIP;
+        }
+        const hipError_t ei = hipGraphInstantiate(&ctx->gexec, graph, nullptr, nullptr, 0);
+        hipGraphDestroy(graph);
+        if (ei != hipSuccess) {
+            ctx->gexec = nullptr;
+            return GL_EHIP;
+        }
+        ctx->gkey_tiles = w.tiles;
+        ctx->gkey_n = w.n;
+        ctx->gkey_b = w.b;
+        ctx->gkey_geo = geo;
+    }
+    GL_HIP_TRY(hipGraphLaunch(ctx->gexec, g));
+    GL_HIP_TRY(hipMemcpyAsync(ctx->res_h, w.res, sizeof(DevResult), hipMemcpyDeviceToHost, g));
+    GL_HIP_TRY(hipEventRecord(ctx->gev[1], g));
+    GL_HIP_TRY(hipStreamWaitEvent(s, ctx->gev[1], 0));
+    GL_HIP_TRY(hipStreamSynchronize(g));
+    return GL_OK;
 }
 
 void fill_result(gl_result *res, const DevResult &d, int b)
@@ -414,7 +490,9 @@ int loglik_eval(gl_context *ctx, const double *x, const double *y, const double 
         w = &f->w;
     }
     int rc = w->ensure(ctx, n, b, o.precision);
-    if (rc == GL_OK) {
+    if (rc == GL_OK && o.graph && o.precision == GL_FP64 && !f) {
+        rc = graph_eval(ctx, *w, x, y, z, th, o, s);
+    } else if (rc == GL_OK) {
         stage_inputs(*w, x, y, z, o.reorder, s);
         rc = eval_launch(ctx->lanes, *w, th, o, s, ctx->res_h, &ctx->last_plan);
         if (rc == GL_OK && hipStreamSynchronize(s) != hipSuccess) rc = GL_EHIP;

@@ -137,4 +137,15 @@ struct gl_context {
     gl::ServeState *serve = nullptr;
     void *ind_buf = nullptr;  // workspace of the independent-blocks evaluations
     size_t ind_cap = 0;
+    // replayed evaluation graph (gl_opts.graph): one entry, keyed by the
+    // workspace geometry and the distance
+    hipStream_t gs = nullptr;        // stream the graph is captured on and replayed on
+    hipEvent_t gev[2] = {nullptr, nullptr};
+    hipGraphExec_t gexec = nullptr;
+    const void *gkey_tiles = nullptr;
+    int64_t gkey_n = 0;
+    int gkey_b = 0;
+    gl::Geom gkey_geo{0, 0.0};
+    gl_theta *theta_h = nullptr;  // pinned
+    gl_theta *theta_d = nullptr;  // device
 };

@@ -93,6 +93,28 @@ void launch_gen_tiles(double *tiles, const double *x, const double *y, int64_t n
     }
 }
 
+// The same, with θ read from device memory (replayed hipGraphs: the graph
+// stays valid while θ changes between replays).
+template <int B>
+__global__ __launch_bounds__(256) void gen_tiles_dev_kernel(double *__restrict__ tiles, const double *__restrict__ x,
+                                                            const double *__restrict__ y, int64_t n,
+                                                            const gl_theta *__restrict__ thp, Geom geo)
+{
+    gen_tiles_body<B>(tiles, x, y, n, *thp, geo, nullptr, blockIdx.x);
+}
+
+void launch_gen_tiles_dev(double *tiles, const double *x, const double *y, int64_t n, int b, int64_t nt,
+                          const gl_theta *thp, Geom geo, hipStream_t s)
+{
+    dim3 grid((unsigned)tile_count(nt));
+    switch (b) {
+    case 128: gen_tiles_dev_kernel<128><<<grid, 256, 0, s>>>(tiles, x, y, n, thp, geo); break;
+    case 256: gen_tiles_dev_kernel<256><<<grid, 256, 0, s>>>(tiles, x, y, n, thp, geo); break;
+    case 384: gen_tiles_dev_kernel<384><<<grid, 256, 0, s>>>(tiles, x, y, n, thp, geo); break;
+    default: gen_tiles_dev_kernel<512><<<grid, 256, 0, s>>>(tiles, x, y, n, thp, geo); break;
+    }
+}
+
 template <int B>
 __global__ __launch_bounds__(256) void gen_batched_kernel(const BatchReq *__restrict__ d, int count)
 {
