@@ -34,6 +34,14 @@ __device__ __forceinline__ void gen_tiles_body(double *__restrict__ tiles, const
     int64_t ti, tj;
     tile_from_index(t, ti, tj);
     const MaternSetup ms = matern_setup(th.theta1, th.theta2, th.theta3);
+    __shared__ BesselTab tab;
+    __shared__ double xcs[B], ycs[B];  // the tile's column locations
+    for (int c = threadIdx.x; c < B; c += 256) {
+        const int64_t gc = tj * B + c;
+        xcs[c] = gc < n ? x[gc] : 0.0;
+        ycs[c] = gc < n ? y[gc] : 0.0;
+    }
+    bessel_tab_init(ms, tab);  // ends with the barrier the staging needs too
     double *T = tiles + t * (int64_t)B * B;
     constexpr int RPT = (B + 255) / 256;
     double xr[RPT], yr[RPT];
@@ -50,14 +58,14 @@ __device__ __forceinline__ void gen_tiles_body(double *__restrict__ tiles, const
     for (int c = 0; c < B; ++c) {
         const int64_t gc = tj * B + c;
         const bool colok = gc < n;
-        const double xc = colok ? x[gc] : 0.0;
-        const double yc = colok ? y[gc] : 0.0;
+        const double xc = xcs[c];
+        const double yc = ycs[c];
 #pragma unroll
         for (int q = 0; q < RPT; ++q) {
             int r = threadIdx.x + 256 * q;
             if (r >= B) continue;
             double v;
-            if (colok && gr[q] < n) v = matern_eval(ms, geo_dist(geo, xr[q], yr[q], xc, yc));
+            if (colok && gr[q] < n) v = matern_eval(ms, geo_dist(geo, xr[q], yr[q], xc, yc), &tab);
             else v = (gr[q] == gc) ? 1.0 : 0.0;
             T[(int64_t)c * B + r] = v;
             ss += v * v;
@@ -146,13 +154,15 @@ __global__ __launch_bounds__(256) void gen_dense_kernel(const double *__restrict
 {
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
     const int64_t j0 = (int64_t)blockIdx.y * 16;
-    if (i >= n1) return;
     const MaternSetup ms = matern_setup(th.theta1, th.theta2, th.theta3);
+    __shared__ BesselTab tab;
+    bessel_tab_init(ms, tab);
+    if (i >= n1) return;
     const double xi = x1[i], yi = y1[i];
     for (int c = 0; c < 16; ++c) {
         int64_t j = j0 + c;
         if (j >= n2) break;
-        out[i + j * ld] = matern_eval(ms, geo_dist(geo, xi, yi, x2[j], y2[j]));
+        out[i + j * ld] = matern_eval(ms, geo_dist(geo, xi, yi, x2[j], y2[j]), &tab);
     }
 }
 
@@ -179,12 +189,14 @@ __global__ __launch_bounds__(256) void krige_kernel(const double *__restrict__ x
     const int64_t k = blockIdx.x;
     const int64_t c = blockIdx.y;
     const MaternSetup ms = matern_setup(th.theta1, th.theta2, th.theta3);
+    __shared__ BesselTab tab;
+    bessel_tab_init(ms, tab);
     const double xk = xn[k], yk = yn[k];
     const int64_t j0 = c * KRIGE_CHUNK;
     const int64_t j1 = min(n, j0 + KRIGE_CHUNK);
     double acc = 0.0;
     for (int64_t j = j0 + threadIdx.x; j < j1; j += 256)
-        acc += matern_eval(ms, geo_dist(geo, xk, yk, x[j], y[j])) * v[j];
+        acc += matern_eval(ms, geo_dist(geo, xk, yk, x[j], y[j]), &tab) * v[j];
     __shared__ double red[4];
     double w = wave_sum(acc);
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = w;
@@ -230,6 +242,8 @@ __global__ __launch_bounds__(256) void gen_rhs_kernel(double *__restrict__ st, c
     const int64_t t = blockIdx.x;
     const int64_t c = t / nt, i = t % nt;
     const MaternSetup ms = matern_setup(th.theta1, th.theta2, th.theta3);
+    __shared__ BesselTab tab;
+    bessel_tab_init(ms, tab);
     double *T = st + t * (int64_t)B * B;
     constexpr int RPT = (B + 255) / 256;
     double xr[RPT], yr[RPT];
@@ -251,7 +265,7 @@ __global__ __launch_bounds__(256) void gen_rhs_kernel(double *__restrict__ st, c
         for (int q = 0; q < RPT; ++q) {
             const int r = threadIdx.x + 256 * q;
             if (r >= B) continue;
-            T[(int64_t)p * B + r] = (pok && rok[q]) ? matern_eval(ms, geo_dist(geo, xr[q], yr[q], xp, yp)) : 0.0;
+            T[(int64_t)p * B + r] = (pok && rok[q]) ? matern_eval(ms, geo_dist(geo, xr[q], yr[q], xp, yp), &tab) : 0.0;
         }
     }
 }

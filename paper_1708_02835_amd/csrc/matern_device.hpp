@@ -80,8 +80,35 @@ __host__ __device__ inline MaternSetup matern_setup(double t1, double t2, double
     return s;
 }
 
+// Reciprocals the series and recurrences below divide by, for one μ: filled
+// once per workgroup in LDS so the per-element loops only multiply
+// (1/(k-μ), 1/(k+μ) for the series, 1/k for both).
+constexpr int GL_TEMME_TERMS = 40;
+constexpr int GL_MILLER_MAX = 80;
+struct BesselTab {
+    double rm[GL_TEMME_TERMS];   // 1/(k - μ)
+    double rp[GL_TEMME_TERMS];   // 1/(k + μ)
+    double rk[GL_MILLER_MAX + 1];  // 1/k
+};
+
+// Every thread of the workgroup calls this before the first matern_eval with
+// the table; it ends with a barrier.
+__device__ inline void bessel_tab_init(const MaternSetup &s, BesselTab &t)
+{
+    for (int k = threadIdx.x; k <= GL_MILLER_MAX; k += blockDim.x) {
+        const double dk = (double)k;
+        if (k >= 1 && k < GL_TEMME_TERMS) {
+            t.rm[k] = 1.0 / (dk - s.mu);
+            t.rp[k] = 1.0 / (dk + s.mu);
+        }
+        t.rk[k] = k ? 1.0 / dk : 0.0;
+    }
+    __syncthreads();
+}
+
 // K_μ(x) and K_μ+1(x) for x <= 2 (Temme's series), unscaled.
-__host__ __device__ inline void bessel_k_temme(const MaternSetup &s, double x, double &k0, double &k1)
+__host__ __device__ inline void bessel_k_temme(const MaternSetup &s, double x, double &k0, double &k1,
+                                               const BesselTab *tab = nullptr)
 {
     const double mu = s.mu;
     const double lx = log(2.0 / x);
@@ -101,12 +128,20 @@ __host__ __device__ inline void bessel_k_temme(const MaternSetup &s, double x, d
     const double d = 0.25 * x * x;
     double sum0 = f, sum1 = p;
     const double mu2 = mu * mu;
-    for (int k = 1; k < 40; ++k) {
+    for (int k = 1; k < GL_TEMME_TERMS; ++k) {
         double dk = (double)k;
-        f = (dk * f + p + q) / (dk * dk - mu2);
-        c *= d / dk;
-        p /= (dk - mu);
-        q /= (dk + mu);
+        if (tab) {
+            const double rm = tab->rm[k], rp = tab->rp[k];
+            f = (dk * f + p + q) * (rm * rp);
+            c *= d * tab->rk[k];
+            p *= rm;
+            q *= rp;
+        } else {
+            f = (dk * f + p + q) / (dk * dk - mu2);
+            c *= d / dk;
+            p /= (dk - mu);
+            q /= (dk + mu);
+        }
         double t0 = c * f;
         double t1 = c * (p - dk * f);
         sum0 += t0;
@@ -118,11 +153,12 @@ __host__ __device__ inline void bessel_k_temme(const MaternSetup &s, double x, d
 }
 
 // e^x K_μ(x) and e^x K_μ+1(x) for x > 2 (backward recurrence for U ratios).
-__host__ __device__ inline void bessel_k_miller_scaled(const MaternSetup &s, double x, double &k0, double &k1)
+__host__ __device__ inline void bessel_k_miller_scaled(const MaternSetup &s, double x, double &k0, double &k1,
+                                                       const BesselTab *tab = nullptr)
 {
     const double mu2 = s.mu * s.mu;
     int kmax = (int)(8.0 + 140.0 / x);
-    if (kmax > 80) kmax = 80;
+    if (kmax > GL_MILLER_MAX) kmax = GL_MILLER_MAX;
     double z1 = 0.0, z0 = 1.0;  // z_{K+1}, z_K
     double t = 1.0;             // Horner accumulation of Σ c_k z_k from the top
     for (int k = kmax; k >= 1; --k) {
@@ -132,7 +168,7 @@ __host__ __device__ inline void bessel_k_miller_scaled(const MaternSetup &s, dou
         z1 = z0;
         z0 = zm;
         double akm = (dk - 0.5) * (dk - 0.5) - mu2;
-        t = zm + (akm / dk) * t;
+        t = zm + (tab ? akm * tab->rk[k] : akm / dk) * t;
     }
     double ssum = t / z0;
     double r0 = z1 / z0;
@@ -140,8 +176,9 @@ __host__ __device__ inline void bessel_k_miller_scaled(const MaternSetup &s, dou
     k1 = k0 * (s.mu + 0.5 + x - (0.25 - mu2) * r0) / x;
 }
 
-// Matérn covariance at distance r (r >= 0).
-__host__ __device__ inline double matern_eval(const MaternSetup &s, double r)
+// Matérn covariance at distance r (r >= 0); tab (may be NULL) from
+// bessel_tab_init for the same setup.
+__host__ __device__ inline double matern_eval(const MaternSetup &s, double r, const BesselTab *tab = nullptr)
 {
     if (r == 0.0) return s.theta1;
     const double x = r / s.theta2;
@@ -154,15 +191,16 @@ __host__ __device__ inline double matern_eval(const MaternSetup &s, double r)
     if (x > 760.0) return 0.0;  // x^ν e^-x is below the binary64 range for every ν <= 50
     double ka, kb;
     const bool small = (x <= 2.0);
-    if (small) bessel_k_temme(s, x, ka, kb);
-    else bessel_k_miller_scaled(s, x, ka, kb);
+    if (small) bessel_k_temme(s, x, ka, kb, tab);
+    else bessel_k_miller_scaled(s, x, ka, kb, tab);
     double knu;
     if (s.nl == 0) {
         knu = ka;
     } else {
         // (ka, kb) = (K_μ+i-1, K_μ+i) → K_μ+nl
+        const double xi = 1.0 / x;
         for (int i = 1; i < s.nl; ++i) {
-            double kc = ka + (2.0 * (s.mu + i) / x) * kb;
+            double kc = ka + (2.0 * (s.mu + i) * xi) * kb;
             ka = kb;
             kb = kc;
         }
