@@ -45,6 +45,8 @@ def parse():
     p.add_argument("--no-serve", action="store_true", help="skip the serving leg")
     p.add_argument("--no-ind", action="store_true", help="skip the independent-blocks leg")
     p.add_argument("--no-graph", action="store_true", help="skip the small-n graph-replay latency leg")
+    p.add_argument("--no-mle", action="store_true", help="skip the maximum-likelihood (FP64 vs mixed) leg")
+    p.add_argument("--mle-n", type=int, default=8100)
     p.add_argument("--serve-clients", type=int, default=64)
     p.add_argument("--serve-evals", type=int, default=5, help="l(theta) requests per client")
     p.add_argument("--serve-rate", type=float, default=400.0, help="client arrivals per second (Poisson)")
@@ -199,6 +201,49 @@ def graph_leg(g, ctx, args, log):
         row["speedup"] = row["direct_ms"] / row["graph_ms"]
         log(f"graph n={n}: direct {row['direct_ms']:.3f} ms, graph {row['graph_ms']:.3f} ms")
         out.append(row)
+    return out
+
+
+def mle_leg(g, ctx, args, log):
+    """θ̂ from FP64 and from the BF16 mixed mode: Nelder-Mead over log θ,
+    restarted from its own result until it stops improving (a derivative-free
+    stand-in for the paper's BOBYQA), same field and start."""
+    import numpy as np
+    import torch
+    from scipy import optimize
+
+    import geoinputs
+    n, truth = args.mle_n, tuple(args.theta)
+    x, y = geoinputs.jittered_grid(n, args.seed + 7)
+    e = geoinputs.normal_vector(n, args.seed + 7)
+    xd, yd, ed = (torch.as_tensor(a).cuda() for a in (x, y, e))
+    zd, info = g.synth_generate(ctx, xd, yd, ed, truth)
+    if info != 0:
+        return {"error": f"field generation failed, info={info}"}
+    start = np.log([0.7 * truth[0], 1.4 * truth[1], 0.8 * truth[2]])
+    out = {"n": n, "theta_true": list(truth), "optimizer": "Nelder-Mead on log theta with restarts, same start"}
+    for name, prec in (("fp64", g.GL_FP64), ("bf16", g.GL_MIXED_BF16)):
+        opts = g.gl_opts_default(precision=prec)
+
+        def negl(v):
+            r = g.loglik_eval(ctx, xd, yd, zd, tuple(float(t) for t in np.exp(v)), opts)
+            return -r["loglik"] if r["status"] == g.GL_OK else 1e300
+
+        t0 = time.perf_counter()
+        xs, res, nfev = start, None, 0
+        for _ in range(5):
+            r = optimize.minimize(negl, xs, method="Nelder-Mead", options={"xatol": 1e-5, "fatol": 1e-7, "maxfev": 600})
+            nfev += r.nfev
+            if res is not None and r.fun > res.fun - 1e-6:
+                break
+            res, xs = r, r.x
+        res.nfev = nfev
+        dt = time.perf_counter() - t0
+        out[name] = {"theta_hat": [float(v) for v in np.exp(res.x)], "loglik": -float(res.fun),
+                     "evals": int(res.nfev), "seconds": dt}
+        log(f"mle {name}: theta_hat={np.exp(res.x)} in {res.nfev} evals, {dt:.1f} s")
+    a, b = np.array(out["fp64"]["theta_hat"]), np.array(out["bf16"]["theta_hat"])
+    out["max_rel_diff_theta_hat"] = float(np.max(np.abs(b - a) / a))
     return out
 
 
@@ -402,6 +447,8 @@ def main():
         out["ind"] = ind_legs(g, ctx, xd, yd, zd, theta, args, res, step_s, log)
     if not args.no_graph:
         out["graph_replay"] = graph_leg(g, ctx, args, log)
+    if not args.no_mle:
+        out["mle"] = mle_leg(g, ctx, args, log)
     if not args.no_serve:
         out["serving"] = serving_leg(g, ctx, args, log)
     ctx.close()
