@@ -253,7 +253,10 @@ void lq_config_default(lq_config *cfg);
 int lq_create(gl_context *ctx, const lq_config *cfg, lq_queue **q_h);
 
 /* Enqueue l(θ) on dataset ds; thread-safe.  *ticket_h identifies the request.
- * opts may be NULL (defaults; keep_factor is ignored by the queue). */
+ * opts may be NULL (defaults; keep_factor and graph are ignored by the queue).
+ * Errors: GL_EINVAL for an unknown dataset, bad θ or options, or ind_tiles != 0
+ * (the independent-blocks approximation is a direct call only); GL_ECANCELED
+ * once the queue is being destroyed. */
 int lq_submit(lq_queue *q, uint64_t ds, gl_theta theta, const gl_opts *opts, uint64_t *ticket_h);
 
 /* Non-blocking: GL_EBUSY while pending, else copies the result and retires

@@ -196,6 +196,21 @@ def test_serve_cancel_and_release(g, ctx):
         assert r["loglik"] == single(g, ctx, *sets[k // 3], THETAS[0], tile=256)["loglik"]
 
 
+def test_serve_rejects_ind_and_ignores_graph(g, ctx):
+    x, y, z = field(500, 70)
+    ds = register(g, ctx, x, y, z)
+    q = g.lq_create(ctx)
+    try:
+        with pytest.raises(g.GeolikError):
+            g.lq_submit(q, ds, THETAS[0], g.gl_opts_default(ind_tiles=2))
+        r = wait_all(g, q, [g.lq_submit(q, ds, THETAS[0], g.gl_opts_default(graph=1))])[0]
+    finally:
+        g.lq_destroy(q)
+        g.gl_dataset_release(ctx, ds)
+    assert r["status"] == g.GL_OK
+    assert r["loglik"] == single(g, ctx, x, y, z, THETAS[0], tile=256)["loglik"]
+
+
 def test_serve_many_clients_threads(g, ctx):
     """Submission from several host threads while the scheduler runs."""
     import threading
