@@ -8,9 +8,15 @@ locations (g = 317, first 100,000 points), θ = (1, 0.1, 0.5), tile 512, FP64,
 with Z = L e simulated at the same θ (Alg. 1) before timing.  Inputs are
 resident in HBM when the timed region starts.
 
-Printed as one JSON line: evals/s, effective Cholesky TFLOP/s (n³/3 per
-step), the trailing-update kernel's live roofline fraction (HIP events around
-each of its launches), and the oracle timed on the host as the CPU baseline.
+Printed as one JSON line: evals/s of the timed FP64 steps, effective Cholesky
+TFLOP/s (n³/3 per step), the trailing-update kernel's live roofline fraction
+(HIP events around each of its launches) with its HBM traffic from the
+committed counter record, and the oracle timed on one host core as the CPU
+baseline.  Legs outside the timed region, each skippable: mixed precision
+against FP64 at the same size for two θ, the independent-blocks
+approximation per super-tile size, small-n latency with and without graph
+replay, maximum-likelihood estimates FP64 vs mixed, and the request queue
+serving 64 concurrent clients against one-at-a-time evaluation.
 """
 from __future__ import annotations
 
@@ -77,7 +83,7 @@ def cpu_baseline(n_target: int, theta) -> dict:
     import geoinputs
     import oracle
     oracle.build()
-    samples = (1500, 3000)
+    samples = (2000, 4000)  # about 17 s of single-core oracle work
     times = []
     for n in samples:
         x, y = geoinputs.jittered_grid(n, 77)
