@@ -126,8 +126,10 @@ typedef struct {
  * memory at creation).  Errors: GL_EINVAL (out == NULL), GL_ENODEV, GL_EHIP. */
 int gl_context_create(int device, size_t hbm_budget_bytes, gl_context **out);
 
-/* Release every workspace and factor still held.  The caller must not use
- * factors or queues of this context afterwards. */
+/* Release every workspace, factor and dataset still held; queues still alive
+ * are destroyed first (as lq_destroy: running requests finish, queued ones
+ * are cancelled).  The caller must not use factors or queues of this context
+ * afterwards. */
 void gl_context_destroy(gl_context *ctx);
 
 /* Fill *opts with defaults: FP64, automatic tile, no factor kept, band 2,

@@ -275,6 +275,7 @@ void gl_context_destroy(gl_context *c)
 {
     if (!c) return;
     hipSetDevice(c->device);
+    serve_stop_queues(c);
     hipDeviceSynchronize();
     c->ws.release();
     if (c->ind_buf) hipFree(c->ind_buf);

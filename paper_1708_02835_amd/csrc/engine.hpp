@@ -107,6 +107,7 @@ void launch_morton_order(const double *x, const double *y, const double *z, int6
 // serving (serve.cpp)
 struct ServeState;
 void serve_context_cleanup(gl_context *ctx);
+void serve_stop_queues(gl_context *ctx);  // destroys the context's live queues
 
 void fill_result(gl_result *res, const DevResult &d, int b);
 

@@ -64,6 +64,18 @@ static ServeState *serve_state(gl_context *ctx)
     return ctx->serve;
 }
 
+void serve_stop_queues(gl_context *ctx)
+{
+    ServeState *st = ctx->serve;
+    if (!st) return;
+    std::vector<lq_queue *> qs;
+    {
+        std::lock_guard<std::mutex> lk(st->mu);
+        qs = st->queues;
+    }
+    for (lq_queue *q : qs) lq_destroy(q);  // each removes itself from st->queues
+}
+
 void serve_context_cleanup(gl_context *ctx)
 {
     ServeState *st = ctx->serve;

@@ -243,3 +243,21 @@ def test_serve_many_clients_threads(g, ctx):
         for ds in dss:
             g.gl_dataset_release(ctx, ds)
     assert not errors, errors[:3]
+
+
+def test_context_destroy_stops_live_queue(g):
+    """Destroying a context whose queue still holds requests cancels or
+    finishes them and stops the scheduler; the device stays usable."""
+    c = g.Context(0)
+    x, y, z = field(1500, 90)
+    ds = register(g, c, x, y, z)
+    q = g.lq_create(c, g.lq_config_default(max_inflight=2, streams=1))
+    for k in range(6):
+        g.lq_submit(q, ds, THETAS[k % 3])
+    c.close()
+    c2 = g.Context(0)
+    try:
+        r = single(g, c2, x, y, z, THETAS[0], tile=256)
+        assert r["status"] == g.GL_OK
+    finally:
+        c2.close()
