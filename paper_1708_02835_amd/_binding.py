@@ -152,11 +152,25 @@ def _theta(theta) -> gl_theta:
     return gl_theta(t1, t2, t3)
 
 
+def _set_fields(obj, kw, what):
+    names = {f for f, _ in type(obj)._fields_}
+    for k, v in kw.items():
+        if k not in names:
+            raise TypeError(f"{what} has no field {k!r}")
+        setattr(obj, k, v)
+
+
+def _same_len(*ts):
+    n = ts[0].numel()
+    if any(t.numel() != n for t in ts[1:]):
+        raise ValueError("coordinate and value vectors must have the same length")
+    return n
+
+
 def gl_opts_default(**kw) -> gl_opts:
     o = gl_opts()
     lib().gl_opts_default(ctypes.byref(o))
-    for k, v in kw.items():
-        setattr(o, k, v)
+    _set_fields(o, kw, "gl_opts")
     return o
 
 
@@ -203,9 +217,11 @@ def matern_generate(ctx: Context, x1, y1, x2, y2, theta, opts: gl_opts | None = 
     returns a torch tensor of shape (n2, n1) whose transpose is Σ12
     (out.T[i, j] = C(d(s1_i, s2_j)))."""
     import torch
-    n1, n2 = x1.numel(), x2.numel()
+    n1, n2 = _same_len(x1, y1), _same_len(x2, y2)
     if out is None:
         out = torch.empty((n2, n1), dtype=torch.float64, device=x1.device)
+    if out.numel() != n1 * n2:
+        raise ValueError("out must hold n1 * n2 values")
     _check(lib().matern_generate(ctx.handle, _ptr(x1), _ptr(y1), n1, _ptr(x2), _ptr(y2), n2, _theta(theta),
                                  ctypes.byref(opts) if opts is not None else None, _ptr(out), n1,
                                  _stream(stream)), "matern_generate")
@@ -216,6 +232,7 @@ def loglik_eval(ctx: Context, x, y, z, theta, opts: gl_opts | None = None, strea
     """Alg. 2 on the device; returns the gl_result fields as a dict."""
     res = gl_result()
     o = opts if opts is not None else gl_opts_default()
+    _same_len(x, y, z)
     st = lib().loglik_eval(ctx.handle, _ptr(x), _ptr(y), _ptr(z), x.numel(), _theta(theta), ctypes.byref(o),
                            ctypes.byref(res), _stream(stream))
     _check(st, "loglik_eval")
@@ -227,9 +244,11 @@ def krige_predict(ctx: Context, factor, xnew, ynew, out=None, return_variance: b
     """Eq. (5) predictions at the new locations; with return_variance, also
     the prediction variances of Eq. (4): returns (pred, var)."""
     import torch
-    m = xnew.numel()
+    m = _same_len(xnew, ynew)
     if out is None:
         out = torch.empty(m, dtype=torch.float64, device=xnew.device)
+    if out.numel() != m or (var is not None and var.numel() != m):
+        raise ValueError("output vectors must have one entry per new location")
     if return_variance and var is None:
         var = torch.empty(m, dtype=torch.float64, device=xnew.device)
     _check(lib().krige_predict(ctx.handle, factor, _ptr(xnew), _ptr(ynew), m, _ptr(out),
@@ -242,6 +261,8 @@ def krige_cv(ctx: Context, x, y, z, theta, folds, opts: gl_opts | None = None, s
     Returns (mse per fold as a list, status)."""
     import numpy as np
     f = np.ascontiguousarray(np.asarray(folds, dtype=np.int32))
+    if f.size != _same_len(x, y, z):
+        raise ValueError("one fold id per location")
     k = int(f.max()) + 1 if f.size else 0
     mse = (ctypes.c_double * max(k, 1))()
     st = lib().krige_cv(ctx.handle, _ptr(x), _ptr(y), _ptr(z), x.numel(), _theta(theta),
@@ -276,7 +297,7 @@ def synth_generate(ctx: Context, x, y, e, theta, tile: int = 0, opts: gl_opts | 
                    stream=None):
     """Alg. 1: returns (z, info).  opts (tile, metric, radius) overrides tile."""
     import torch
-    n = x.numel()
+    n = _same_len(x, y, e)
     if out is None:
         out = torch.empty(n, dtype=torch.float64, device=x.device)
     o = opts if opts is not None else gl_opts_default(tile=int(tile))
@@ -287,6 +308,7 @@ def synth_generate(ctx: Context, x, y, e, theta, tile: int = 0, opts: gl_opts | 
 
 
 def gl_dataset_register(ctx: Context, x, y, z) -> int:
+    _same_len(x, y, z)
     ds = _U64()
     _check(lib().gl_dataset_register(ctx.handle, _ptr(x), _ptr(y), _ptr(z), x.numel(), ctypes.byref(ds)),
            "gl_dataset_register")
@@ -300,8 +322,7 @@ def gl_dataset_release(ctx: Context, ds: int) -> None:
 def lq_config_default(**kw) -> lq_config:
     c = lq_config()
     lib().lq_config_default(ctypes.byref(c))
-    for k, v in kw.items():
-        setattr(c, k, v)
+    _set_fields(c, kw, "lq_config")
     return c
 
 

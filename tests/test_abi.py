@@ -104,3 +104,14 @@ def test_context_create_without_gpu_reports_enodev():
     with pytest.raises(g.GeolikError) as ei:
         g.Context()
     assert ei.value.status == g.GL_ENODEV
+
+
+def test_binding_rejects_unknown_option_names():
+    _ensure_built()
+    import paper_1708_02835_amd as g
+    with pytest.raises(TypeError):
+        g.gl_opts_default(tol64=0.5)
+    with pytest.raises(TypeError):
+        g.lq_config_default(max_in_flight=3)
+    o = g.gl_opts_default(tol_64=0.5, ind_tiles=2)
+    assert o.tol_64 == 0.5 and o.ind_tiles == 2
