@@ -312,8 +312,11 @@ __global__ __launch_bounds__(256, 2) void trailing_bf16_kernel(double *__restric
         for (int b = 0; b < 4; ++b) acc[a][b] = (f4){0.f, 0.f, 0.f, 0.f};
 
     // loader: 128 rows × 32 bf16 per part and operand = 512 16-byte pieces, two per thread
-    u4 ra[NP][2], rbv[NP][2];
-    auto load = [&](int k0) {
+    // two register sets (one or two parts): the chunk two steps ahead is in
+    // flight while one is computed, so global latency is covered by two chunks
+    // of products
+    u4 ra0[NP][2], rb0[NP][2], ra1[NP][2], rb1[NP][2];
+    auto load = [&](u4 (&ra)[NP][2], u4 (&rbv)[NP][2], int k0) {
 #pragma unroll
         for (int p = 0; p < NP; ++p)
 #pragma unroll
@@ -324,7 +327,7 @@ __global__ __launch_bounds__(256, 2) void trailing_bf16_kernel(double *__restric
                 rbv[p][h] = *reinterpret_cast<const u4 *>(Bp + p * plane_stride + (int64_t)row * B + k0 + part * 8);
             }
     };
-    auto store = [&]() {
+    auto store = [&](const u4 (&ra)[NP][2], const u4 (&rbv)[NP][2]) {
 #pragma unroll
         for (int p = 0; p < NP; ++p)
 #pragma unroll
@@ -335,12 +338,7 @@ __global__ __launch_bounds__(256, 2) void trailing_bf16_kernel(double *__restric
                 *reinterpret_cast<u4 *>(&Bs[p][row][part * 8]) = rbv[p][h];
             }
     };
-    load(0);
-    constexpr int NK = B / HK;
-    for (int kc = 0; kc < NK; ++kc) {
-        store();
-        __syncthreads();
-        if (kc + 1 < NK) load((kc + 1) * HK);
+    auto compute = [&]() {
         // fragments: 8 consecutive k of one row per lane
         bf16x8 af[NP][4], bfr[NP][4];
 #pragma unroll
@@ -366,7 +364,33 @@ __global__ __launch_bounds__(256, 2) void trailing_bf16_kernel(double *__restric
                     acc[a][b] = mfma_bf16(bfr[1][b], af[1][a], acc[a][b]);
                 }
             }
-        __syncthreads();
+    };
+    constexpr int NK = B / HK;  // even for every supported tile size
+    if constexpr (NP <= 2) {
+        load(ra0, rb0, 0);
+        load(ra1, rb1, HK);
+        for (int kc = 0; kc < NK; kc += 2) {
+            store(ra0, rb0);
+            __syncthreads();
+            if (kc + 2 < NK) load(ra0, rb0, (kc + 2) * HK);
+            compute();
+            __syncthreads();
+            store(ra1, rb1);
+            __syncthreads();
+            if (kc + 3 < NK) load(ra1, rb1, (kc + 3) * HK);
+            compute();
+            __syncthreads();
+        }
+    } else {
+        // three parts: one register set (a second would spill)
+        load(ra0, rb0, 0);
+        for (int kc = 0; kc < NK; ++kc) {
+            store(ra0, rb0);
+            __syncthreads();
+            if (kc + 1 < NK) load(ra0, rb0, (kc + 1) * HK);
+            compute();
+            __syncthreads();
+        }
     }
 #pragma unroll
     for (int a = 0; a < 4; ++a)
