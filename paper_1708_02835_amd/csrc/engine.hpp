@@ -18,6 +18,7 @@ struct MixedViews {
     int2 *lists = nullptr;                       // per-class tile lists (device)
     uint8_t *map = nullptr;                      // per-tile precision class (device)
     double *thr = nullptr;                       // ρ and the effective thresholds (device, 4 doubles)
+    float *delta = nullptr;                      // FP32 running sums of low-precision updates, per tile
 };
 
 // Host-side plan of one mixed evaluation: per class, the offset of its list

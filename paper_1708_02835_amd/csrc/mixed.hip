@@ -8,16 +8,19 @@
 // measured when Σ is generated:
 //   class 0  FP64    diagonal tiles, tiles with i - j < band, and tiles
 //                    with ν_ij > tol_64 (both modes);
-// Thresholds left negative in the options follow from an accuracy target
-// and the first diagonal tile's pivots (thresholds_kernel below).
 //   class 1  FP32    FP32 matrix-core products (GL_MIXED_FP32);
 //   class 2  BF16x6  operands split into three bfloat16 parts a = h + m + l,
 //                    products hh + hm + mh + hl + lh + mm: about FP32 accuracy
 //                    (GL_MIXED_BF16, ν_ij > tol_hi);
 //   class 3  BF16x3  two parts, products hh + hm + mh (tol_lo < ν_ij <= tol_hi);
 //   class 4  BF16    one part (ν_ij <= tol_lo).
+// Thresholds left negative in the options follow from an accuracy target
+// and the first diagonal tile's pivots (thresholds_kernel below).
 // Low-precision products accumulate in FP32 over the whole K = b of one tile
-// update and are then subtracted from the binary64 tile.
+// update and are subtracted from an FP32 running sum of the tile's updates
+// (half the bytes of a binary64 read-modify-write per update); the sum is
+// added to the binary64 tile once, when the tile's column becomes the panel
+// (before its TRSM).
 // The split-bfloat16 products follow Henry, Tang and Heinecke, "Leveraging the
 // bfloat16 artificial intelligence datatype for higher-precision
 // computations" (ARITH 2019).
@@ -166,7 +169,7 @@ __device__ inline void list_tile(const int2 *__restrict__ list, int64_t G, int64
 }
 
 template <int B>
-__global__ __launch_bounds__(256, 2) void trailing_f32_kernel(double *__restrict__ tiles,
+__global__ __launch_bounds__(256, 2) void trailing_f32_kernel(float *__restrict__ delta,
                                                               const float *__restrict__ p32,
                                                               const int2 *__restrict__ list,
                                                               int64_t nblocks,
@@ -185,7 +188,7 @@ __global__ __launch_bounds__(256, 2) void trailing_f32_kernel(double *__restrict
     const int rb = sub / SB, cb = sub % SB;
     const float *Ap = p32 + (int64_t)ij.x * B * B + rb * FB;
     const float *Bp = p32 + (int64_t)ij.y * B * B + cb * FB;
-    double *C = tiles + tile_offset(ij.x, ij.y, B) + (int64_t)(cb * FB) * B + rb * FB;
+    float *C = delta + tile_offset(ij.x, ij.y, B) + (int64_t)(cb * FB) * B + rb * FB;
 
     __shared__ float As[2][FK][FB];
     __shared__ float Bs[2][FK][FB];
@@ -263,7 +266,7 @@ __global__ __launch_bounds__(256, 2) void trailing_f32_kernel(double *__restrict
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int64_t col = wn * 64 + b * 16 + mfma32_row(lane, r);
-                C[col * B + row] -= (double)acc[a][b][r];
+                C[col * B + row] -= acc[a][b][r];
             }
         }
 }
@@ -274,7 +277,7 @@ constexpr int HK = 32;        // k chunk = one 16x16x32 product
 constexpr int HP = HK + 8;    // LDS row pitch in bf16 (80 bytes: conflict-free 16-byte reads)
 
 template <int B, int NP>
-__global__ __launch_bounds__(256, 2) void trailing_bf16_kernel(double *__restrict__ tiles,
+__global__ __launch_bounds__(256, 2) void trailing_bf16_kernel(float *__restrict__ delta,
                                                                const uint16_t *__restrict__ planes,
                                                                int64_t plane_stride,
                                                                const int2 *__restrict__ list,
@@ -295,7 +298,7 @@ __global__ __launch_bounds__(256, 2) void trailing_bf16_kernel(double *__restric
     // row-major parts: element (r, kk) of tile slot s at s*B*B + r*B + kk
     const uint16_t *Ap = planes + (int64_t)ij.x * B * B + (int64_t)(rb * FB) * B;
     const uint16_t *Bp = planes + (int64_t)ij.y * B * B + (int64_t)(cb * FB) * B;
-    double *C = tiles + tile_offset(ij.x, ij.y, B) + (int64_t)(cb * FB) * B + rb * FB;
+    float *C = delta + tile_offset(ij.x, ij.y, B) + (int64_t)(cb * FB) * B + rb * FB;
 
     __shared__ uint16_t As[NP][FB][HP];
     __shared__ uint16_t Bs[NP][FB][HP];
@@ -400,7 +403,7 @@ __global__ __launch_bounds__(256, 2) void trailing_bf16_kernel(double *__restric
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int64_t col = wn * 64 + b * 16 + mfma32_row(lane, r);
-                C[col * B + row] -= (double)acc[a][b][r];
+                C[col * B + row] -= acc[a][b][r];
             }
         }
 }
@@ -422,16 +425,16 @@ static void launch_class(int cls, double *tiles, int64_t k, const MixedViews &mv
         launch_trailing_list(tiles, B, k, list, count, info, critical, s);
         break;
     case C32:
-        trailing_f32_kernel<B><<<grid, 256, 0, s>>>(tiles, mv.p32[par], list, nblocks, info, crit);
+        trailing_f32_kernel<B><<<grid, 256, 0, s>>>(mv.delta, mv.p32[par], list, nblocks, info, crit);
         break;
     case CB6:
-        trailing_bf16_kernel<B, 3><<<grid, 256, 0, s>>>(tiles, mv.planes[par], mv.plane_stride, list, nblocks, info, crit);
+        trailing_bf16_kernel<B, 3><<<grid, 256, 0, s>>>(mv.delta, mv.planes[par], mv.plane_stride, list, nblocks, info, crit);
         break;
     case CB3:
-        trailing_bf16_kernel<B, 2><<<grid, 256, 0, s>>>(tiles, mv.planes[par], mv.plane_stride, list, nblocks, info, crit);
+        trailing_bf16_kernel<B, 2><<<grid, 256, 0, s>>>(mv.delta, mv.planes[par], mv.plane_stride, list, nblocks, info, crit);
         break;
     default:
-        trailing_bf16_kernel<B, 1><<<grid, 256, 0, s>>>(tiles, mv.planes[par], mv.plane_stride, list, nblocks, info, crit);
+        trailing_bf16_kernel<B, 1><<<grid, 256, 0, s>>>(mv.delta, mv.planes[par], mv.plane_stride, list, nblocks, info, crit);
         break;
     }
 }
@@ -444,6 +447,35 @@ static void launch_class_any(int b, int cls, double *tiles, int64_t k, const Mix
     case 256: launch_class<256>(cls, tiles, k, mv, list, count, info, critical, s); break;
     case 384: launch_class<384>(cls, tiles, k, mv, list, count, info, critical, s); break;
     default: launch_class<512>(cls, tiles, k, mv, list, count, info, critical, s); break;
+    }
+}
+
+// Tiles of column k in a low-precision class receive their FP32 running sum
+// of updates: A_ik += Δ_ik (binary64), before the TRSM of step k.
+template <int B>
+__global__ __launch_bounds__(256) void delta_flush_kernel(double *__restrict__ tiles, const float *__restrict__ delta,
+                                                          const uint8_t *__restrict__ map, int64_t k,
+                                                          const int64_t *__restrict__ info)
+{
+    if (*info != 0) return;
+    const int64_t i = k + 1 + blockIdx.x;
+    if (map[tile_index(i, k)] == C64) return;
+    const int64_t off = tile_offset(i, k, B);
+    constexpr int64_t CH = (int64_t)B * B / 64;  // elements per chunk (blockIdx.y of 64)
+    const int64_t e0 = off + (int64_t)blockIdx.y * CH;
+    for (int64_t e = threadIdx.x; e < CH; e += 256) tiles[e0 + e] += (double)delta[e0 + e];
+}
+
+static void launch_delta_flush(const Work &w, int64_t k, hipStream_t s)
+{
+    const int64_t m = w.nt - k - 1;
+    if (m <= 0 || k == 0) return;
+    dim3 grid((unsigned)m, 64);
+    switch (w.b) {
+    case 128: delta_flush_kernel<128><<<grid, 256, 0, s>>>(w.tiles, w.mv.delta, w.mv.map, k, w.info); break;
+    case 256: delta_flush_kernel<256><<<grid, 256, 0, s>>>(w.tiles, w.mv.delta, w.mv.map, k, w.info); break;
+    case 384: delta_flush_kernel<384><<<grid, 256, 0, s>>>(w.tiles, w.mv.delta, w.mv.map, k, w.info); break;
+    default: delta_flush_kernel<512><<<grid, 256, 0, s>>>(w.tiles, w.mv.delta, w.mv.map, k, w.info); break;
     }
 }
 
@@ -471,7 +503,7 @@ size_t mixed_extra_bytes(int64_t nt, int b, int precision)
     const size_t slot = (size_t)nt * b * b;
     size_t panel = (precision == GL_MIXED_FP32) ? 2 * slot * sizeof(float) : 2 * 3 * slot * sizeof(uint16_t);
     const size_t tc = (size_t)tile_count(nt);
-    return panel + tc * sizeof(int2) + ((tc + 255) / 256) * 256 + 1024;
+    return tc * b * b * sizeof(float) + panel + tc * sizeof(int2) + ((tc + 255) / 256) * 256 + 1024;
 }
 
 void mixed_views(Work &w)
@@ -481,6 +513,8 @@ void mixed_views(Work &w)
     if (w.precision == GL_FP64 || !w.mix) return;
     const size_t slot = (size_t)w.nt * w.b * w.b;
     char *p = static_cast<char *>(w.mix);
+    mv.delta = reinterpret_cast<float *>(p);  // one FP32 b×b block per tile, packed like the tiles
+    p += (size_t)tile_count(w.nt) * w.b * w.b * sizeof(float);
     if (w.precision == GL_MIXED_FP32) {
         mv.p32[0] = reinterpret_cast<float *>(p);
         mv.p32[1] = mv.p32[0] + slot;
@@ -552,6 +586,7 @@ static void class_updates(Work &w, int64_t k, int64_t j0, int64_t j1, const Mixe
 int mixed_factorize(Lanes &ln, Work &w, gl_theta th, const gl_opts &o, hipStream_t s, MixedPlan *plan_out)
 {
     launch_gen_tiles(w.tiles, w.x, w.y, w.n, w.b, w.nt, th, geom_of(o), w.norm2, s);
+    launch_fill(reinterpret_cast<double *>(w.mv.delta), tile_count(w.nt) * w.b * w.b / 2, 0.0, s);
     // step 0's POTRF first: its pivots set the adaptive thresholds
     launch_potrf(w.tiles, w.b, 0, w.n, w.info, w.logsum, w.dinv_k(0), s);
     thresholds_kernel<<<1, 256, 0, s>>>(w.tiles, w.b, w.n, th.theta1, o.accuracy, o.tol_64, o.tol_hi, o.tol_lo,
@@ -566,6 +601,7 @@ int mixed_factorize(Lanes &ln, Work &w, gl_theta th, const gl_opts &o, hipStream
     for (int64_t k = 0; k < w.nt; ++k) {
         if (k > 0) launch_potrf(w.tiles, w.b, k, w.n, w.info, w.logsum, w.dinv_k(k), s);
         launch_fwd_diag(w.tiles, w.b, k, w.n, w.v, w.quad, w.dinv_k(k), w.info, s);
+        launch_delta_flush(w, k, s);
         launch_trsm(w.tiles, w.b, w.nt, k, w.dinv_k(k), w.info, s);
         launch_fwd_update(w.tiles, w.b, w.nt, k, w.v, w.info, s);
         if (k + 1 < w.nt) {

@@ -80,10 +80,11 @@ def test_footprint_formula(n, tile):
         p2 *= 2
     vec = (3 * nt * tile + 2 * nt + nt * (nt + 1) // 2 + 64 * nt * tile + 16 + p2 + 4) * 8
     assert g.gl_footprint_bytes(n, tile, g.GL_FP64) == tiles + vec
-    # mixed modes add the double-buffered panel copies, the tile lists and the map
+    # mixed modes add the FP32 running sums (one b×b block per tile), the
+    # double-buffered panel copies, the tile lists and the map
     tc = nt * (nt + 1) // 2
-    extra32 = 2 * nt * tile * tile * 4 + tc * 8 + ((tc + 255) // 256) * 256 + 1024
-    extra16 = 2 * 3 * nt * tile * tile * 2 + tc * 8 + ((tc + 255) // 256) * 256 + 1024
+    extra32 = tc * tile * tile * 4 + 2 * nt * tile * tile * 4 + tc * 8 + ((tc + 255) // 256) * 256 + 1024
+    extra16 = tc * tile * tile * 4 + 2 * 3 * nt * tile * tile * 2 + tc * 8 + ((tc + 255) // 256) * 256 + 1024
     assert g.gl_footprint_bytes(n, tile, g.GL_MIXED_FP32) == tiles + vec + extra32
     assert g.gl_footprint_bytes(n, tile, g.GL_MIXED_BF16) == tiles + vec + extra16
 
