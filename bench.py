@@ -147,8 +147,8 @@ def mixed_legs(g, ctx, xd, yd, ed, zd, theta, theta_b, args, res64, t64, log):
         else:
             r64, t64b = res64, t64
         leg = {"theta": list(th), "fp64_ms": t64b * 1e3, "loglik_fp64": r64["loglik"]}
-        for name, prec in (("bf16", g.GL_MIXED_BF16), ("fp32", g.GL_MIXED_FP32)):
-            r, dt, stats = run(z, th, prec, steps if name == "bf16" else 1)
+        for name, prec in (("fp16", g.GL_MIXED_FP16), ("bf16", g.GL_MIXED_BF16), ("fp32", g.GL_MIXED_FP32)):
+            r, dt, stats = run(z, th, prec, steps if name != "fp32" else 1)
             leg[name] = {"ms": dt * 1e3, "speedup_vs_fp64": t64b / dt,
                          "rel_err_loglik": abs(r["loglik"] - r64["loglik"]) / abs(r64["loglik"]),
                          "rel_err_logdet": abs(r["logdet"] - r64["logdet"]) / abs(r64["logdet"]),
@@ -211,7 +211,7 @@ def graph_leg(g, ctx, args, log):
 
 
 def mle_leg(g, ctx, args, log):
-    """θ̂ from FP64 and from the BF16 mixed mode: Nelder-Mead over log θ,
+    """θ̂ from FP64 and from the BF16 and FP16 mixed modes: Nelder-Mead over log θ,
     restarted from its own result until it stops improving (a derivative-free
     stand-in for the paper's BOBYQA), same field and start."""
     import numpy as np
@@ -228,7 +228,7 @@ def mle_leg(g, ctx, args, log):
         return {"error": f"field generation failed, info={info}"}
     start = np.log([0.7 * truth[0], 1.4 * truth[1], 0.8 * truth[2]])
     out = {"n": n, "theta_true": list(truth), "optimizer": "Nelder-Mead on log theta with restarts, same start"}
-    for name, prec in (("fp64", g.GL_FP64), ("bf16", g.GL_MIXED_BF16)):
+    for name, prec in (("fp64", g.GL_FP64), ("bf16", g.GL_MIXED_BF16), ("fp16", g.GL_MIXED_FP16)):
         opts = g.gl_opts_default(precision=prec)
 
         def negl(v):
@@ -248,8 +248,9 @@ def mle_leg(g, ctx, args, log):
         out[name] = {"theta_hat": [float(v) for v in np.exp(res.x)], "loglik": -float(res.fun),
                      "evals": int(res.nfev), "seconds": dt}
         log(f"mle {name}: theta_hat={np.exp(res.x)} in {res.nfev} evals, {dt:.1f} s")
-    a, b = np.array(out["fp64"]["theta_hat"]), np.array(out["bf16"]["theta_hat"])
-    out["max_rel_diff_theta_hat"] = float(np.max(np.abs(b - a) / a))
+    a = np.array(out["fp64"]["theta_hat"])
+    out["max_rel_diff_theta_hat"] = {m: float(np.max(np.abs(np.array(out[m]["theta_hat"]) - a) / a))
+                                     for m in ("bf16", "fp16")}
     return out
 
 

@@ -53,8 +53,12 @@ typedef enum {
 typedef enum {
     GL_FP64 = 0,        /* every tile and every update in binary64 */
     GL_MIXED_FP32 = 1,  /* off-band trailing updates in binary32 on MFMA */
-    GL_MIXED_BF16 = 2   /* far off-band updates in bfloat16 (fp32 accumulate), others as MIXED_FP32 */
+    GL_MIXED_BF16 = 2,  /* off-band updates as split-bfloat16 products, fp32 accumulate */
+    GL_MIXED_FP16 = 3   /* off-band updates as scaled split-binary16 products, fp32 accumulate */
 } gl_precision;
+
+/* Precision classes of the tiles in the mixed modes (gl_precision_stats). */
+enum { GL_NCLASS = 7 };
 
 /* Options of one likelihood evaluation.  Fill with gl_opts_default().
  *
@@ -67,15 +71,22 @@ typedef enum {
  *   GL_MIXED_FP32: FP32 products otherwise;
  *   GL_MIXED_BF16: bfloat16 products with FP32 accumulation, operands split
  *                  in three parts (about FP32 accuracy) when ν_ij > tol_hi,
- *                  two parts when tol_lo < ν_ij <= tol_hi, one part below.
+ *                  two parts when tol_lo < ν_ij <= tol_hi, one part below;
+ *   GL_MIXED_FP16: binary16 products with FP32 accumulation of operands
+ *                  scaled by a power of two (|L_ik| <= sqrt(max(θ1, 1)) maps
+ *                  below 2^14), split in two parts (products hh + hl + lh,
+ *                  about 22 bits) when ν_ij > tol_lo, one part below; tol_hi
+ *                  is not used.
  * Thresholds left negative (the default) are adaptive: with the accuracy
  * target ε (default 1e-4) and ρ = min_r L_rr² / θ1 over the first diagonal
  * tile (its binary64 POTRF runs before any off-band update; ρ is the smallest
  * conditional variance ratio of those locations, small when neighbours
  * explain most of a value and the Schur complements cancel), a class with
  * unit roundoff u is used for tile (i, j) only while ν_ij u <= ε ρ:
- * tol_64 = ε ρ / 2⁻²⁴, tol_hi = ε ρ / 2⁻¹⁶, tol_lo = ε ρ / 2⁻⁸.
- * Tiles with i - j < band stay binary64.
+ * tol_64 = ε ρ / 2⁻²⁴, tol_hi = ε ρ / 2⁻¹⁶, tol_lo = ε ρ / 2⁻⁸ (FP32 and
+ * BF16 modes); tol_64 = ε ρ / 2⁻²², tol_lo = ε ρ / 2⁻¹¹ (FP16 mode).
+ * Tiles with i - j < band stay binary64.  The mixed modes keep FP32 running
+ * sums of the updates, so they require θ1 <= 1e30 (GL_EINVAL otherwise).
  *
  * Distance (Sec. 2 and Sec. 7.4): metric GL_EUCLIDEAN uses r = ||s_i - s_j||
  * in the plane; GL_GREAT_CIRCLE reads x as longitude and y as latitude in
@@ -93,7 +104,7 @@ typedef struct {
                             on the order; kept factors are in the order used. */
     int32_t metric;      /* GL_EUCLIDEAN (default) or GL_GREAT_CIRCLE */
     double tol_hi;       /* GL_MIXED_BF16: see above (negative: adaptive) */
-    double tol_lo;       /* GL_MIXED_BF16: see above (negative: adaptive) */
+    double tol_lo;       /* GL_MIXED_BF16 and GL_MIXED_FP16: see above (negative: adaptive) */
     double radius;       /* GL_GREAT_CIRCLE: sphere radius (> 0; default 6371, the Earth in km) */
     double tol_64;       /* mixed modes: see above (negative: adaptive) */
     double accuracy;     /* mixed modes: ε of the adaptive thresholds (negative: 1e-4) */
@@ -293,14 +304,16 @@ int gl_morton_order(gl_context *ctx, const double *x, const double *y, int64_t n
 
 /* Precision map of the last mixed-precision loglik_eval on this context:
  * tiles per class and work per class (Σ over tiles of the trailing updates
- * they receive), classes 0 FP64, 1 FP32, 2 BF16x6, 3 BF16x3, 4 BF16 (5 values
- * each), and thresholds_h = {ρ, tol_64, tol_hi, tol_lo} as used (4 values).
+ * they receive), classes 0 FP64, 1 FP32, 2 BF16x6, 3 BF16x3, 4 BF16,
+ * 5 FP16x3 (two parts), 6 FP16 (GL_NCLASS = 7 values each), and
+ * thresholds_h = {ρ, tol_64, tol_hi, tol_lo} as used (4 values).
  * Any pointer may be NULL. */
 int gl_precision_stats(gl_context *ctx, int64_t *tiles_h, double *work_h, double *thresholds_h);
 
 /* Runs a built-in device self-check `which` and writes up to `cap` doubles of
  * output to out_h: 0 = the lane layout of the FP64 16x16x4 matrix-core
- * product (256 values), 1 = the same for FP32 16x16x4, 2 = BF16 16x16x32. */
+ * product (256 values), 1 = the same for FP32 16x16x4, 2 = BF16 16x16x32,
+ * 3 = FP16 16x16x32. */
 int gl_selftest(gl_context *ctx, int32_t which, double *out_h, int64_t cap);
 
 /* Kernel timing of the trailing-update launches (the dominant kernel family).

@@ -25,6 +25,7 @@ GL_ENODEV = -7
 GL_FP64 = 0
 GL_MIXED_FP32 = 1
 GL_MIXED_BF16 = 2
+GL_MIXED_FP16 = 3
 
 GL_EUCLIDEAN = 0
 GL_GREAT_CIRCLE = 1
@@ -410,13 +411,13 @@ def gl_morton_order(ctx: Context, x, y, stream=None):
     return perm
 
 
-PRECISION_CLASSES = ("fp64", "fp32", "bf16x6", "bf16x3", "bf16")
+PRECISION_CLASSES = ("fp64", "fp32", "bf16x6", "bf16x3", "bf16", "fp16x3", "fp16")
 
 
 def gl_precision_stats(ctx: Context) -> dict:
     """Tiles and trailing-update work per precision class of the last mixed evaluation."""
-    tiles = (_I64 * 5)()
-    work = (_D * 5)()
+    tiles = (_I64 * len(PRECISION_CLASSES))()
+    work = (_D * len(PRECISION_CLASSES))()
     thr = (_D * 4)()
     _check(lib().gl_precision_stats(ctx.handle, tiles, work, thr), "gl_precision_stats")
     tot = sum(work) or 1.0

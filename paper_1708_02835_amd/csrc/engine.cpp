@@ -38,6 +38,12 @@ bool valid_theta(const gl_theta &t)
            isfinite(t.theta1) && isfinite(t.theta2);
 }
 
+// The mixed modes keep FP32 running sums of updates whose size is of order θ1.
+bool valid_theta_for(const gl_theta &t, const gl_opts &o)
+{
+    return valid_theta(t) && (o.precision == GL_FP64 || t.theta1 <= 1e30);
+}
+
 // Sizes of the three device allocations of a workspace.
 static void work_sizes(int64_t n, int b, int precision, size_t &tiles, size_t &vec, size_t &mix)
 {
@@ -351,7 +357,7 @@ bool valid_opts(const gl_opts &o)
     if (!valid_metric(o)) return false;
     if (o.ind_tiles < 0 || (o.ind_tiles > 0 && (o.precision != GL_FP64 || o.keep_factor))) return false;
     if (o.graph < 0 || o.graph > 1) return false;
-    if (o.precision < GL_FP64 || o.precision > GL_MIXED_BF16) return false;
+    if (o.precision < GL_FP64 || o.precision > GL_MIXED_FP16) return false;
     if (o.tile != 0 && o.tile != 128 && o.tile != 256 && o.tile != 384 && o.tile != 512) return false;
     if (o.reorder < -1 || o.reorder > 1) return false;
     if (o.precision != GL_FP64 && o.band < 1) return false;
@@ -471,7 +477,7 @@ int loglik_eval(gl_context *ctx, const double *x, const double *y, const double 
     gl_opts o;
     gl_opts_default(&o);
     if (opts) o = *opts;
-    if (!ctx || !x || !y || !z || n < 1 || !valid_theta(th) || !valid_opts(o)) {
+    if (!ctx || !x || !y || !z || n < 1 || !valid_opts(o) || !valid_theta_for(th, o)) {
         res->status = GL_EINVAL;
         return GL_EINVAL;
     }
@@ -615,7 +621,7 @@ int krige_cv(gl_context *ctx, const double *x, const double *y, const double *z,
     gl_opts_default(&o);
     if (opts) o = *opts;
     o.keep_factor = 1;
-    if (!valid_opts(o)) return GL_EINVAL;
+    if (!valid_opts(o) || !valid_theta_for(th, o)) return GL_EINVAL;
     std::vector<int64_t> count(k, 0);
     for (int64_t i = 0; i < n; ++i) {
         if (fold_h[i] < 0 || fold_h[i] >= k) return GL_EINVAL;
@@ -751,7 +757,7 @@ int gl_morton_order(gl_context *ctx, const double *x, const double *y, int64_t n
 int gl_precision_stats(gl_context *ctx, int64_t *tiles_h, double *work_h, double *thresholds_h)
 {
     if (!ctx) return GL_EINVAL;
-    for (int c = 0; c < 5; ++c) {
+    for (int c = 0; c < GL_NCLASS; ++c) {
         if (tiles_h) tiles_h[c] = ctx->last_plan.tiles[c];
         if (work_h) work_h[c] = ctx->last_plan.work[c];
     }
@@ -762,7 +768,7 @@ int gl_precision_stats(gl_context *ctx, int64_t *tiles_h, double *work_h, double
 
 int gl_selftest(gl_context *ctx, int32_t which, double *out_h, int64_t cap)
 {
-    if (!ctx || !out_h || cap < 256 || which < 0 || which > 2) return GL_EINVAL;
+    if (!ctx || !out_h || cap < 256 || which < 0 || which > 3) return GL_EINVAL;
     GL_HIP_TRY(hipSetDevice(ctx->device));
     return selftest_mfma(which, out_h, cap);
 }

@@ -12,22 +12,24 @@ namespace gl {
 // Views into the mixed-precision side buffer of a workspace.
 struct MixedViews {
     float *p32[2] = {nullptr, nullptr};          // FP32 panel copies, by parity of k
-    uint16_t *planes[2] = {nullptr, nullptr};    // bfloat16 parts (3 planes each), by parity of k
+    uint16_t *planes[2] = {nullptr, nullptr};    // bfloat16 (3) or binary16 (2) part planes, by parity of k
     int64_t plane_stride = 0;                    // elements between the parts of one parity
     int np = 0;                                  // parts written per panel element
     int2 *lists = nullptr;                       // per-class tile lists (device)
     uint8_t *map = nullptr;                      // per-tile precision class (device)
     double *thr = nullptr;                       // ρ and the effective thresholds (device, 4 doubles)
     float *delta = nullptr;                      // FP32 running sums of low-precision updates, per tile
+    double f16_scale = 0.0;                      // FP16 mode: power of two applied to the panel parts
+    float f16_unscale = 1.0f;                    // 1 / f16_scale², applied to the products
 };
 
 // Host-side plan of one mixed evaluation: per class, the offset of its list
 // and, per tile column j, the list position where column j starts.
 struct MixedPlan {
-    int64_t base[5] = {0, 0, 0, 0, 0};
-    int64_t tiles[5] = {0, 0, 0, 0, 0};
-    double work[5] = {0, 0, 0, 0, 0};  // Σ over tiles of the number of trailing updates they receive
-    double thr[4] = {0, 0, 0, 0};      // ρ, tol_64, tol_hi, tol_lo as used
+    int64_t base[GL_NCLASS] = {};
+    int64_t tiles[GL_NCLASS] = {};
+    double work[GL_NCLASS] = {};   // Σ over tiles of the number of trailing updates they receive
+    double thr[4] = {0, 0, 0, 0};  // ρ, tol_64, tol_hi, tol_lo as used
     std::vector<std::vector<int64_t>> start;
 };
 
@@ -80,6 +82,7 @@ struct Lanes {
 
 int pick_tile(int64_t n, int32_t requested);
 bool valid_theta(const gl_theta &t);
+bool valid_theta_for(const gl_theta &t, const gl_opts &o);
 size_t work_bytes(int64_t n, int b, int precision);
 int factorize(Lanes &ln, Work &w, hipStream_t s, bool solve);
 // Enqueue a whole evaluation on s (inputs already in w.x, w.y, w.v) and the

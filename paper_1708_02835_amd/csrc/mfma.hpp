@@ -6,8 +6,9 @@
 // The FP32 16x16x4 form takes operands the same way but returns
 // D[4 (l / 16) + r][l % 16]; the BF16 16x16x32 form gives each lane 8
 // consecutive k values, A[l % 16][8 (l / 16) + 0..7] and
-// B[8 (l / 16) + 0..7][l % 16], with the FP32 result layout.  These layouts
-// are checked on the device by gl_selftest.
+// B[8 (l / 16) + 0..7][l % 16], with the FP32 result layout; the FP16
+// 16x16x32 form takes the same layout.  These layouts are checked on the
+// device by gl_selftest.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -18,6 +19,7 @@ typedef double d4 __attribute__((ext_vector_type(4)));
 typedef double d2 __attribute__((ext_vector_type(2)));  // 16-byte vector loads and stores
 typedef float f4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
 
 // result coordinates of element r of lane `lane`
 __device__ inline int mfma_row(int lane, int r) { return (lane >> 4) + 4 * r; }  // FP64 form
@@ -37,6 +39,11 @@ __device__ inline f4 mfma_f32(float a, float b, f4 c)
 __device__ inline f4 mfma_bf16(bf16x8 a, bf16x8 b, f4 c)
 {
     return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
+__device__ inline f4 mfma_f16(f16x8 a, f16x8 b, f4 c)
+{
+    return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
 }
 
 // Value of v in lane l (l uniform across the wave), as two 32-bit readlanes.

@@ -13,7 +13,17 @@
 //                    products hh + hm + mh + hl + lh + mm: about FP32 accuracy
 //                    (GL_MIXED_BF16, ν_ij > tol_hi);
 //   class 3  BF16x3  two parts, products hh + hm + mh (tol_lo < ν_ij <= tol_hi);
-//   class 4  BF16    one part (ν_ij <= tol_lo).
+//   class 4  BF16    one part (ν_ij <= tol_lo);
+//   class 5  FP16x3  (GL_MIXED_FP16) operands scaled by s = 2^e so that
+//                    |L_ik| <= sqrt(max(θ1, 1)) maps below 2^14, split in two
+//                    binary16 parts a = h + l, products hh + hl + lh (about 22
+//                    bits; ν_ij > tol_lo), the FP32 result times s⁻²;
+//   class 6  FP16    one scaled binary16 part (ν_ij <= tol_lo).
+// Binary16 carries 11 bits against bfloat16's 8, so with the scale keeping
+// every panel value inside its range, two parts and three products reach the
+// accuracy for which bfloat16 needs three parts and six products.  Values far
+// below the scale lose relative precision (subnormal low parts), but only at
+// an absolute level of 2^-39 sqrt(max(θ1, 1)).
 // Thresholds left negative in the options follow from an accuracy target
 // and the first diagonal tile's pivots (thresholds_kernel below).
 // Low-precision products accumulate in FP32 over the whole K = b of one tile
@@ -30,6 +40,8 @@
 // row-major (k contiguous, the operand layout of the BF16 matrix-core
 // product).  Copies are double-buffered by the parity of k, so the bulk
 // update of step k can still read them while step k+1 writes its own.
+#include <algorithm>
+#include <cmath>
 #include <vector>
 
 #include "engine.hpp"
@@ -37,7 +49,8 @@
 
 namespace gl {
 
-enum { C64 = 0, C32 = 1, CB6 = 2, CB3 = 3, CB1 = 4, NCLASS = 5 };
+enum { C64 = 0, C32 = 1, CB6 = 2, CB3 = 3, CB1 = 4, CH2 = 5, CH1 = 6, NCLASS = GL_NCLASS };
+static_assert(NCLASS == 7, "class count");
 
 // ------------------------------------------------------------ precision map --
 
@@ -48,11 +61,13 @@ enum { C64 = 0, C32 = 1, CB6 = 2, CB3 = 3, CB1 = 4, NCLASS = 5 };
 // every adaptive threshold zero, so every tile stays binary64.  Then the
 // effective thresholds: a negative option is replaced by ε ρ / u for the
 // class it bounds (u = 2⁻²⁴ for FP32 and the three-part split, 2⁻¹⁶ for two
-// parts, 2⁻⁸ for one part), i.e. a class is used for tile (i, j) only while
-// ν_ij u <= ε ρ.  thr = {ρ, tol_64, tol_hi, tol_lo}.
+// bfloat16 parts, 2⁻⁸ for one; 2⁻²² for two binary16 parts, 2⁻¹¹ for one),
+// i.e. a class is used for tile (i, j) only while ν_ij u <= ε ρ.
+// thr = {ρ, tol_64, tol_hi, tol_lo}; the FP16 mode has no tol_hi class and
+// reports tol_64 there.
 __global__ __launch_bounds__(256) void thresholds_kernel(const double *__restrict__ tile0, int b, int64_t n,
-                                                         double theta1, double eps, double tol_64, double tol_hi,
-                                                         double tol_lo, double *__restrict__ thr)
+                                                         double theta1, int mode, double eps, double tol_64,
+                                                         double tol_hi, double tol_lo, double *__restrict__ thr)
 {
     const int m = (int)(n < b ? n : b);
     double lo = INFINITY;
@@ -69,9 +84,15 @@ __global__ __launch_bounds__(256) void thresholds_kernel(const double *__restric
         if (!(rho > 0.0) || !(rho <= 1.0)) rho = 0.0;
         const double er = eps * rho;
         thr[0] = rho;
-        thr[1] = tol_64 >= 0.0 ? tol_64 : er * 16777216.0;  // / 2^-24
-        thr[2] = tol_hi >= 0.0 ? tol_hi : er * 65536.0;     // / 2^-16
-        thr[3] = tol_lo >= 0.0 ? tol_lo : er * 256.0;       // / 2^-8
+        if (mode == GL_MIXED_FP16) {
+            thr[1] = tol_64 >= 0.0 ? tol_64 : er * 4194304.0;  // / 2^-22
+            thr[2] = thr[1];
+            thr[3] = tol_lo >= 0.0 ? tol_lo : er * 2048.0;     // / 2^-11
+        } else {
+            thr[1] = tol_64 >= 0.0 ? tol_64 : er * 16777216.0;  // / 2^-24
+            thr[2] = tol_hi >= 0.0 ? tol_hi : er * 65536.0;     // / 2^-16
+            thr[3] = tol_lo >= 0.0 ? tol_lo : er * 256.0;       // / 2^-8
+        }
     }
 }
 
@@ -95,6 +116,7 @@ __global__ void classify_kernel(const double *__restrict__ norm2, int64_t nt, in
         const double v = nij / sqrt(nii * njj);
         if (!(v <= tol_64)) c = C64;
         else if (mode == GL_MIXED_FP32) c = C32;
+        else if (mode == GL_MIXED_FP16) c = (v > tol_lo) ? CH2 : CH1;
         else c = (v > tol_hi) ? CB6 : (v > tol_lo) ? CB3 : CB1;
     }
     map[t] = c;
@@ -110,14 +132,23 @@ __device__ inline uint16_t bf16_bits(float f)
 }
 __device__ inline float bf16_value(uint16_t h) { return __uint_as_float(((uint32_t)h) << 16); }
 
+__device__ inline uint16_t f16_bits(_Float16 h)
+{
+    uint16_t u;
+    __builtin_memcpy(&u, &h, sizeof(u));
+    return u;
+}
+
 // Panel copies of step k.  Workgroup (tile i, 64×64 block): reads the binary64
-// block of L_ik and writes the FP32 copy (column-major) or np bfloat16 parts
-// (row-major, via an LDS transpose).
+// block of L_ik and writes the FP32 copy (column-major), or np parts (row-major,
+// via an LDS transpose): bfloat16 parts when f16s = 0, else the two binary16
+// parts of s L_ik, s = f16s (a power of two, so the scaling is exact; the
+// residual of the first part is exact in FP32).
 template <int B>
 __global__ __launch_bounds__(256) void panel_convert_kernel(const double *__restrict__ tiles, int64_t k,
                                                             float *__restrict__ p32,
                                                             uint16_t *__restrict__ planes,
-                                                            int64_t plane_stride, int np,
+                                                            int64_t plane_stride, int np, float f16s,
                                                             const int64_t *__restrict__ info)
 {
     if (*info != 0) return;
@@ -144,6 +175,13 @@ __global__ __launch_bounds__(256) void panel_convert_kernel(const double *__rest
             const int r = e >> 6, c = e & 63;  // write row-major: consecutive threads, consecutive c
             const int64_t off = i * (int64_t)B * B + (int64_t)(bi * 64 + r) * B + bj * 64 + c;
             float v = T[r][c];
+            if (f16s > 0.0f) {
+                v *= f16s;
+                const _Float16 h = (_Float16)v;
+                planes[off] = f16_bits(h);
+                planes[plane_stride + off] = f16_bits((_Float16)(v - (float)h));
+                continue;
+            }
             for (int p = 0; p < np; ++p) {
                 const uint16_t h = bf16_bits(v);
                 planes[p * plane_stride + off] = h;
@@ -276,14 +314,14 @@ __global__ __launch_bounds__(256, 2) void trailing_f32_kernel(float *__restrict_
 constexpr int HK = 32;        // k chunk = one 16x16x32 product
 constexpr int HP = HK + 8;    // LDS row pitch in bf16 (80 bytes: conflict-free 16-byte reads)
 
-template <int B, int NP>
+template <int B, int NP, bool F16>
 __global__ __launch_bounds__(256, 2) void trailing_bf16_kernel(float *__restrict__ delta,
                                                                const uint16_t *__restrict__ planes,
                                                                int64_t plane_stride,
                                                                const int2 *__restrict__ list,
                                                                int64_t nblocks,
                                                                const int64_t *__restrict__ info,
-                                                               int critical)
+                                                               int critical, float unscale)
 {
     if (*info != 0) return;
     if (critical) __builtin_amdgcn_s_setprio(3);
@@ -308,11 +346,27 @@ __global__ __launch_bounds__(256, 2) void trailing_bf16_kernel(float *__restrict
     const int wm = wave >> 1, wn = wave & 1;
     typedef uint32_t u4 __attribute__((ext_vector_type(4)));
 
+    // One part: little arithmetic per byte, so the running sum is read before
+    // the k loop (overlapping the first operand loads) and the accumulators
+    // start from it (times s² in the binary16 class: exact); the sum then
+    // takes one FP32 rounding per product step, far below these classes' own
+    // 2^-8 / 2^-11 grade.  Two or three parts: the products are summed from
+    // zero and subtracted once, one rounding per update.
+    const float upscale = F16 ? 1.0f / unscale : 1.0f;
     f4 acc[4][4];
 #pragma unroll
     for (int a = 0; a < 4; ++a)
 #pragma unroll
-        for (int b = 0; b < 4; ++b) acc[a][b] = (f4){0.f, 0.f, 0.f, 0.f};
+        for (int b = 0; b < 4; ++b) {
+            if constexpr (NP == 1) {
+                const int row = wm * 64 + a * 16 + mfma_col(lane);
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    acc[a][b][r] = -C[(int64_t)(wn * 64 + b * 16 + mfma32_row(lane, r)) * B + row] * upscale;
+            } else {
+                acc[a][b] = (f4){0.f, 0.f, 0.f, 0.f};
+            }
+        }
 
     // loader: 128 rows × 32 bf16 per part and operand = 512 16-byte pieces, two per thread
     // two register sets (one or two parts): the chunk two steps ahead is in
@@ -341,6 +395,11 @@ __global__ __launch_bounds__(256, 2) void trailing_bf16_kernel(float *__restrict
                 *reinterpret_cast<u4 *>(&Bs[p][row][part * 8]) = rbv[p][h];
             }
     };
+    // the same bits feed the bfloat16 or the binary16 matrix-core product
+    auto mm = [](const bf16x8 &x, const bf16x8 &y, f4 c) {
+        if constexpr (F16) return mfma_f16(__builtin_bit_cast(f16x8, x), __builtin_bit_cast(f16x8, y), c);
+        else return mfma_bf16(x, y, c);
+    };
     auto compute = [&]() {
         // fragments: 8 consecutive k of one row per lane
         bf16x8 af[NP][4], bfr[NP][4];
@@ -356,15 +415,15 @@ __global__ __launch_bounds__(256, 2) void trailing_bf16_kernel(float *__restrict
 #pragma unroll
             for (int b = 0; b < 4; ++b) {
                 // operands swapped (B-part first): result row = C column, lane % 16 = C row
-                acc[a][b] = mfma_bf16(bfr[0][b], af[0][a], acc[a][b]);
+                acc[a][b] = mm(bfr[0][b], af[0][a], acc[a][b]);
                 if (NP >= 2) {
-                    acc[a][b] = mfma_bf16(bfr[1][b], af[0][a], acc[a][b]);
-                    acc[a][b] = mfma_bf16(bfr[0][b], af[1][a], acc[a][b]);
+                    acc[a][b] = mm(bfr[1][b], af[0][a], acc[a][b]);
+                    acc[a][b] = mm(bfr[0][b], af[1][a], acc[a][b]);
                 }
                 if (NP >= 3) {
-                    acc[a][b] = mfma_bf16(bfr[2][b], af[0][a], acc[a][b]);
-                    acc[a][b] = mfma_bf16(bfr[0][b], af[2][a], acc[a][b]);
-                    acc[a][b] = mfma_bf16(bfr[1][b], af[1][a], acc[a][b]);
+                    acc[a][b] = mm(bfr[2][b], af[0][a], acc[a][b]);
+                    acc[a][b] = mm(bfr[0][b], af[2][a], acc[a][b]);
+                    acc[a][b] = mm(bfr[1][b], af[1][a], acc[a][b]);
                 }
             }
     };
@@ -403,7 +462,9 @@ __global__ __launch_bounds__(256, 2) void trailing_bf16_kernel(float *__restrict
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int64_t col = wn * 64 + b * 16 + mfma32_row(lane, r);
-                C[col * B + row] -= acc[a][b][r];
+                const float v = F16 ? acc[a][b][r] * unscale : acc[a][b][r];  // exact: a power of two
+                if constexpr (NP == 1) C[col * B + row] = -v;
+                else C[col * B + row] -= v;
             }
         }
 }
@@ -428,13 +489,24 @@ static void launch_class(int cls, double *tiles, int64_t k, const MixedViews &mv
         trailing_f32_kernel<B><<<grid, 256, 0, s>>>(mv.delta, mv.p32[par], list, nblocks, info, crit);
         break;
     case CB6:
-        trailing_bf16_kernel<B, 3><<<grid, 256, 0, s>>>(mv.delta, mv.planes[par], mv.plane_stride, list, nblocks, info, crit);
+        trailing_bf16_kernel<B, 3, false><<<grid, 256, 0, s>>>(mv.delta, mv.planes[par], mv.plane_stride, list,
+                                                                 nblocks, info, crit, 1.0f);
         break;
     case CB3:
-        trailing_bf16_kernel<B, 2><<<grid, 256, 0, s>>>(mv.delta, mv.planes[par], mv.plane_stride, list, nblocks, info, crit);
+        trailing_bf16_kernel<B, 2, false><<<grid, 256, 0, s>>>(mv.delta, mv.planes[par], mv.plane_stride, list,
+                                                                 nblocks, info, crit, 1.0f);
+        break;
+    case CB1:
+        trailing_bf16_kernel<B, 1, false><<<grid, 256, 0, s>>>(mv.delta, mv.planes[par], mv.plane_stride, list,
+                                                                 nblocks, info, crit, 1.0f);
+        break;
+    case CH2:
+        trailing_bf16_kernel<B, 2, true><<<grid, 256, 0, s>>>(mv.delta, mv.planes[par], mv.plane_stride, list,
+                                                                nblocks, info, crit, mv.f16_unscale);
         break;
     default:
-        trailing_bf16_kernel<B, 1><<<grid, 256, 0, s>>>(mv.delta, mv.planes[par], mv.plane_stride, list, nblocks, info, crit);
+        trailing_bf16_kernel<B, 1, true><<<grid, 256, 0, s>>>(mv.delta, mv.planes[par], mv.plane_stride, list,
+                                                                nblocks, info, crit, mv.f16_unscale);
         break;
     }
 }
@@ -487,21 +559,24 @@ static void launch_panel_convert(const Work &w, int64_t k, const MixedViews &mv,
     dim3 grid((unsigned)m, (unsigned)((w.b / 64) * (w.b / 64)));
     float *p32 = mv.p32[par];
     uint16_t *pl = mv.planes[par];
+    const float f16s = (float)mv.f16_scale;
     switch (w.b) {
-    case 128: panel_convert_kernel<128><<<grid, 256, 0, s>>>(w.tiles, k, p32, pl, mv.plane_stride, mv.np, w.info); break;
-    case 256: panel_convert_kernel<256><<<grid, 256, 0, s>>>(w.tiles, k, p32, pl, mv.plane_stride, mv.np, w.info); break;
-    case 384: panel_convert_kernel<384><<<grid, 256, 0, s>>>(w.tiles, k, p32, pl, mv.plane_stride, mv.np, w.info); break;
-    default: panel_convert_kernel<512><<<grid, 256, 0, s>>>(w.tiles, k, p32, pl, mv.plane_stride, mv.np, w.info); break;
+    case 128: panel_convert_kernel<128><<<grid, 256, 0, s>>>(w.tiles, k, p32, pl, mv.plane_stride, mv.np, f16s, w.info); break;
+    case 256: panel_convert_kernel<256><<<grid, 256, 0, s>>>(w.tiles, k, p32, pl, mv.plane_stride, mv.np, f16s, w.info); break;
+    case 384: panel_convert_kernel<384><<<grid, 256, 0, s>>>(w.tiles, k, p32, pl, mv.plane_stride, mv.np, f16s, w.info); break;
+    default: panel_convert_kernel<512><<<grid, 256, 0, s>>>(w.tiles, k, p32, pl, mv.plane_stride, mv.np, f16s, w.info); break;
     }
 }
 
 // Device bytes of the mixed-precision side buffers for nt tiles of size b:
-// panel copies (two parities), the precision map and the tile lists.
+// the FP32 running sums, panel copies (two parities; FP32, three bfloat16 or
+// two binary16 parts), the tile lists and the precision map.
 size_t mixed_extra_bytes(int64_t nt, int b, int precision)
 {
     if (precision == GL_FP64) return 0;
     const size_t slot = (size_t)nt * b * b;
-    size_t panel = (precision == GL_MIXED_FP32) ? 2 * slot * sizeof(float) : 2 * 3 * slot * sizeof(uint16_t);
+    const size_t parts = (precision == GL_MIXED_FP16) ? 2 : 3;
+    size_t panel = (precision == GL_MIXED_FP32) ? 2 * slot * sizeof(float) : 2 * parts * slot * sizeof(uint16_t);
     const size_t tc = (size_t)tile_count(nt);
     return tc * b * b * sizeof(float) + panel + tc * sizeof(int2) + ((tc + 255) / 256) * 256 + 1024;
 }
@@ -521,11 +596,12 @@ void mixed_views(Work &w)
         p += 2 * slot * sizeof(float);
         mv.np = 0;
     } else {
+        const int parts = (w.precision == GL_MIXED_FP16) ? 2 : 3;
         mv.planes[0] = reinterpret_cast<uint16_t *>(p);
-        mv.planes[1] = mv.planes[0] + 3 * slot;
+        mv.planes[1] = mv.planes[0] + parts * slot;
         mv.plane_stride = (int64_t)slot;
-        mv.np = 3;
-        p += 2 * 3 * slot * sizeof(uint16_t);
+        mv.np = parts;
+        p += 2 * parts * slot * sizeof(uint16_t);
     }
     const size_t tc = (size_t)tile_count(w.nt);
     mv.lists = reinterpret_cast<int2 *>(p);
@@ -589,8 +665,16 @@ int mixed_factorize(Lanes &ln, Work &w, gl_theta th, const gl_opts &o, hipStream
     launch_fill(reinterpret_cast<double *>(w.mv.delta), tile_count(w.nt) * w.b * w.b / 2, 0.0, s);
     // step 0's POTRF first: its pivots set the adaptive thresholds
     launch_potrf(w.tiles, w.b, 0, w.n, w.info, w.logsum, w.dinv_k(0), s);
-    thresholds_kernel<<<1, 256, 0, s>>>(w.tiles, w.b, w.n, th.theta1, o.accuracy, o.tol_64, o.tol_hi, o.tol_lo,
-                                        w.mv.thr);
+    thresholds_kernel<<<1, 256, 0, s>>>(w.tiles, w.b, w.n, th.theta1, w.precision, o.accuracy, o.tol_64, o.tol_hi,
+                                        o.tol_lo, w.mv.thr);
+    if (w.precision == GL_MIXED_FP16) {
+        // every |L_ik| <= sqrt(max Σ_ii) = sqrt(max(θ1, 1)) (padding rows have
+        // a unit diagonal); scale that bound to at most 2^14, below the
+        // binary16 maximum 65504 with room for rounding
+        const int e = 14 - (int)std::ceil(0.5 * std::log2(std::max(th.theta1, 1.0)));
+        w.mv.f16_scale = std::ldexp(1.0, e);
+        w.mv.f16_unscale = (float)std::ldexp(1.0, -2 * e);
+    }
     MixedPlan plan;
     int rc = build_lists(w, o, s, plan);
     if (rc != GL_OK) return rc;

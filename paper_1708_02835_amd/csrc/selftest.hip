@@ -40,13 +40,28 @@ __global__ void probe_bf16(double *out)
     for (int r = 0; r < 4; ++r) out[l * 4 + r] = (double)acc[r];
 }
 
+__global__ void probe_f16(double *out)
+{
+    const int l = threadIdx.x;
+    f16x8 a, b;
+    for (int q = 0; q < 8; ++q) {
+        const int k = 8 * (l >> 4) + q;
+        a[q] = (_Float16)(float)((l & 15) + 1 + (k & 3));  // small integers: exact in fp16
+        b[q] = (_Float16)(float)(((l & 15) % 5) - (k % 3));
+    }
+    f4 acc = {0.f, 0.f, 0.f, 0.f};
+    acc = mfma_f16(a, b, acc);
+    for (int r = 0; r < 4; ++r) out[l * 4 + r] = (double)acc[r];
+}
+
 int selftest_mfma(int which, double *out_h, int64_t cap)
 {
     double *d = nullptr;
     GL_HIP_TRY(hipMalloc(reinterpret_cast<void **>(&d), 256 * sizeof(double)));
     if (which == 0) probe_f64<<<1, 64>>>(d);
     else if (which == 1) probe_f32<<<1, 64>>>(d);
-    else probe_bf16<<<1, 64>>>(d);
+    else if (which == 2) probe_bf16<<<1, 64>>>(d);
+    else probe_f16<<<1, 64>>>(d);
     hipError_t e = hipGetLastError();
     if (e == hipSuccess) e = hipMemcpy(out_h, d, 256 * sizeof(double), hipMemcpyDeviceToHost);
     hipFree(d);

@@ -630,7 +630,7 @@ int lq_submit(lq_queue *q, uint64_t ds, gl_theta th, const gl_opts *opts, uint64
     if (opts) o = *opts;
     o.keep_factor = 0;
     o.graph = 0;  // the queue schedules its own launches
-    if (!valid_opts(o) || o.ind_tiles != 0) return GL_EINVAL;
+    if (!valid_opts(o) || !valid_theta_for(th, o) || o.ind_tiles != 0) return GL_EINVAL;
     o = resolved_opts(o);
     ServeState *st = serve_state(q->ctx);
     Request *r = new Request();

@@ -87,6 +87,8 @@ def test_footprint_formula(n, tile):
     extra16 = tc * tile * tile * 4 + 2 * 3 * nt * tile * tile * 2 + tc * 8 + ((tc + 255) // 256) * 256 + 1024
     assert g.gl_footprint_bytes(n, tile, g.GL_MIXED_FP32) == tiles + vec + extra32
     assert g.gl_footprint_bytes(n, tile, g.GL_MIXED_BF16) == tiles + vec + extra16
+    extrah = tc * tile * tile * 4 + 2 * 2 * nt * tile * tile * 2 + tc * 8 + ((tc + 255) // 256) * 256 + 1024
+    assert g.gl_footprint_bytes(n, tile, g.GL_MIXED_FP16) == tiles + vec + extrah
 
 
 def test_automatic_tile_choice_footprints_are_monotone():

@@ -124,16 +124,17 @@ def test_krige_variance_parity(g, ctx, metric, n, tile, m, theta):
     assert np.all(np.abs(var[:2]) <= tol * theta[0])
 
 
-def test_krige_variance_mixed_factor(g, ctx):
-    """Variances from a BF16-mode factor against the FP64 ones: the stated
-    mixed bound of 1e-4, relative to θ1."""
+@pytest.mark.parametrize("mixed", [2, 3])
+def test_krige_variance_mixed_factor(g, ctx, mixed):
+    """Variances from a BF16- or FP16-mode factor against the FP64 ones: the
+    stated mixed bound of 1e-4, relative to θ1."""
     theta = (1.0, 0.1, 0.5)
     n, m = 2048, 400
     x, y = geoinputs.jittered_grid(n, 8)
     z = geoinputs.normal_vector(n, 8)
     xn, yn = geoinputs.uniform_points(m, 8)
     out = {}
-    for prec in (0, 2):
+    for prec in (0, mixed):
         r = g.loglik_eval(ctx, dev(x), dev(y), dev(z), theta, g.gl_opts_default(precision=prec, tile=256,
                                                                                   keep_factor=1))
         try:
@@ -141,8 +142,8 @@ def test_krige_variance_mixed_factor(g, ctx):
                                                                   return_variance=True)]
         finally:
             g.gl_factor_release(ctx, r["factor"])
-    assert np.max(np.abs(out[2][1] - out[0][1])) <= 1e-4 * theta[0]
-    assert np.max(np.abs(out[2][0] - out[0][0])) <= 1e-4 * np.max(np.abs(z))
+    assert np.max(np.abs(out[mixed][1] - out[0][1])) <= 1e-4 * theta[0]
+    assert np.max(np.abs(out[mixed][0] - out[0][0])) <= 1e-4 * np.max(np.abs(z))
 
 
 def test_serve_gcd_bit_identical(g, ctx):

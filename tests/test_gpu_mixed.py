@@ -10,7 +10,9 @@
   unit roundoff supports on a well-conditioned Σ (θ = (1, 0.1, 0.5), n = 2048,
   about 2e-8 for FP32-grade products, 2e-5 for single bfloat16 products in
   CPU emulations of the same algorithm), with a margin of 25-50×, so that a
-  missing product term or a wrong operand fails loudly.
+  missing product term or a wrong operand fails loudly.  The scaled binary16
+  classes: about 4e-9 for two parts (three products) and 8e-7 for one part
+  in the same emulation; bounds 1e-6 and 5e-5.
 """
 import math
 
@@ -100,6 +102,8 @@ FORCED = [
     ("bf16x6", 2, 0.0, 0.0, "bf16x6", 1e-6),
     ("bf16x3", 2, math.inf, 0.0, "bf16x3", 1e-5),
     ("bf16", 2, math.inf, math.inf, "bf16", 5e-4),
+    ("fp16x3", 3, -1.0, 0.0, "fp16x3", 1e-6),
+    ("fp16", 3, -1.0, math.inf, "fp16", 5e-5),
 ]
 
 
@@ -120,7 +124,7 @@ def test_mixed_forced_class(g, ctx, name, prec, thi, tlo, cls, bound):
 
 
 @pytest.mark.parametrize("theta", [(1.0, 0.1, 0.5), (1.0, 0.3, 1.0)])
-@pytest.mark.parametrize("prec", [1, 2])
+@pytest.mark.parametrize("prec", [1, 2, 3])
 def test_mixed_default_bound(g, ctx, theta, prec):
     x, y, z, ref = _problem(theta)
     r = g.loglik_eval(ctx, dev(x), dev(y), dev(z), theta, g.gl_opts_default(precision=prec, tile=256))
@@ -129,13 +133,14 @@ def test_mixed_default_bound(g, ctx, theta, prec):
 
 
 @pytest.mark.parametrize("tile", [128, 256, 384, 512])
-@pytest.mark.parametrize("prec", [1, 2])
+@pytest.mark.parametrize("prec", [1, 2, 3])
 def test_mixed_all_tile_sizes_ragged(g, ctx, tile, prec):
     n, theta = 1700, (1.3, 0.07, 1.5)
     x, y = geoinputs.jittered_grid(n, 77)
     z = geoinputs.normal_vector(n, 77)
     ref = oracle.loglik(x, y, z, theta)
-    # every off-band tile in the FP32-grade class of the mode (FP32, or BF16x6)
+    # every off-band tile in the FP32-grade class of the mode (FP32, BF16x6 or
+    # FP16x3: tol_lo = 0 in the FP16 mode)
     thi = math.inf if prec == 1 else 0.0
     r = g.loglik_eval(ctx, dev(x), dev(y), dev(z), theta,
                       g.gl_opts_default(precision=prec, tile=tile, band=1, tol_64=math.inf, tol_hi=thi,
@@ -159,6 +164,44 @@ def test_mixed_not_spd(g, ctx):
     # the context stays usable after a failure
     ok = g.loglik_eval(ctx, dev(x), dev(y), dev(z), (1.0, 0.05, 0.5), g.gl_opts_default(precision=2, tile=256))
     assert ok["status"] == g.GL_OK and math.isfinite(ok["loglik"])
+
+
+def test_mixed_fp16_not_spd(g, ctx):
+    """The same indefinite case with every off-band tile in one binary16 part."""
+    x, y = geoinputs.jittered_grid(N_MIX, 5)
+    z = geoinputs.normal_vector(N_MIX, 5)
+    opts = g.gl_opts_default(precision=3, tile=256, band=1, tol_64=math.inf, tol_lo=math.inf)
+    r = g.loglik_eval(ctx, dev(x), dev(y), dev(z), (1.0, 0.3, 2.5), opts)
+    assert r["status"] == g.GL_NOT_SPD and r["loglik"] == -math.inf and r["info"] > 0
+
+
+@pytest.mark.parametrize("theta1", [0.01, 1.0, 37.0, 1e6])
+def test_mixed_fp16_scale_follows_theta1(g, ctx, theta1):
+    """The binary16 parts are scaled by a power of two from θ1, so the error
+    relative to l does not depend on the variance scale (values above 65504
+    or far below the binary16 range would show up here)."""
+    n, tile = 1500, 256
+    theta = (theta1, 0.1, 0.5)
+    x, y = geoinputs.jittered_grid(n, 91)
+    e = geoinputs.normal_vector(n, 91)
+    z, info = oracle.synth(x, y, e, theta)
+    assert info == 0
+    ref = oracle.loglik(x, y, z, theta)
+    r = g.loglik_eval(ctx, dev(x), dev(y), dev(z), theta,
+                      g.gl_opts_default(precision=3, tile=tile, band=1, tol_64=math.inf, tol_lo=0.0))
+    assert r["status"] == g.GL_OK
+    assert rel(r["loglik"], ref[0]) <= 1e-6
+    assert rel(r["logdet"], ref[1]) <= 1e-5
+
+
+def test_mixed_rejects_huge_variance(g, ctx):
+    x, y = geoinputs.jittered_grid(300, 92)
+    z = geoinputs.normal_vector(300, 92)
+    for prec in (1, 2, 3):
+        with pytest.raises(g.GeolikError):
+            g.loglik_eval(ctx, dev(x), dev(y), dev(z), (1e31, 0.1, 0.5), g.gl_opts_default(precision=prec))
+    r = g.loglik_eval(ctx, dev(x), dev(y), dev(z), (1e31, 0.1, 0.5), g.gl_opts_default(precision=0))
+    assert r["status"] == g.GL_OK
 
 
 def test_mixed_factor_kriging(g, ctx):
@@ -191,3 +234,8 @@ def test_adaptive_thresholds_follow_first_tile_pivots(g, ctx):
         assert thr["rho"] == pytest.approx(rho, rel=1e-9)
         er = 1e-4 * thr["rho"]
         assert thr["tol_64"] == er * 2.0 ** 24 and thr["tol_hi"] == er * 2.0 ** 16 and thr["tol_lo"] == er * 2.0 ** 8
+        r = g.loglik_eval(ctx, dev(x), dev(y), dev(z), theta, g.gl_opts_default(precision=3, tile=256))
+        assert r["status"] == g.GL_OK
+        t16 = g.gl_precision_stats(ctx)["thresholds"]
+        assert t16["rho"] == thr["rho"]
+        assert t16["tol_64"] == er * 2.0 ** 22 and t16["tol_hi"] == t16["tol_64"] and t16["tol_lo"] == er * 2.0 ** 11

@@ -2,8 +2,9 @@
 FP64 ones: a derivative-free optimiser (Nelder-Mead over log θ, restarted
 from its own result until it stops improving — the restarts keep a collapsed
 simplex on the Matérn likelihood's ridge from ending the search; a stand-in
-for the paper's BOBYQA) maximises l(θ) with each precision from the same
-start; every component of θ̂ must agree within 1 %."""
+for the paper's BOBYQA) maximises l(θ) with each precision (FP64, the BF16
+and the FP16 modes) from the same start; every component of θ̂ must agree
+within 1 %."""
 import math
 
 import numpy as np
@@ -54,9 +55,11 @@ def test_mixed_mle_within_one_percent_of_fp64(g, truth):
         assert info == 0
         start = (0.7 * truth[0], 1.4 * truth[1], 0.8 * truth[2])
         t64, r64 = fit(g, ctx, xd, yd, zd, g.GL_FP64, start)
-        tbf, rbf = fit(g, ctx, xd, yd, zd, g.GL_MIXED_BF16, start)
+        fits = {name: fit(g, ctx, xd, yd, zd, prec, start)
+                for name, prec in (("bf16", g.GL_MIXED_BF16), ("fp16", g.GL_MIXED_FP16))}
     finally:
         ctx.close()
-    rel = np.abs(tbf - t64) / t64
-    print(f"truth={truth} fp64={t64} bf16={tbf} rel={rel} evals={r64.nfev},{rbf.nfev}")
-    assert np.all(rel <= 0.01), (t64, tbf)
+    for name, (tm, rm) in fits.items():
+        rel = np.abs(tm - t64) / t64
+        print(f"truth={truth} fp64={t64} {name}={tm} rel={rel} evals={r64.nfev},{rm.nfev}")
+        assert np.all(rel <= 0.01), (name, t64, tm)

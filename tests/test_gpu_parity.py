@@ -107,7 +107,7 @@ def noise_floor(x, y, z, theta, reps=3):
 
 # ------------------------------------------------------------------ layouts --
 
-@pytest.mark.parametrize("which", [0, 1, 2])
+@pytest.mark.parametrize("which", [0, 1, 2, 3])
 def test_matrix_core_lane_layout(g, ctx, which):
     out = g.gl_selftest(ctx, which)
     lanes = np.arange(64)
