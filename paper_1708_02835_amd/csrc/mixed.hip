@@ -317,6 +317,7 @@ constexpr int HP = HK + 8;    // LDS row pitch in bf16 (80 bytes: conflict-free 
 template <int B, int NP, bool F16>
 __global__ __launch_bounds__(256, 2) void trailing_bf16_kernel(float *__restrict__ delta,
                                                                const uint16_t *__restrict__ planes,
+                                                               const uint16_t *__restrict__ planes_prev,
                                                                int64_t plane_stride,
                                                                const int2 *__restrict__ list,
                                                                int64_t nblocks,
@@ -333,9 +334,12 @@ __global__ __launch_bounds__(256, 2) void trailing_bf16_kernel(float *__restrict
     if (!valid) return;
     const int2 ij = list[t];
     const int rb = sub / SB, cb = sub % SB;
-    // row-major parts: element (r, kk) of tile slot s at s*B*B + r*B + kk
-    const uint16_t *Ap = planes + (int64_t)ij.x * B * B + (int64_t)(rb * FB) * B;
-    const uint16_t *Bp = planes + (int64_t)ij.y * B * B + (int64_t)(cb * FB) * B;
+    // row-major parts: element (r, kk) of tile slot s at s*B*B + r*B + kk.
+    // With planes_prev (the parts of step k-1) the update covers both steps,
+    // K = 2b: A_ij -= L_i,k-1 L_j,k-1ᵀ + L_ik L_jkᵀ, one running-sum update.
+    const int64_t aoff = (int64_t)ij.x * B * B + (int64_t)(rb * FB) * B;
+    const int64_t boff = (int64_t)ij.y * B * B + (int64_t)(cb * FB) * B;
+    const uint16_t *first = planes_prev ? planes_prev : planes;
     float *C = delta + tile_offset(ij.x, ij.y, B) + (int64_t)(cb * FB) * B + rb * FB;
 
     __shared__ uint16_t As[NP][FB][HP];
@@ -372,8 +376,14 @@ __global__ __launch_bounds__(256, 2) void trailing_bf16_kernel(float *__restrict
     // two register sets (one or two parts): the chunk two steps ahead is in
     // flight while one is computed, so global latency is covered by two chunks
     // of products
+    constexpr int NK = B / HK;  // chunks per step; even for every supported tile size
+    const int NKT = planes_prev ? 2 * NK : NK;
     u4 ra0[NP][2], rb0[NP][2], ra1[NP][2], rb1[NP][2];
-    auto load = [&](u4 (&ra)[NP][2], u4 (&rbv)[NP][2], int k0) {
+    auto load = [&](u4 (&ra)[NP][2], u4 (&rbv)[NP][2], int kc) {
+        const bool second = kc >= NK;
+        const uint16_t *P = second ? planes : first;
+        const uint16_t *Ap = P + aoff, *Bp = P + boff;
+        const int k0 = (second ? kc - NK : kc) * HK;
 #pragma unroll
         for (int p = 0; p < NP; ++p)
 #pragma unroll
@@ -427,29 +437,28 @@ __global__ __launch_bounds__(256, 2) void trailing_bf16_kernel(float *__restrict
                 }
             }
     };
-    constexpr int NK = B / HK;  // even for every supported tile size
     if constexpr (NP <= 2) {
         load(ra0, rb0, 0);
-        load(ra1, rb1, HK);
-        for (int kc = 0; kc < NK; kc += 2) {
+        load(ra1, rb1, 1);
+        for (int kc = 0; kc < NKT; kc += 2) {
             store(ra0, rb0);
             __syncthreads();
-            if (kc + 2 < NK) load(ra0, rb0, (kc + 2) * HK);
+            if (kc + 2 < NKT) load(ra0, rb0, kc + 2);
             compute();
             __syncthreads();
             store(ra1, rb1);
             __syncthreads();
-            if (kc + 3 < NK) load(ra1, rb1, (kc + 3) * HK);
+            if (kc + 3 < NKT) load(ra1, rb1, kc + 3);
             compute();
             __syncthreads();
         }
     } else {
         // three parts: one register set (a second would spill)
         load(ra0, rb0, 0);
-        for (int kc = 0; kc < NK; ++kc) {
+        for (int kc = 0; kc < NKT; ++kc) {
             store(ra0, rb0);
             __syncthreads();
-            if (kc + 1 < NK) load(ra0, rb0, (kc + 1) * HK);
+            if (kc + 1 < NKT) load(ra0, rb0, kc + 1);
             compute();
             __syncthreads();
         }
@@ -471,9 +480,14 @@ __global__ __launch_bounds__(256, 2) void trailing_bf16_kernel(float *__restrict
 
 // ------------------------------------------------------------- launchers --
 
+// Split-product classes (bfloat16 and binary16 parts) can take the updates of
+// steps k-1 and k in one launch (pair = true: the parts of both panels are
+// held, by parity).
+static bool paired_class(int cls) { return cls >= CB6; }
+
 template <int B>
 static void launch_class(int cls, double *tiles, int64_t k, const MixedViews &mv, const int2 *list,
-                         int64_t count, const int64_t *info, bool critical, hipStream_t s)
+                         int64_t count, const int64_t *info, bool critical, bool pair, hipStream_t s)
 {
     if (count <= 0) return;
     const int64_t sub = (int64_t)(B / FB) * (B / FB);
@@ -481,6 +495,7 @@ static void launch_class(int cls, double *tiles, int64_t k, const MixedViews &mv
     const unsigned grid = (unsigned)(ceil_div(nblocks, 8) * 8);
     const int crit = critical ? 1 : 0;
     const int par = (int)(k & 1);
+    const uint16_t *prev = pair ? mv.planes[par ^ 1] : nullptr;
     switch (cls) {
     case C64:
         launch_trailing_list(tiles, B, k, list, count, info, critical, s);
@@ -489,36 +504,36 @@ static void launch_class(int cls, double *tiles, int64_t k, const MixedViews &mv
         trailing_f32_kernel<B><<<grid, 256, 0, s>>>(mv.delta, mv.p32[par], list, nblocks, info, crit);
         break;
     case CB6:
-        trailing_bf16_kernel<B, 3, false><<<grid, 256, 0, s>>>(mv.delta, mv.planes[par], mv.plane_stride, list,
+        trailing_bf16_kernel<B, 3, false><<<grid, 256, 0, s>>>(mv.delta, mv.planes[par], prev, mv.plane_stride, list,
                                                                  nblocks, info, crit, 1.0f);
         break;
     case CB3:
-        trailing_bf16_kernel<B, 2, false><<<grid, 256, 0, s>>>(mv.delta, mv.planes[par], mv.plane_stride, list,
+        trailing_bf16_kernel<B, 2, false><<<grid, 256, 0, s>>>(mv.delta, mv.planes[par], prev, mv.plane_stride, list,
                                                                  nblocks, info, crit, 1.0f);
         break;
     case CB1:
-        trailing_bf16_kernel<B, 1, false><<<grid, 256, 0, s>>>(mv.delta, mv.planes[par], mv.plane_stride, list,
+        trailing_bf16_kernel<B, 1, false><<<grid, 256, 0, s>>>(mv.delta, mv.planes[par], prev, mv.plane_stride, list,
                                                                  nblocks, info, crit, 1.0f);
         break;
     case CH2:
-        trailing_bf16_kernel<B, 2, true><<<grid, 256, 0, s>>>(mv.delta, mv.planes[par], mv.plane_stride, list,
+        trailing_bf16_kernel<B, 2, true><<<grid, 256, 0, s>>>(mv.delta, mv.planes[par], prev, mv.plane_stride, list,
                                                                 nblocks, info, crit, mv.f16_unscale);
         break;
     default:
-        trailing_bf16_kernel<B, 1, true><<<grid, 256, 0, s>>>(mv.delta, mv.planes[par], mv.plane_stride, list,
+        trailing_bf16_kernel<B, 1, true><<<grid, 256, 0, s>>>(mv.delta, mv.planes[par], prev, mv.plane_stride, list,
                                                                 nblocks, info, crit, mv.f16_unscale);
         break;
     }
 }
 
 static void launch_class_any(int b, int cls, double *tiles, int64_t k, const MixedViews &mv, const int2 *list,
-                             int64_t count, const int64_t *info, bool critical, hipStream_t s)
+                             int64_t count, const int64_t *info, bool critical, bool pair, hipStream_t s)
 {
     switch (b) {
-    case 128: launch_class<128>(cls, tiles, k, mv, list, count, info, critical, s); break;
-    case 256: launch_class<256>(cls, tiles, k, mv, list, count, info, critical, s); break;
-    case 384: launch_class<384>(cls, tiles, k, mv, list, count, info, critical, s); break;
-    default: launch_class<512>(cls, tiles, k, mv, list, count, info, critical, s); break;
+    case 128: launch_class<128>(cls, tiles, k, mv, list, count, info, critical, pair, s); break;
+    case 256: launch_class<256>(cls, tiles, k, mv, list, count, info, critical, pair, s); break;
+    case 384: launch_class<384>(cls, tiles, k, mv, list, count, info, critical, pair, s); break;
+    default: launch_class<512>(cls, tiles, k, mv, list, count, info, critical, pair, s); break;
     }
 }
 
@@ -649,13 +664,21 @@ static int build_lists(Work &w, const gl_opts &o, hipStream_t s, MixedPlan &plan
 }
 
 // Trailing updates of step k for tile columns [j0, j1] of every class.
+// Which classes a launch group covers: every class with panel k alone, only
+// the per-step classes (binary64, FP32) with panel k, or those with panel k
+// and the split-product classes with panels k-1 and k.
+enum { UPD_ALL = 0, UPD_STEP = 1, UPD_PAIR = 2 };
+
 static void class_updates(Work &w, int64_t k, int64_t j0, int64_t j1, const MixedPlan &plan, bool critical,
-                          hipStream_t s)
+                          int sel, hipStream_t s)
 {
     for (int c = 0; c < NCLASS; ++c) {
+        if (sel == UPD_STEP && paired_class(c)) continue;
+        const bool pair = sel == UPD_PAIR && paired_class(c);
         const int64_t a = plan.start[c][j0], e = plan.start[c][j1 + 1];
         if (e > a)
-            launch_class_any(w.b, c, w.tiles, k, w.mv, w.mv.lists + plan.base[c] + a, e - a, w.info, critical, s);
+            launch_class_any(w.b, c, w.tiles, k, w.mv, w.mv.lists + plan.base[c] + a, e - a, w.info, critical, pair,
+                             s);
     }
 }
 
@@ -680,6 +703,7 @@ int mixed_factorize(Lanes &ln, Work &w, gl_theta th, const gl_opts &o, hipStream
     if (rc != GL_OK) return rc;
     if (plan_out) *plan_out = plan;
     hipStream_t la = ln.la;
+    const bool pairs = w.precision == GL_MIXED_BF16 || w.precision == GL_MIXED_FP16;
     GL_HIP_TRY(hipEventRecord(ln.fork, s));
     GL_HIP_TRY(hipStreamWaitEvent(la, ln.fork, 0));
     for (int64_t k = 0; k < w.nt; ++k) {
@@ -689,13 +713,22 @@ int mixed_factorize(Lanes &ln, Work &w, gl_theta th, const gl_opts &o, hipStream
         launch_trsm(w.tiles, w.b, w.nt, k, w.dinv_k(k), w.info, s);
         launch_fwd_update(w.tiles, w.b, w.nt, k, w.v, w.info, s);
         if (k + 1 < w.nt) {
+            // Split-product classes take two steps per update of their running
+            // sums: at an even step k only the next column gets panel k (the
+            // critical path needs it); the rest of panel k joins panel k+1 in
+            // the launches of step k+1, which read both parities.  So the
+            // parity that an even step writes may still be read by the
+            // previous step's bulk launch: wait for it first.
+            const bool odd = pairs && (k & 1);
+            const bool even_wait = pairs && !odd && k > 0;
+            if (even_wait) GL_HIP_TRY(hipStreamWaitEvent(s, ln.bulk, 0));
             launch_panel_convert(w, k, w.mv, s);
             GL_HIP_TRY(hipEventRecord(ln.panel, s));
-            if (k > 0) GL_HIP_TRY(hipStreamWaitEvent(s, ln.bulk, 0));
-            class_updates(w, k, k + 1, k + 1, plan, true, s);
+            if (k > 0 && !even_wait) GL_HIP_TRY(hipStreamWaitEvent(s, ln.bulk, 0));
+            class_updates(w, k, k + 1, k + 1, plan, true, odd ? UPD_PAIR : UPD_ALL, s);
             if (k + 2 < w.nt) {
                 GL_HIP_TRY(hipStreamWaitEvent(la, ln.panel, 0));
-                class_updates(w, k, k + 2, w.nt - 1, plan, false, la);
+                class_updates(w, k, k + 2, w.nt - 1, plan, false, odd ? UPD_PAIR : (pairs ? UPD_STEP : UPD_ALL), la);
                 GL_HIP_TRY(hipEventRecord(ln.bulk, la));
             }
         }
