@@ -704,6 +704,13 @@ int mixed_factorize(Lanes &ln, Work &w, gl_theta th, const gl_opts &o, hipStream
     if (plan_out) *plan_out = plan;
     hipStream_t la = ln.la;
     const bool pairs = w.precision == GL_MIXED_BF16 || w.precision == GL_MIXED_FP16;
+    // Split-product tiles per column, for the split column of each pair below.
+    std::vector<int64_t> pcol((size_t)w.nt, 0);
+    for (int c = 0; c < NCLASS; ++c)
+        if (paired_class(c))
+            for (int64_t j = 0; j < w.nt; ++j) pcol[(size_t)j] += plan.start[c][j + 1] - plan.start[c][j];
+    const int64_t near_tiles = (int64_t)1536 * (512 / w.b) * (512 / w.b) * (512 / w.b);
+    int64_t js = w.nt;  // columns >= js take the current pair of panels in one update
     GL_HIP_TRY(hipEventRecord(ln.fork, s));
     GL_HIP_TRY(hipStreamWaitEvent(la, ln.fork, 0));
     for (int64_t k = 0; k < w.nt; ++k) {
@@ -714,21 +721,35 @@ int mixed_factorize(Lanes &ln, Work &w, gl_theta th, const gl_opts &o, hipStream
         launch_fwd_update(w.tiles, w.b, w.nt, k, w.v, w.info, s);
         if (k + 1 < w.nt) {
             // Split-product classes take two steps per update of their running
-            // sums: at an even step k only the next column gets panel k (the
-            // critical path needs it); the rest of panel k joins panel k+1 in
-            // the launches of step k+1, which read both parities.  So the
-            // parity that an even step writes may still be read by the
-            // previous step's bulk launch: wait for it first.
+            // sums.  At an even step k the next column gets panel k (the
+            // critical path needs it), and so do the nearest columns up to js,
+            // about near_tiles split-product tiles: work for the lookahead
+            // stream while step k+1's critical path runs.  Columns from js on
+            // defer panel k to step k+1, whose launches apply panels k and
+            // k+1 together (both parities are held).  So the parity that an
+            // even step writes may still be read by the previous step's bulk
+            // launch: wait for it first.
             const bool odd = pairs && (k & 1);
             const bool even_wait = pairs && !odd && k > 0;
+            if (pairs && !odd) {
+                int64_t acc = 0;
+                js = k + 2;
+                while (js < w.nt && acc < near_tiles) acc += pcol[(size_t)js++];
+            }
             if (even_wait) GL_HIP_TRY(hipStreamWaitEvent(s, ln.bulk, 0));
             launch_panel_convert(w, k, w.mv, s);
             GL_HIP_TRY(hipEventRecord(ln.panel, s));
             if (k > 0 && !even_wait) GL_HIP_TRY(hipStreamWaitEvent(s, ln.bulk, 0));
-            class_updates(w, k, k + 1, k + 1, plan, true, odd ? UPD_PAIR : UPD_ALL, s);
+            class_updates(w, k, k + 1, k + 1, plan, true, (odd && k + 1 >= js) ? UPD_PAIR : UPD_ALL, s);
             if (k + 2 < w.nt) {
                 GL_HIP_TRY(hipStreamWaitEvent(la, ln.panel, 0));
-                class_updates(w, k, k + 2, w.nt - 1, plan, false, odd ? UPD_PAIR : (pairs ? UPD_STEP : UPD_ALL), la);
+                if (!pairs) {
+                    class_updates(w, k, k + 2, w.nt - 1, plan, false, UPD_ALL, la);
+                } else {
+                    const int64_t split = std::max(js, k + 2);
+                    if (split > k + 2) class_updates(w, k, k + 2, split - 1, plan, false, UPD_ALL, la);
+                    if (split < w.nt) class_updates(w, k, split, w.nt - 1, plan, false, odd ? UPD_PAIR : UPD_STEP, la);
+                }
                 GL_HIP_TRY(hipEventRecord(ln.bulk, la));
             }
         }
