@@ -80,15 +80,18 @@ __host__ __device__ inline MaternSetup matern_setup(double t1, double t2, double
     return s;
 }
 
-// Reciprocals the series and recurrences below divide by, for one μ: filled
-// once per workgroup in LDS so the per-element loops only multiply
-// (1/(k-μ), 1/(k+μ) for the series, 1/k for both).
+// Per-k constants of the series and the recurrence below, for one μ: filled
+// once per workgroup in LDS so the per-element loops only multiply and add
+// (1/(k-μ), 1/(k+μ) for the series, 1/k for both, and the recurrence
+// coefficients (k+1/2)² - μ² and ((k-1/2)² - μ²)/k).
 constexpr int GL_TEMME_TERMS = 40;
 constexpr int GL_MILLER_MAX = 80;
 struct BesselTab {
-    double rm[GL_TEMME_TERMS];   // 1/(k - μ)
-    double rp[GL_TEMME_TERMS];   // 1/(k + μ)
+    double rm[GL_TEMME_TERMS];     // 1/(k - μ)
+    double rp[GL_TEMME_TERMS];     // 1/(k + μ)
     double rk[GL_MILLER_MAX + 1];  // 1/k
+    double ma[GL_MILLER_MAX + 1];  // (k + 1/2)² - μ²
+    double mb[GL_MILLER_MAX + 1];  // ((k - 1/2)² - μ²) / k
 };
 
 // Every thread of the workgroup calls this before the first matern_eval with
@@ -102,28 +105,30 @@ __device__ inline void bessel_tab_init(const MaternSetup &s, BesselTab &t)
             t.rp[k] = 1.0 / (dk + s.mu);
         }
         t.rk[k] = k ? 1.0 / dk : 0.0;
+        t.ma[k] = (dk + 0.5) * (dk + 0.5) - s.mu * s.mu;
+        t.mb[k] = k ? ((dk - 0.5) * (dk - 0.5) - s.mu * s.mu) / dk : 0.0;
     }
     __syncthreads();
 }
 
-// K_μ(x) and K_μ+1(x) for x <= 2 (Temme's series), unscaled.
-__host__ __device__ inline void bessel_k_temme(const MaternSetup &s, double x, double &k0, double &k1,
+// K_μ(x) and K_μ+1(x) for x <= 2 (Temme's series), unscaled; lx = log(2/x).
+// One exponential e^σ, σ = μ lx, gives sinh σ, cosh σ and (x/2)^∓μ.
+__host__ __device__ inline void bessel_k_temme(const MaternSetup &s, double x, double lx, double &k0, double &k1,
                                                const BesselTab *tab = nullptr)
 {
     const double mu = s.mu;
-    const double lx = log(2.0 / x);
     const double sig = mu * lx;
+    const double e = exp(sig), ei = 1.0 / e;
     double shs;  // sinh(σ)/σ
-    if (fabs(sig) < 1e-3) {
-        double q = sig * sig;
-        shs = 1.0 + q / 6.0 + q * q / 120.0;
+    if (fabs(sig) < 0.1) {
+        const double q = sig * sig;  // Taylor series to σ⁸, remainder below 3e-18
+        shs = 1.0 + q / 6.0 * (1.0 + q / 20.0 * (1.0 + q / 42.0 * (1.0 + q / 72.0)));
     } else {
-        shs = sinh(sig) / sig;
+        shs = 0.5 * (e - ei) / sig;
     }
-    double f = s.fact * (cosh(sig) * s.g1 + shs * lx * s.g2);
-    double e = exp(sig);
-    double p = 0.5 * e / s.rgp;    // ½ (x/2)^-μ Γ(1+μ)
-    double q = 0.5 / (e * s.rgm);  // ½ (x/2)^μ Γ(1-μ)
+    double f = s.fact * (0.5 * (e + ei) * s.g1 + shs * lx * s.g2);
+    double p = 0.5 * e / s.rgp;   // ½ (x/2)^-μ Γ(1+μ)
+    double q = 0.5 * ei / s.rgm;  // ½ (x/2)^μ Γ(1-μ)
     double c = 1.0;
     const double d = 0.25 * x * x;
     double sum0 = f, sum1 = p;
@@ -163,12 +168,17 @@ __host__ __device__ inline void bessel_k_miller_scaled(const MaternSetup &s, dou
     double t = 1.0;             // Horner accumulation of Σ c_k z_k from the top
     for (int k = kmax; k >= 1; --k) {
         double dk = (double)k;
-        double ak = (dk + 0.5) * (dk + 0.5) - mu2;
-        double zm = 2.0 * (dk + x) * z0 - ak * z1;
+        double zm, ck;
+        if (tab) {
+            zm = 2.0 * (dk + x) * z0 - tab->ma[k] * z1;
+            ck = tab->mb[k];
+        } else {
+            zm = 2.0 * (dk + x) * z0 - ((dk + 0.5) * (dk + 0.5) - mu2) * z1;
+            ck = ((dk - 0.5) * (dk - 0.5) - mu2) / dk;
+        }
         z1 = z0;
         z0 = zm;
-        double akm = (dk - 0.5) * (dk - 0.5) - mu2;
-        t = zm + (tab ? akm * tab->rk[k] : akm / dk) * t;
+        t = zm + ck * t;
     }
     double ssum = t / z0;
     double r0 = z1 / z0;
@@ -191,7 +201,8 @@ __host__ __device__ inline double matern_eval(const MaternSetup &s, double r, co
     if (x > 760.0) return 0.0;  // x^ν e^-x is below the binary64 range for every ν <= 50
     double ka, kb;
     const bool small = (x <= 2.0);
-    if (small) bessel_k_temme(s, x, ka, kb, tab);
+    const double lgx = log(x);  // serves the series' log(2/x) and x^ν or x^ν e^-x
+    if (small) bessel_k_temme(s, x, M_LN2 - lgx, ka, kb, tab);
     else bessel_k_miller_scaled(s, x, ka, kb, tab);
     double knu;
     if (s.nl == 0) {
@@ -206,8 +217,8 @@ __host__ __device__ inline double matern_eval(const MaternSetup &s, double r, co
         }
         knu = kb;
     }
-    if (small) return s.pref * pow(x, s.nu) * knu;
-    return s.pref * exp(s.nu * log(x) - x) * knu;
+    if (small) return s.pref * exp(s.nu * lgx) * knu;
+    return s.pref * exp(s.nu * lgx - x) * knu;
 }
 
 __host__ __device__ inline double dist2d(double x1, double y1, double x2, double y2)
