@@ -345,3 +345,46 @@ int64_t oracle_loglik_ind(const double *x, const double *y, const double *z, int
     out[2] = q;
     return 0;
 }
+
+/*
+ * Kriging under the IND approximation (Sec. 6.8, with the prediction of
+ * Sec. 2.3 Eq. (5)): Σ22 is replaced by its block-diagonal part, blocks of
+ * `block` consecutive observed locations (the last one shorter), so
+ * X = Σ̃22⁻¹ Z2 is solved block by block; the cross-covariance Σ12 between the
+ * new and the observed locations is kept whole: Z1 = Σ12 X.  Returns 0, or the
+ * 1-based global column of the first non-positive pivot.
+ */
+int64_t oracle_krige_ind(const double *x, const double *y, const double *z, int64_t n,
+                         const double *xn, const double *yn, int64_t m,
+                         double theta1, double theta2, double theta3, int metric, double radius,
+                         int64_t block, double *znew)
+{
+    double *v = (double *)malloc((size_t)n * sizeof(double));
+    double *a = (double *)malloc((size_t)block * (size_t)block * sizeof(double));
+    double *w = (double *)malloc((size_t)block * sizeof(double));
+    int64_t info = 0;
+    for (int64_t s = 0; s < n && info == 0; s += block) {
+        const int64_t nb = (n - s < block) ? n - s : block;
+        oracle_cov_symmetric(x + s, y + s, nb, theta1, theta2, theta3, metric, radius, a);
+        const int64_t bi = oracle_cholesky(a, nb);
+        if (bi != 0) {
+            info = s + bi;
+            break;
+        }
+        oracle_forward(a, nb, z + s, w);
+        oracle_backward(a, nb, w, v + s);
+    }
+    if (info == 0) {
+        for (int64_t k = 0; k < m; ++k) {
+            double acc = 0.0;
+            for (int64_t j = 0; j < n; ++j)
+                acc += oracle_matern(oracle_distance(metric, radius, xn[k], yn[k], x[j], y[j]), theta1, theta2,
+                                     theta3) * v[j];
+            znew[k] = acc;
+        }
+    }
+    free(v);
+    free(a);
+    free(w);
+    return info;
+}

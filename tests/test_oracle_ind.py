@@ -61,3 +61,61 @@ def test_ind_reports_first_failing_column():
     z = geoinputs.normal_vector(60, 6)
     l, ld, q, info = oracle.loglik_ind(x, y, z, (1.0, 0.1, 0.5), 30)
     assert info == 46 and l == -math.inf
+
+
+# ------------------------------------------------ kriging under IND (Eq. 5) --
+
+def masked_krige(x, y, z, xn, yn, theta, block):
+    """Z1 = Σ12 Σ̃22⁻¹ Z2 with Σ̃22 the block-masked dense covariance, by a
+    dense LU solve (numpy), independent of the oracle's Cholesky path."""
+    n = x.size
+    a = oracle.cov_symmetric(x, y, theta)
+    blk = np.arange(n) // block
+    a = np.where(blk[:, None] == blk[None, :], a, 0.0)
+    return oracle.cov_matrix(xn, yn, x, y, theta) @ np.linalg.solve(a, z)
+
+
+@pytest.mark.parametrize("n,block", [(90, 32), (100, 25), (64, 7)])
+@pytest.mark.parametrize("theta", [(1.0, 0.1, 0.5), (1.4, 0.2, 1.5)])
+def test_krige_ind_vs_masked_dense(n, block, theta):
+    x, y = geoinputs.jittered_grid(n, 31)
+    z = geoinputs.normal_vector(n, 31)
+    xn, yn = geoinputs.uniform_points(17, 32)
+    got, info = oracle.krige_ind(x, y, z, xn, yn, theta, block)
+    assert info == 0
+    want = masked_krige(x, y, z, xn, yn, theta, block)
+    assert np.max(np.abs(got - want)) <= 1e-10 * np.max(np.abs(want))
+
+
+def test_krige_ind_single_location_blocks_closed_form():
+    """Blocks of one location: Σ̃22 = θ1 I, so Z1 = Σ12 Z2 / θ1."""
+    x, y = geoinputs.jittered_grid(40, 33)
+    z = geoinputs.normal_vector(40, 33)
+    xn, yn = geoinputs.uniform_points(9, 34)
+    theta = (1.6, 0.12, 0.5)
+    got, info = oracle.krige_ind(x, y, z, xn, yn, theta, 1)
+    r = np.hypot(xn[:, None] - x[None, :], yn[:, None] - y[None, :])
+    want = (theta[0] * np.exp(-r / theta[1])) @ z / theta[0]  # ν = 1/2: θ1 exp(-r/θ2)
+    assert info == 0 and np.max(np.abs(got - want)) <= 1e-13 * np.max(np.abs(want))
+
+
+def test_krige_ind_one_block_is_exact():
+    n = 110
+    x, y = geoinputs.jittered_grid(n, 35)
+    z = geoinputs.normal_vector(n, 35)
+    xn, yn = geoinputs.uniform_points(13, 36)
+    theta = (1.0, 0.15, 1.0)
+    exact, info = oracle.krige(x, y, z, xn, yn, theta)
+    assert info == 0
+    for block in (n, 3 * n):
+        got, info = oracle.krige_ind(x, y, z, xn, yn, theta, block)
+        assert info == 0 and np.array_equal(got, exact)
+
+
+def test_krige_ind_reports_first_failing_column():
+    x, y = geoinputs.jittered_grid(60, 37)
+    x[45], y[45] = x[44], y[44]
+    z = geoinputs.normal_vector(60, 37)
+    xn, yn = geoinputs.uniform_points(5, 38)
+    _, info = oracle.krige_ind(x, y, z, xn, yn, (1.0, 0.1, 0.5), 30)
+    assert info == 46
