@@ -112,7 +112,7 @@ typedef struct {
                             every tile outside the diagonal super tiles of s×s tiles is
                             annihilated, i.e. l is summed over blocks of s·b consecutive
                             locations (after reordering, if on), each factored on its own;
-                            GL_FP64 only, no kept factor */
+                            GL_FP64 only, no kept factor (krige_cv also takes it) */
     int32_t graph;       /* 1: GL_FP64 without a kept factor runs everything after staging the
                             inputs as a replayed hipGraph, captured on the first call for a
                             workspace geometry (n, tile) and distance and replayed while they
@@ -206,7 +206,13 @@ int krige_predict(gl_context *ctx, gl_factor *factor, const double *xnew, const 
  * f the locations outside it are factored (loglik_eval with keep_factor, the
  * other opts as given), the fold's measurements are predicted by Eq. (5), and
  * mse_h[f] (host, k doubles) receives the mean squared prediction error over
- * the fold.  Synchronous with respect to `stream`.
+ * the fold.  With opts->ind_tiles = s >= 1 the prediction uses the IND
+ * approximation of the observed locations' covariance (Sec. 6.8, the
+ * exact-versus-IND prediction comparison of the paper's experiments): blocks of
+ * s·b consecutive observed locations (input order, or Morton order with
+ * reorder = 1) are factored on their own, X = Σ̃22⁻¹ Z2 is solved block by
+ * block, and the cross-covariances to the fold's locations are kept whole,
+ * Z1 = Σ12 X.  Synchronous with respect to `stream`.
  * Returns GL_OK; GL_NOT_SPD when some fold's Σ was not positive definite (its
  * mse_h is NaN, the other folds are still computed); GL_EINVAL for k < 2, a
  * fold id out of range, an empty fold or a fold holding every location.

@@ -620,8 +620,10 @@ int krige_cv(gl_context *ctx, const double *x, const double *y, const double *z,
     gl_opts o;
     gl_opts_default(&o);
     if (opts) o = *opts;
-    o.keep_factor = 1;
+    const bool ind = o.ind_tiles > 0;  // IND kriging keeps no factor object
+    o.keep_factor = ind ? 0 : 1;
     if (!valid_opts(o) || !valid_theta_for(th, o)) return GL_EINVAL;
+    const gl_opts ro = resolved_opts(o);
     std::vector<int64_t> count(k, 0);
     for (int64_t i = 0; i < n; ++i) {
         if (fold_h[i] < 0 || fold_h[i] >= k) return GL_EINVAL;
@@ -655,20 +657,26 @@ int krige_cv(gl_context *ctx, const double *x, const double *y, const double *z,
         if (rc == GL_OK) {
             launch_gather3(x, y, z, idx, nk, kx, ky, kz, s);
             launch_gather3(x, y, z, idx + nk, nm, mx, my, mz, s);
-            gl_result r;
-            rc = loglik_eval(ctx, kx, ky, kz, nk, th, &o, &r, stream);
-            if (rc == GL_OK) {
-                rc = krige_predict(ctx, r.factor, mx, my, nm, pred, nullptr, stream);
+            gl_factor *fac = nullptr;
+            if (ind) {
+                rc = ind_krige(ctx, kx, ky, kz, nk, th, ro, mx, my, nm, pred, s);
+            } else {
+                gl_result r;
+                rc = loglik_eval(ctx, kx, ky, kz, nk, th, &o, &r, stream);
                 if (rc == GL_OK) {
-                    launch_mse(pred, mz, nm, dmse, s);
-                    if (hipMemcpyAsync(&mse_h[f], dmse, sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess ||
-                        hipStreamSynchronize(s) != hipSuccess)
-                        rc = GL_EHIP;
+                    fac = static_cast<gl_factor *>(r.factor);
+                    rc = krige_predict(ctx, fac, mx, my, nm, pred, nullptr, stream);
                 }
-                gl_factor_release(ctx, r.factor);
+            }
+            if (rc == GL_OK) {
+                launch_mse(pred, mz, nm, dmse, s);
+                if (hipMemcpyAsync(&mse_h[f], dmse, sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess ||
+                    hipStreamSynchronize(s) != hipSuccess)
+                    rc = GL_EHIP;
             } else if (rc == GL_NOT_SPD) {
                 mse_h[f] = NAN;
             }
+            if (fac) gl_factor_release(ctx, fac);
         }
         if (rc < 0) {
             status = rc;

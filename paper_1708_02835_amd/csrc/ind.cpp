@@ -5,6 +5,12 @@
 // factored: the blocks are independent factorisations of s tile columns each
 // (the last one possibly shorter), advanced together through the fused
 // multi-factorisation launches, one tile step per launch group.
+//
+// Kriging under the same approximation (the prediction experiment of Sec. 7
+// with IND, Eq. (5)): X = Σ̃22⁻¹ Z2 is solved block by block from the block
+// factors (backward substitution of w = L⁻¹ Z2 within each block), and the
+// cross-covariance Σ12 between new and observed locations is kept whole,
+// generated on the fly: Z1 = Σ12 X.
 #include <algorithm>
 #include <vector>
 
@@ -33,8 +39,22 @@ __global__ void ind_total_kernel(const DevResult *__restrict__ r, int64_t nblk, 
     out->quad = info ? NAN : q;
 }
 
-int ind_eval(gl_context *ctx, const double *x, const double *y, const double *z, int64_t n, gl_theta th,
-             const gl_opts &o, gl_result *res, hipStream_t s)
+// The blocks of one IND factorisation: one descriptor per block (factor
+// tiles, padded coordinates, w = L⁻¹ Z of the block in v), the locations the
+// blocks were cut from (input or Morton order) and the device total.
+struct IndPlan {
+    int b = 0;
+    int64_t block = 0, nblk = 0;
+    std::vector<BatchReq> proto;
+    std::vector<int64_t> nb, ntb;
+    const double *sx = nullptr, *sy = nullptr;
+    DevResult *total = nullptr;
+};
+
+// Enqueues the factorisation of every block and the fixed-order sum of the
+// per-block results into p.total (all on s).
+static int ind_factor(gl_context *ctx, const double *x, const double *y, const double *z, int64_t n, gl_theta th,
+                      const gl_opts &o, hipStream_t s, IndPlan &p)
 {
     const int b = pick_tile(n, o.tile);
     const int64_t bt = o.ind_tiles;          // tiles per super tile
@@ -58,14 +78,14 @@ int ind_eval(gl_context *ctx, const double *x, const double *y, const double *z,
     const size_t bytes = off * sizeof(double);
     if (bytes > ctx->ind_cap) {
         const size_t old = ctx->ind_cap;
-        if (ctx->used.load() - old + bytes > ctx->budget) return res->status = GL_ENOMEM;
+        if (ctx->used.load() - old + bytes > ctx->budget) return GL_ENOMEM;
         if (ctx->ind_buf) hipFree(ctx->ind_buf);
         ctx->ind_buf = nullptr;
         ctx->ind_cap = 0;
         ctx->used -= old;
         if (hipMalloc(&ctx->ind_buf, bytes) != hipSuccess) {
             (void)hipGetLastError();
-            return res->status = GL_ENOMEM;
+            return GL_ENOMEM;
         }
         ctx->ind_cap = bytes;
         ctx->used += bytes;
@@ -125,14 +145,68 @@ int ind_eval(gl_context *ctx, const double *x, const double *y, const double *z,
         }
         if (h.empty()) break;
         const int rc = enqueue_step(h.data(), ddesc, (int)h.size(), b, s, nullptr);
-        if (rc != GL_OK) return res->status = rc;
+        if (rc != GL_OK) return rc;
     }
     ind_total_kernel<<<1, 64, 0, s>>>(bres, nblk, block, total);
     GL_HIP_TRY(hipGetLastError());
-    GL_HIP_TRY(hipMemcpyAsync(ctx->res_h, total, sizeof(DevResult), hipMemcpyDeviceToHost, s));
+    p.b = b;
+    p.block = block;
+    p.nblk = nblk;
+    p.proto = std::move(proto);
+    p.nb = std::move(nb);
+    p.ntb = std::move(ntb);
+    p.sx = sx;
+    p.sy = sy;
+    p.total = total;
+    return GL_OK;
+}
+
+int ind_eval(gl_context *ctx, const double *x, const double *y, const double *z, int64_t n, gl_theta th,
+             const gl_opts &o, gl_result *res, hipStream_t s)
+{
+    IndPlan p;
+    const int rc = ind_factor(ctx, x, y, z, n, th, o, s, p);
+    if (rc != GL_OK) return res->status = rc;
+    GL_HIP_TRY(hipMemcpyAsync(ctx->res_h, p.total, sizeof(DevResult), hipMemcpyDeviceToHost, s));
     GL_HIP_TRY(hipStreamSynchronize(s));
-    fill_result(res, *ctx->res_h, b);
+    fill_result(res, *ctx->res_h, p.b);
     return res->status;
+}
+
+int ind_krige(gl_context *ctx, const double *x, const double *y, const double *z, int64_t n, gl_theta th,
+              const gl_opts &o, const double *xnew, const double *ynew, int64_t m, double *znew, hipStream_t s)
+{
+    IndPlan p;
+    int rc = ind_factor(ctx, x, y, z, n, th, o, s, p);
+    if (rc != GL_OK) return rc;
+    GL_HIP_TRY(hipMemcpyAsync(ctx->res_h, p.total, sizeof(DevResult), hipMemcpyDeviceToHost, s));
+    GL_HIP_TRY(hipStreamSynchronize(s));
+    if (ctx->res_h->info != 0) return GL_NOT_SPD;
+    // X = L⁻ᵀ w within each block, in place
+    for (int64_t i = 0; i < p.nblk; ++i) {
+        const BatchReq &d = p.proto[i];
+        for (int64_t k = p.ntb[i] - 1; k >= 0; --k) {
+            launch_bwd_diag(d.tiles, p.b, k, d.v, s);
+            launch_bwd_update(d.tiles, p.b, k, d.v, s);
+        }
+    }
+    // X of all observed locations in the order of (sx, sy), then Z1 = Σ12 X
+    const int64_t nchunk = krige_chunks(n);
+    double *buf = nullptr;
+    if (hipMallocAsync(reinterpret_cast<void **>(&buf), ((size_t)n + (size_t)m * nchunk) * sizeof(double), s) !=
+        hipSuccess) {
+        (void)hipGetLastError();
+        return GL_ENOMEM;
+    }
+    double *xv = buf, *part = buf + n;
+    for (int64_t i = 0; i < p.nblk; ++i)
+        GL_HIP_TRY(hipMemcpyAsync(xv + i * p.block, p.proto[i].v, (size_t)p.nb[i] * sizeof(double),
+                                  hipMemcpyDeviceToDevice, s));
+    launch_krige(p.sx, p.sy, n, xv, th, geom_of(o), xnew, ynew, m, part, nchunk, s);
+    launch_krige_reduce(part, m, nchunk, znew, s);
+    GL_HIP_TRY(hipGetLastError());
+    GL_HIP_TRY(hipFreeAsync(buf, s));
+    return GL_OK;
 }
 
 }  // namespace gl

@@ -113,3 +113,76 @@ def test_ind_n100000_is_the_sum_of_exact_block_evaluations(g):
         print(f"n=100000 IND s={s}: l_IND={r['loglik']:.6f} exact={exact['loglik']:.6f}")
     finally:
         ctx.close()
+
+
+# ------------------------------------------------ kriging under IND (k-fold) --
+
+def _folds(n, k, seed):
+    return np.random.Generator(np.random.PCG64(seed)).permutation(np.arange(n) % k).astype(np.int32)
+
+
+def _oracle_cv_ind(x, y, z, theta, folds, k, block, reorder):
+    out = []
+    for f in range(k):
+        known, miss = folds != f, folds == f
+        xk, yk, zk = x[known], y[known], z[known]
+        if reorder:
+            p = morton_reference(xk, yk)
+            xk, yk, zk = xk[p], yk[p], zk[p]
+        pred, info = oracle.krige_ind(xk, yk, zk, x[miss], y[miss], theta, block)
+        assert info == 0
+        out.append(float(np.mean((pred - z[miss]) ** 2)))
+    return np.array(out)
+
+
+@pytest.mark.parametrize("s,tile,reorder", [(1, 128, 0), (2, 128, 0), (3, 128, 1), (1, 256, 0)])
+@pytest.mark.parametrize("theta", [(1.0, 0.1, 0.5), (1.2, 0.08, 1.3)])
+def test_ind_krige_cv_parity(g, ctx, s, tile, reorder, theta):
+    """Each fold's observed locations in blocks of s·b (input or Morton order),
+    X solved block by block, Σ12 whole: per-fold MSE against the oracle."""
+    n, k = 1100, 5
+    x, y = geoinputs.jittered_grid(n, 40)
+    e = geoinputs.normal_vector(n, 40)
+    z, info = oracle.synth(x, y, e, theta)
+    assert info == 0
+    folds = _folds(n, k, 41)
+    mse, st = g.krige_cv(ctx, dev(x), dev(y), dev(z), theta, folds,
+                         g.gl_opts_default(tile=tile, ind_tiles=s, reorder=reorder))
+    assert st == g.GL_OK
+    ref = _oracle_cv_ind(x, y, z, theta, folds, k, s * tile, reorder)
+    assert np.all(np.abs(np.array(mse) - ref) <= 1e-9 * ref), (mse, ref)
+
+
+def test_ind_krige_cv_one_block_is_exact_and_blocks_cost_accuracy(g, ctx):
+    """A super tile holding every observed location is the exact prediction;
+    smaller super tiles predict worse on a smooth field (the trend the paper
+    reports for its IND prediction experiment)."""
+    n, k, tile = 1500, 5, 128
+    theta = (1.0, 0.2, 1.5)
+    x, y = geoinputs.jittered_grid(n, 42)
+    e = geoinputs.normal_vector(n, 42)
+    z, info = oracle.synth(x, y, e, theta)
+    assert info == 0
+    folds = _folds(n, k, 43)
+    exact, st = g.krige_cv(ctx, dev(x), dev(y), dev(z), theta, folds, g.gl_opts_default(tile=tile))
+    assert st == g.GL_OK
+    whole, st = g.krige_cv(ctx, dev(x), dev(y), dev(z), theta, folds, g.gl_opts_default(tile=tile, ind_tiles=64))
+    assert st == g.GL_OK
+    assert np.all(np.abs(np.array(whole) - np.array(exact)) <= 1e-9 * np.array(exact))
+    means = [float(np.mean(g.krige_cv(ctx, dev(x), dev(y), dev(z), theta, folds,
+                                      g.gl_opts_default(tile=tile, ind_tiles=s))[0])) for s in (1, 2, 4)]
+    assert float(np.mean(exact)) < min(means) and means[2] < means[0]
+
+
+def test_ind_krige_cv_reports_failing_fold(g, ctx):
+    n, k = 600, 3
+    x, y = geoinputs.jittered_grid(n, 44)
+    folds = _folds(n, k, 45)
+    # 30 repeated locations inside every fold's observed set: blocks with them fail
+    rep = np.arange(30)
+    x[300 + rep], y[300 + rep] = x[rep], y[rep]
+    folds[300 + rep] = folds[rep]
+    z = geoinputs.normal_vector(n, 44)
+    mse, st = g.krige_cv(ctx, dev(x), dev(y), dev(z), (1.0, 0.1, 0.5), folds,
+                         g.gl_opts_default(tile=128, ind_tiles=8))
+    assert st == g.GL_NOT_SPD and any(math.isnan(v) for v in mse)
