@@ -14,7 +14,8 @@ TFLOP/s (n³/3 per step), the trailing-update kernel's live roofline fraction
 committed counter record, and the oracle timed on one host core as the CPU
 baseline.  Legs outside the timed region, each skippable: mixed precision
 against FP64 at the same size for two θ, the independent-blocks
-approximation per super-tile size, small-n latency with and without graph
+approximation per super-tile size (l, and 10-fold prediction MSE against the
+exact prediction), small-n latency with and without graph
 replay, maximum-likelihood estimates FP64 vs mixed, and the request queue
 serving 64 concurrent clients against one-at-a-time evaluation.
 """
@@ -178,6 +179,37 @@ def ind_legs(g, ctx, xd, yd, zd, theta, args, res64, t64, log):
         out.append({"super_tile": s, "block_points": s * args.tile, "ms": dt * 1e3, "speedup_vs_exact": t64 / dt,
                     "loglik": r["loglik"], "rel_diff_vs_exact": abs(r["loglik"] - res64["loglik"]) / abs(res64["loglik"])})
         log(f"IND s={s}: {dt * 1e3:.1f} ms, l={r['loglik']:.6f}")
+    return out
+
+
+def ind_prediction_leg(g, ctx, args, log):
+    """Prediction MSE of 10-fold cross-validation, exact against IND with
+    super tiles of s tiles (the paper's exact-versus-IND prediction
+    comparison, on a synthetic field of n = 40,000 jittered-grid locations
+    with Z = L e simulated at θ), with the time per fold."""
+    import numpy as np
+    import torch
+
+    import geoinputs
+    n, k, theta = 40000, 10, tuple(args.theta)
+    x, y = geoinputs.jittered_grid(n, args.seed + 11)
+    e = geoinputs.normal_vector(n, args.seed + 11)
+    xd, yd, ed = (torch.as_tensor(a).cuda() for a in (x, y, e))
+    zd, info = g.synth_generate(ctx, xd, yd, ed, theta, args.tile)
+    if info != 0:
+        return {"error": f"field generation failed, info={info}"}
+    folds = np.random.Generator(np.random.PCG64([args.seed, 12])).permutation(np.arange(n) % k).astype(np.int32)
+    out = {"n": n, "folds": k, "theta": list(theta), "tile": args.tile, "runs": []}
+    for s in (0, 1, 2, 4, 8, 16):
+        opts = g.gl_opts_default(tile=args.tile, ind_tiles=s)
+        t0 = time.perf_counter()
+        mse, st = g.krige_cv(ctx, xd, yd, zd, theta, folds, opts)
+        dt = time.perf_counter() - t0
+        run = {"super_tile": s if s else "exact", "block_points": s * args.tile if s else n,
+               "mse_mean": float(np.mean(mse)), "mse_folds": [float(v) for v in mse], "status": st,
+               "seconds_per_fold": dt / k}
+        out["runs"].append(run)
+        log(f"IND prediction s={run['super_tile']}: MSE {run['mse_mean']:.5f}, {dt / k * 1e3:.0f} ms per fold")
     return out
 
 
@@ -452,6 +484,7 @@ def main():
         out["mixed"] = mixed_legs(g, ctx, xd, yd, ed, zd, theta, tuple(args.theta_b), args, res, step_s, log)
     if not args.no_ind:
         out["ind"] = ind_legs(g, ctx, xd, yd, zd, theta, args, res, step_s, log)
+        out["ind_prediction"] = ind_prediction_leg(g, ctx, args, log)
     if not args.no_graph:
         out["graph_replay"] = graph_leg(g, ctx, args, log)
     if not args.no_mle:

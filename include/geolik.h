@@ -207,12 +207,12 @@ int krige_predict(gl_context *ctx, gl_factor *factor, const double *xnew, const 
  * other opts as given), the fold's measurements are predicted by Eq. (5), and
  * mse_h[f] (host, k doubles) receives the mean squared prediction error over
  * the fold.  With opts->ind_tiles = s >= 1 the prediction uses the IND
- * approximation of the observed locations' covariance (Sec. 6.8, the
- * exact-versus-IND prediction comparison of the paper's experiments): blocks of
- * s·b consecutive observed locations (input order, or Morton order with
- * reorder = 1) are factored on their own, X = Σ̃22⁻¹ Z2 is solved block by
- * block, and the cross-covariances to the fold's locations are kept whole,
- * Z1 = Σ12 X.  Synchronous with respect to `stream`.
+ * approximation (Sec. 6.8; the exact-versus-IND prediction comparison of the
+ * paper's experiments) of the covariance of all n locations: blocks of s·b
+ * consecutive locations in input order (b the tile size) are independent
+ * fields, so each held-out value is predicted by Eq. (5) from the observed
+ * values of its own block (0 when the block observes nothing); reorder = 1 is
+ * rejected there.  Synchronous with respect to `stream`.
  * Returns GL_OK; GL_NOT_SPD when some fold's Σ was not positive definite (its
  * mse_h is NaN, the other folds are still computed); GL_EINVAL for k < 2, a
  * fold id out of range, an empty fold or a fold holding every location.

@@ -20,8 +20,8 @@ Functions (each follows the passage named in ``oracle.c``):
 * ``synth`` — Alg. 1, Z = L e.
 * ``loglik_ind`` — the IND approximation of Sec. 6.8 (blocks of consecutive
   locations, off-block covariances annihilated).
-* ``krige_ind`` — kriging (Eq. (5)) with Σ22 replaced by its IND
-  approximation, Σ12 whole.
+* ``krige_ind`` — kriging (Eq. (5)) under the IND approximation of the
+  covariance of all locations: each held-out value from its own block.
 """
 from __future__ import annotations
 
@@ -73,7 +73,7 @@ def _load():
         "oracle_krige": (I64, [P, P, P, I64, P, P, I64, D, D, D, ctypes.c_int, D, P, P]),
         "oracle_synth": (I64, [P, P, P, I64, D, D, D, ctypes.c_int, D, P]),
         "oracle_loglik_ind": (I64, [P, P, P, I64, D, D, D, ctypes.c_int, D, I64, P]),
-        "oracle_krige_ind": (I64, [P, P, P, I64, P, P, I64, D, D, D, ctypes.c_int, D, I64, P]),
+        "oracle_krige_ind": (I64, [P, P, P, P, I64, D, D, D, ctypes.c_int, D, I64, P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -210,12 +210,15 @@ def loglik_ind(x, y, z, theta, block: int, metric: int = EUCLIDEAN, radius: floa
     return float(out[0]), float(out[1]), float(out[2]), int(info)
 
 
-def krige_ind(x, y, z, xnew, ynew, theta, block: int, metric: int = EUCLIDEAN, radius: float = EARTH_RADIUS_KM):
-    """Kriging under the IND approximation (Sec. 6.8 with Eq. (5)): Σ22 kept
-    only in diagonal blocks of `block` consecutive observed locations, Σ12
-    whole.  Returns (Z1, info)."""
-    x, y, z, xnew, ynew = map(_f64, (x, y, z, xnew, ynew))
-    out = np.zeros(xnew.size, dtype=np.float64)
-    info = _load().oracle_krige_ind(_p(x), _p(y), _p(z), x.size, _p(xnew), _p(ynew), xnew.size,
-                                    *map(float, theta), int(metric), float(radius), int(block), _p(out))
+def krige_ind(x, y, z, missing, theta, block: int, metric: int = EUCLIDEAN, radius: float = EARTH_RADIUS_KM):
+    """Kriging under the IND approximation (Sec. 6.8 with Eq. (5)): blocks of
+    `block` consecutive locations (observed and held-out alike) are
+    independent; each held-out value (missing != 0) is predicted from the
+    observed values of its block.  Returns (predictions in location order,
+    info)."""
+    x, y, z = map(_f64, (x, y, z))
+    miss = np.ascontiguousarray(missing, dtype=np.int32)
+    out = np.zeros(int(np.count_nonzero(miss)), dtype=np.float64)
+    info = _load().oracle_krige_ind(_p(x), _p(y), _p(z), _p(miss), x.size, *map(float, theta), int(metric),
+                                    float(radius), int(block), _p(out))
     return out, int(info)

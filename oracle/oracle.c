@@ -347,44 +347,65 @@ int64_t oracle_loglik_ind(const double *x, const double *y, const double *z, int
 }
 
 /*
- * Kriging under the IND approximation (Sec. 6.8, with the prediction of
- * Sec. 2.3 Eq. (5)): Σ22 is replaced by its block-diagonal part, blocks of
- * `block` consecutive observed locations (the last one shorter), so
- * X = Σ̃22⁻¹ Z2 is solved block by block; the cross-covariance Σ12 between the
- * new and the observed locations is kept whole: Z1 = Σ12 X.  Returns 0, or the
- * 1-based global column of the first non-positive pivot.
+ * Kriging under the IND approximation (Sec. 6.8 applied to the prediction of
+ * Sec. 2.3 Eq. (5)): the covariance of all n locations, observed and
+ * held-out alike, keeps only its diagonal blocks of `block` consecutive
+ * locations (the last one shorter), so the blocks are independent fields and
+ * each held-out value is predicted from the observed values of its own block:
+ * Z_M = Σ_MO Σ_OO⁻¹ Z_O within the block (zero when the block observes
+ * nothing).  miss[i] != 0 marks location i as held out; znew receives the
+ * predictions in location order (one per held-out location).  Returns 0, or
+ * the 1-based index, among all n locations, of the observed location whose
+ * pivot is not positive.
  */
-int64_t oracle_krige_ind(const double *x, const double *y, const double *z, int64_t n,
-                         const double *xn, const double *yn, int64_t m,
+int64_t oracle_krige_ind(const double *x, const double *y, const double *z, const int32_t *miss, int64_t n,
                          double theta1, double theta2, double theta3, int metric, double radius,
                          int64_t block, double *znew)
 {
-    double *v = (double *)malloc((size_t)n * sizeof(double));
     double *a = (double *)malloc((size_t)block * (size_t)block * sizeof(double));
+    double *bx = (double *)malloc((size_t)block * sizeof(double));
+    double *by = (double *)malloc((size_t)block * sizeof(double));
+    double *bz = (double *)malloc((size_t)block * sizeof(double));
     double *w = (double *)malloc((size_t)block * sizeof(double));
-    int64_t info = 0;
+    double *v = (double *)malloc((size_t)block * sizeof(double));
+    int64_t *gi = (int64_t *)malloc((size_t)block * sizeof(int64_t));
+    int64_t info = 0, out = 0;
     for (int64_t s = 0; s < n && info == 0; s += block) {
-        const int64_t nb = (n - s < block) ? n - s : block;
-        oracle_cov_symmetric(x + s, y + s, nb, theta1, theta2, theta3, metric, radius, a);
-        const int64_t bi = oracle_cholesky(a, nb);
-        if (bi != 0) {
-            info = s + bi;
-            break;
+        const int64_t e = (n - s < block) ? n : s + block;
+        int64_t no = 0;
+        for (int64_t i = s; i < e; ++i)
+            if (!miss[i]) {
+                bx[no] = x[i];
+                by[no] = y[i];
+                bz[no] = z[i];
+                gi[no] = i;
+                ++no;
+            }
+        if (no > 0) {
+            oracle_cov_symmetric(bx, by, no, theta1, theta2, theta3, metric, radius, a);
+            const int64_t bi = oracle_cholesky(a, no);
+            if (bi != 0) {
+                info = gi[bi - 1] + 1;
+                break;
+            }
+            oracle_forward(a, no, bz, w);
+            oracle_backward(a, no, w, v);
         }
-        oracle_forward(a, nb, z + s, w);
-        oracle_backward(a, nb, w, v + s);
-    }
-    if (info == 0) {
-        for (int64_t k = 0; k < m; ++k) {
+        for (int64_t i = s; i < e; ++i) {
+            if (!miss[i]) continue;
             double acc = 0.0;
-            for (int64_t j = 0; j < n; ++j)
-                acc += oracle_matern(oracle_distance(metric, radius, xn[k], yn[k], x[j], y[j]), theta1, theta2,
+            for (int64_t j = 0; j < no; ++j)
+                acc += oracle_matern(oracle_distance(metric, radius, x[i], y[i], bx[j], by[j]), theta1, theta2,
                                      theta3) * v[j];
-            znew[k] = acc;
+            znew[out++] = acc;
         }
     }
-    free(v);
     free(a);
+    free(bx);
+    free(by);
+    free(bz);
     free(w);
+    free(v);
+    free(gi);
     return info;
 }

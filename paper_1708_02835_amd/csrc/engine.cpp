@@ -622,8 +622,13 @@ int krige_cv(gl_context *ctx, const double *x, const double *y, const double *z,
     if (opts) o = *opts;
     const bool ind = o.ind_tiles > 0;  // IND kriging keeps no factor object
     o.keep_factor = ind ? 0 : 1;
-    if (!valid_opts(o) || !valid_theta_for(th, o)) return GL_EINVAL;
+    if (!valid_opts(o) || !valid_theta_for(th, o) || (ind && o.reorder == 1)) return GL_EINVAL;
     const gl_opts ro = resolved_opts(o);
+    // IND: blocks of ind_tiles·b consecutive locations of the whole input
+    const int ib = ind ? pick_tile(n, o.tile) : 0;
+    const int64_t iblock = ind ? o.ind_tiles * (int64_t)ib : 1;
+    const int64_t nblocks = ind ? ceil_div(n, iblock) : 0;
+    std::vector<int64_t> kcount(nblocks), mcount(nblocks);
     std::vector<int64_t> count(k, 0);
     for (int64_t i = 0; i < n; ++i) {
         if (fold_h[i] < 0 || fold_h[i] >= k) return GL_EINVAL;
@@ -659,7 +664,10 @@ int krige_cv(gl_context *ctx, const double *x, const double *y, const double *z,
             launch_gather3(x, y, z, idx + nk, nm, mx, my, mz, s);
             gl_factor *fac = nullptr;
             if (ind) {
-                rc = ind_krige(ctx, kx, ky, kz, nk, th, ro, mx, my, nm, pred, s);
+                std::fill(kcount.begin(), kcount.end(), 0);
+                std::fill(mcount.begin(), mcount.end(), 0);
+                for (int64_t i = 0; i < n; ++i) ++(fold_h[i] == f ? mcount : kcount)[i / iblock];
+                rc = ind_krige(ctx, kx, ky, kz, kcount.data(), mx, my, mcount.data(), nblocks, th, ro, ib, pred, s);
             } else {
                 gl_result r;
                 rc = loglik_eval(ctx, kx, ky, kz, nk, th, &o, &r, stream);

@@ -118,11 +118,15 @@ void fill_result(gl_result *res, const DevResult &d, int b);
 // Independent-blocks approximation (ind.cpp); o resolved and validated.
 int ind_eval(gl_context *ctx, const double *x, const double *y, const double *z, int64_t n, gl_theta th,
              const gl_opts &o, gl_result *res, hipStream_t s);
-// Kriging with the IND-approximated covariance of the observed locations
-// (blocks as in ind_eval), Σ12 whole; znew: m predictions.  GL_NOT_SPD when a
-// block's factorisation fails.
-int ind_krige(gl_context *ctx, const double *x, const double *y, const double *z, int64_t n, gl_theta th,
-              const gl_opts &o, const double *xnew, const double *ynew, int64_t m, double *znew, hipStream_t s);
+// Kriging under the IND approximation of the covariance of all locations:
+// nblocks blocks, block B holding kcount[B] observed locations (consecutive in
+// x, y, z) and mcount[B] held-out ones (consecutive in xnew, ynew); each
+// held-out value is predicted from its block's observed values (0 when there
+// are none).  b: tile size of the block factorisations (o.ind_tiles tiles per
+// block at most).  GL_NOT_SPD when a block's factorisation fails.
+int ind_krige(gl_context *ctx, const double *x, const double *y, const double *z, const int64_t *kcount,
+              const double *xnew, const double *ynew, const int64_t *mcount, int64_t nblocks, gl_theta th,
+              const gl_opts &o, int b, double *znew, hipStream_t s);
 
 }  // namespace gl
 

@@ -6,11 +6,12 @@
 // (the last one possibly shorter), advanced together through the fused
 // multi-factorisation launches, one tile step per launch group.
 //
-// Kriging under the same approximation (the prediction experiment of Sec. 7
-// with IND, Eq. (5)): X = Σ̃22⁻¹ Z2 is solved block by block from the block
-// factors (backward substitution of w = L⁻¹ Z2 within each block), and the
-// cross-covariance Σ12 between new and observed locations is kept whole,
-// generated on the fly: Z1 = Σ12 X.
+// Kriging under the same approximation (the exact-versus-IND prediction
+// comparison of the paper's experiments, with Eq. (5)): applied to the
+// covariance of all locations, observed and held-out alike, the blocks are
+// independent fields, so each held-out value is predicted from the observed
+// values of its own block, Z_M = Σ_MO Σ_OO⁻¹ Z_O, through the block's factor
+// (backward substitution of w = L⁻¹ Z_O).
 #include <algorithm>
 #include <vector>
 
@@ -44,22 +45,23 @@ __global__ void ind_total_kernel(const DevResult *__restrict__ r, int64_t nblk, 
 // blocks were cut from (input or Morton order) and the device total.
 struct IndPlan {
     int b = 0;
-    int64_t block = 0, nblk = 0;
+    int64_t nblk = 0;
     std::vector<BatchReq> proto;
-    std::vector<int64_t> nb, ntb;
+    std::vector<int64_t> start, nb, ntb;
     const double *sx = nullptr, *sy = nullptr;
     DevResult *total = nullptr;
 };
 
-// Enqueues the factorisation of every block and the fixed-order sum of the
-// per-block results into p.total (all on s).
+// Enqueues the factorisation of the blocks [start[i], start[i] + count[i])
+// of the locations (each count >= 1, at most bt tiles of b) and the
+// fixed-order sum of the per-block results into p.total (all on s).  With
+// reorder the locations are first put in Morton order.
 static int ind_factor(gl_context *ctx, const double *x, const double *y, const double *z, int64_t n, gl_theta th,
-                      const gl_opts &o, hipStream_t s, IndPlan &p)
+                      const gl_opts &o, int b, int64_t bt, const std::vector<int64_t> &start,
+                      const std::vector<int64_t> &count, bool reorder, hipStream_t s, IndPlan &p)
 {
-    const int b = pick_tile(n, o.tile);
-    const int64_t bt = o.ind_tiles;          // tiles per super tile
-    const int64_t block = bt * b;            // locations per block
-    const int64_t nblk = ceil_div(n, block);
+    const int64_t nblk = (int64_t)start.size();
+    const int64_t block = bt * b;  // uniform block length (the likelihood's), for the reported column
     // layout (in doubles): descriptors | totals | per-block results, info |
     // per block: tiles, x, y, v, logsum, quad, dinv | reordered inputs, keys
     const size_t desc_d = ((size_t)nblk * sizeof(BatchReq) + 15) / 16 * 2;
@@ -67,14 +69,14 @@ static int ind_factor(gl_context *ctx, const double *x, const double *y, const d
     std::vector<size_t> boff(nblk);
     std::vector<int64_t> nb(nblk), ntb(nblk);
     for (int64_t i = 0; i < nblk; ++i) {
-        nb[i] = std::min(block, n - i * block);
+        nb[i] = count[i];
         ntb[i] = ceil_div(nb[i], b);
         const int64_t npb = ntb[i] * b;
         boff[i] = off;
         off += (size_t)tile_count(ntb[i]) * b * b + 3 * npb + 2 * ntb[i] + (ntb[i] & 1) + 64 * npb;
     }
     const size_t morton_off = off;
-    if (o.reorder) off += 3 * (size_t)n + (n & 1) + (size_t)npow2_of(n) + 4;
+    if (reorder) off += 3 * (size_t)n + (n & 1) + (size_t)npow2_of(n) + 4;
     const size_t bytes = off * sizeof(double);
     if (bytes > ctx->ind_cap) {
         const size_t old = ctx->ind_cap;
@@ -96,7 +98,7 @@ static int ind_factor(gl_context *ctx, const double *x, const double *y, const d
     DevResult *bres = reinterpret_cast<DevResult *>(base + desc_d + 8);
     int64_t *binfo = reinterpret_cast<int64_t *>(base + desc_d + 8 + 8 * nblk);
     const double *sx = x, *sy = y, *sz = z;
-    if (o.reorder) {
+    if (reorder) {
         double *xo = base + morton_off, *yo = xo + n, *zo = yo + n;
         uint64_t *keys = reinterpret_cast<uint64_t *>(zo + n + (n & 1));
         launch_morton_order(x, y, z, n, n, keys, xo, yo, zo, nullptr, s);  // unpadded output
@@ -121,9 +123,9 @@ static int ind_factor(gl_context *ctx, const double *x, const double *y, const d
         d.dinv = p;
         d.info = binfo + 8 * i;
         d.res = bres + i;
-        d.sx = sx + i * block;
-        d.sy = sy + i * block;
-        d.sz = sz + i * block;
+        d.sx = sx + start[i];
+        d.sy = sy + start[i];
+        d.sz = sz + start[i];
         d.th = th;
         d.geo = geom_of(o);
         d.n = nb[i];
@@ -150,9 +152,9 @@ static int ind_factor(gl_context *ctx, const double *x, const double *y, const d
     ind_total_kernel<<<1, 64, 0, s>>>(bres, nblk, block, total);
     GL_HIP_TRY(hipGetLastError());
     p.b = b;
-    p.block = block;
     p.nblk = nblk;
     p.proto = std::move(proto);
+    p.start = start;
     p.nb = std::move(nb);
     p.ntb = std::move(ntb);
     p.sx = sx;
@@ -164,8 +166,15 @@ static int ind_factor(gl_context *ctx, const double *x, const double *y, const d
 int ind_eval(gl_context *ctx, const double *x, const double *y, const double *z, int64_t n, gl_theta th,
              const gl_opts &o, gl_result *res, hipStream_t s)
 {
+    const int b = pick_tile(n, o.tile);
+    const int64_t block = o.ind_tiles * (int64_t)b;
+    std::vector<int64_t> start, count;
+    for (int64_t a = 0; a < n; a += block) {
+        start.push_back(a);
+        count.push_back(std::min(block, n - a));
+    }
     IndPlan p;
-    const int rc = ind_factor(ctx, x, y, z, n, th, o, s, p);
+    const int rc = ind_factor(ctx, x, y, z, n, th, o, b, o.ind_tiles, start, count, o.reorder != 0, s, p);
     if (rc != GL_OK) return res->status = rc;
     GL_HIP_TRY(hipMemcpyAsync(ctx->res_h, p.total, sizeof(DevResult), hipMemcpyDeviceToHost, s));
     GL_HIP_TRY(hipStreamSynchronize(s));
@@ -173,39 +182,62 @@ int ind_eval(gl_context *ctx, const double *x, const double *y, const double *z,
     return res->status;
 }
 
-int ind_krige(gl_context *ctx, const double *x, const double *y, const double *z, int64_t n, gl_theta th,
-              const gl_opts &o, const double *xnew, const double *ynew, int64_t m, double *znew, hipStream_t s)
+int ind_krige(gl_context *ctx, const double *x, const double *y, const double *z, const int64_t *kcount,
+              const double *xnew, const double *ynew, const int64_t *mcount, int64_t nblocks, gl_theta th,
+              const gl_opts &o, int b, double *znew, hipStream_t s)
 {
-    IndPlan p;
-    int rc = ind_factor(ctx, x, y, z, n, th, o, s, p);
-    if (rc != GL_OK) return rc;
-    GL_HIP_TRY(hipMemcpyAsync(ctx->res_h, p.total, sizeof(DevResult), hipMemcpyDeviceToHost, s));
-    GL_HIP_TRY(hipStreamSynchronize(s));
-    if (ctx->res_h->info != 0) return GL_NOT_SPD;
-    // X = L⁻ᵀ w within each block, in place
-    for (int64_t i = 0; i < p.nblk; ++i) {
-        const BatchReq &d = p.proto[i];
-        for (int64_t k = p.ntb[i] - 1; k >= 0; --k) {
-            launch_bwd_diag(d.tiles, p.b, k, d.v, s);
-            launch_bwd_update(d.tiles, p.b, k, d.v, s);
+    // blocks that observe something are factored; the others predict 0
+    std::vector<int64_t> start, count, kstart(nblocks + 1, 0), mstart(nblocks + 1, 0), slot(nblocks, -1);
+    for (int64_t B = 0; B < nblocks; ++B) {
+        kstart[B + 1] = kstart[B] + kcount[B];
+        mstart[B + 1] = mstart[B] + mcount[B];
+        if (kcount[B] > 0) {
+            slot[B] = (int64_t)start.size();
+            start.push_back(kstart[B]);
+            count.push_back(kcount[B]);
         }
     }
-    // X of all observed locations in the order of (sx, sy), then Z1 = Σ12 X
-    const int64_t nchunk = krige_chunks(n);
-    double *buf = nullptr;
-    if (hipMallocAsync(reinterpret_cast<void **>(&buf), ((size_t)n + (size_t)m * nchunk) * sizeof(double), s) !=
-        hipSuccess) {
+    const int64_t n = kstart[nblocks], m = mstart[nblocks];
+    IndPlan p;
+    if (!start.empty()) {
+        int rc = ind_factor(ctx, x, y, z, n, th, o, b, o.ind_tiles, start, count, false, s, p);
+        if (rc != GL_OK) return rc;
+        GL_HIP_TRY(hipMemcpyAsync(ctx->res_h, p.total, sizeof(DevResult), hipMemcpyDeviceToHost, s));
+        GL_HIP_TRY(hipStreamSynchronize(s));
+        if (ctx->res_h->info != 0) return GL_NOT_SPD;
+        // X = L⁻ᵀ w within each block, in place
+        for (int64_t i = 0; i < p.nblk; ++i) {
+            const BatchReq &d = p.proto[i];
+            for (int64_t k = p.ntb[i] - 1; k >= 0; --k) {
+                launch_bwd_diag(d.tiles, p.b, k, d.v, s);
+                launch_bwd_update(d.tiles, p.b, k, d.v, s);
+            }
+        }
+    }
+    // each block's held-out values from its own observed values
+    int64_t part_len = 1;
+    for (int64_t B = 0; B < nblocks; ++B)
+        if (mcount[B] > 0 && kcount[B] > 0) part_len = std::max(part_len, mcount[B] * krige_chunks(kcount[B]));
+    double *part = nullptr;
+    if (hipMallocAsync(reinterpret_cast<void **>(&part), (size_t)part_len * sizeof(double), s) != hipSuccess) {
         (void)hipGetLastError();
         return GL_ENOMEM;
     }
-    double *xv = buf, *part = buf + n;
-    for (int64_t i = 0; i < p.nblk; ++i)
-        GL_HIP_TRY(hipMemcpyAsync(xv + i * p.block, p.proto[i].v, (size_t)p.nb[i] * sizeof(double),
-                                  hipMemcpyDeviceToDevice, s));
-    launch_krige(p.sx, p.sy, n, xv, th, geom_of(o), xnew, ynew, m, part, nchunk, s);
-    launch_krige_reduce(part, m, nchunk, znew, s);
+    for (int64_t B = 0; B < nblocks; ++B) {
+        if (mcount[B] == 0) continue;
+        double *out = znew + mstart[B];
+        if (kcount[B] == 0) {
+            launch_fill(out, mcount[B], 0.0, s);
+            continue;
+        }
+        const int64_t nchunk = krige_chunks(kcount[B]);
+        launch_krige(x + kstart[B], y + kstart[B], kcount[B], p.proto[slot[B]].v, th, geom_of(o), xnew + mstart[B],
+                     ynew + mstart[B], mcount[B], part, nchunk, s);
+        launch_krige_reduce(part, mcount[B], nchunk, out, s);
+    }
     GL_HIP_TRY(hipGetLastError());
-    GL_HIP_TRY(hipFreeAsync(buf, s));
+    GL_HIP_TRY(hipFreeAsync(part, s));
+    (void)m;
     return GL_OK;
 }
 

@@ -121,42 +121,38 @@ def _folds(n, k, seed):
     return np.random.Generator(np.random.PCG64(seed)).permutation(np.arange(n) % k).astype(np.int32)
 
 
-def _oracle_cv_ind(x, y, z, theta, folds, k, block, reorder):
+def _oracle_cv_ind(x, y, z, theta, folds, k, block):
     out = []
     for f in range(k):
-        known, miss = folds != f, folds == f
-        xk, yk, zk = x[known], y[known], z[known]
-        if reorder:
-            p = morton_reference(xk, yk)
-            xk, yk, zk = xk[p], yk[p], zk[p]
-        pred, info = oracle.krige_ind(xk, yk, zk, x[miss], y[miss], theta, block)
+        miss = (folds == f).astype(np.int32)
+        pred, info = oracle.krige_ind(x, y, z, miss, theta, block)
         assert info == 0
-        out.append(float(np.mean((pred - z[miss]) ** 2)))
+        out.append(float(np.mean((pred - z[folds == f]) ** 2)))
     return np.array(out)
 
 
-@pytest.mark.parametrize("s,tile,reorder", [(1, 128, 0), (2, 128, 0), (3, 128, 1), (1, 256, 0)])
+@pytest.mark.parametrize("s,tile", [(1, 128), (2, 128), (3, 128), (1, 256)])
 @pytest.mark.parametrize("theta", [(1.0, 0.1, 0.5), (1.2, 0.08, 1.3)])
-def test_ind_krige_cv_parity(g, ctx, s, tile, reorder, theta):
-    """Each fold's observed locations in blocks of s·b (input or Morton order),
-    X solved block by block, Σ12 whole: per-fold MSE against the oracle."""
+def test_ind_krige_cv_parity(g, ctx, s, tile, theta):
+    """Blocks of s·b consecutive locations (observed and held-out alike) are
+    independent; each held-out value from its block's observed values:
+    per-fold MSE against the oracle."""
     n, k = 1100, 5
     x, y = geoinputs.jittered_grid(n, 40)
     e = geoinputs.normal_vector(n, 40)
     z, info = oracle.synth(x, y, e, theta)
     assert info == 0
     folds = _folds(n, k, 41)
-    mse, st = g.krige_cv(ctx, dev(x), dev(y), dev(z), theta, folds,
-                         g.gl_opts_default(tile=tile, ind_tiles=s, reorder=reorder))
+    mse, st = g.krige_cv(ctx, dev(x), dev(y), dev(z), theta, folds, g.gl_opts_default(tile=tile, ind_tiles=s))
     assert st == g.GL_OK
-    ref = _oracle_cv_ind(x, y, z, theta, folds, k, s * tile, reorder)
+    ref = _oracle_cv_ind(x, y, z, theta, folds, k, s * tile)
     assert np.all(np.abs(np.array(mse) - ref) <= 1e-9 * ref), (mse, ref)
 
 
 def test_ind_krige_cv_one_block_is_exact_and_blocks_cost_accuracy(g, ctx):
-    """A super tile holding every observed location is the exact prediction;
-    smaller super tiles predict worse on a smooth field (the trend the paper
-    reports for its IND prediction experiment)."""
+    """A super tile holding every location is the exact prediction; smaller
+    super tiles predict worse (the trend the paper reports for its IND
+    prediction experiment)."""
     n, k, tile = 1500, 5, 128
     theta = (1.0, 0.2, 1.5)
     x, y = geoinputs.jittered_grid(n, 42)
@@ -174,11 +170,20 @@ def test_ind_krige_cv_one_block_is_exact_and_blocks_cost_accuracy(g, ctx):
     assert float(np.mean(exact)) < min(means) and means[2] < means[0]
 
 
+def test_ind_krige_cv_rejects_morton_order(g, ctx):
+    x, y = geoinputs.jittered_grid(300, 46)
+    z = geoinputs.normal_vector(300, 46)
+    with pytest.raises(g.GeolikError):
+        g.krige_cv(ctx, dev(x), dev(y), dev(z), (1.0, 0.1, 0.5), _folds(300, 3, 47),
+                   g.gl_opts_default(tile=128, ind_tiles=2, reorder=1))
+
+
 def test_ind_krige_cv_reports_failing_fold(g, ctx):
     n, k = 600, 3
     x, y = geoinputs.jittered_grid(n, 44)
     folds = _folds(n, k, 45)
-    # 30 repeated locations inside every fold's observed set: blocks with them fail
+    # 30 locations repeated within the same block of 1024 and the same fold:
+    # every fold observes some repeated pairs, whose block then fails
     rep = np.arange(30)
     x[300 + rep], y[300 + rep] = x[rep], y[rep]
     folds[300 + rep] = folds[rep]

@@ -65,14 +65,20 @@ def test_ind_reports_first_failing_column():
 
 # ------------------------------------------------ kriging under IND (Eq. 5) --
 
-def masked_krige(x, y, z, xn, yn, theta, block):
-    """Z1 = Σ12 Σ̃22⁻¹ Z2 with Σ̃22 the block-masked dense covariance, by a
-    dense LU solve (numpy), independent of the oracle's Cholesky path."""
+def masked_conditional_mean(x, y, z, miss, theta, block):
+    """E[Z_M | Z_O] under the covariance of all locations with every entry
+    between different blocks set to zero, by a dense LU solve (numpy) on the
+    whole masked matrix — independent of the oracle's per-block Cholesky."""
     n = x.size
     a = oracle.cov_symmetric(x, y, theta)
     blk = np.arange(n) // block
     a = np.where(blk[:, None] == blk[None, :], a, 0.0)
-    return oracle.cov_matrix(xn, yn, x, y, theta) @ np.linalg.solve(a, z)
+    o, m = ~miss.astype(bool), miss.astype(bool)
+    return a[np.ix_(m, o)] @ np.linalg.solve(a[np.ix_(o, o)], z[o])
+
+
+def _miss(n, k, seed):
+    return (np.random.Generator(np.random.PCG64(seed)).permutation(np.arange(n) % k) == 0).astype(np.int32)
 
 
 @pytest.mark.parametrize("n,block", [(90, 32), (100, 25), (64, 7)])
@@ -80,42 +86,42 @@ def masked_krige(x, y, z, xn, yn, theta, block):
 def test_krige_ind_vs_masked_dense(n, block, theta):
     x, y = geoinputs.jittered_grid(n, 31)
     z = geoinputs.normal_vector(n, 31)
-    xn, yn = geoinputs.uniform_points(17, 32)
-    got, info = oracle.krige_ind(x, y, z, xn, yn, theta, block)
+    miss = _miss(n, 5, 32)
+    got, info = oracle.krige_ind(x, y, z, miss, theta, block)
     assert info == 0
-    want = masked_krige(x, y, z, xn, yn, theta, block)
+    want = masked_conditional_mean(x, y, z, miss, theta, block)
     assert np.max(np.abs(got - want)) <= 1e-10 * np.max(np.abs(want))
 
 
-def test_krige_ind_single_location_blocks_closed_form():
-    """Blocks of one location: Σ̃22 = θ1 I, so Z1 = Σ12 Z2 / θ1."""
+def test_krige_ind_single_location_blocks_predict_the_mean():
+    """Blocks of one location: a held-out value has no observed neighbour in
+    its block, so it is predicted by the zero mean."""
     x, y = geoinputs.jittered_grid(40, 33)
     z = geoinputs.normal_vector(40, 33)
-    xn, yn = geoinputs.uniform_points(9, 34)
-    theta = (1.6, 0.12, 0.5)
-    got, info = oracle.krige_ind(x, y, z, xn, yn, theta, 1)
-    r = np.hypot(xn[:, None] - x[None, :], yn[:, None] - y[None, :])
-    want = (theta[0] * np.exp(-r / theta[1])) @ z / theta[0]  # ν = 1/2: θ1 exp(-r/θ2)
-    assert info == 0 and np.max(np.abs(got - want)) <= 1e-13 * np.max(np.abs(want))
+    miss = _miss(40, 4, 34)
+    got, info = oracle.krige_ind(x, y, z, miss, (1.6, 0.12, 0.5), 1)
+    assert info == 0 and got.size == int(miss.sum()) and np.all(got == 0.0)
 
 
 def test_krige_ind_one_block_is_exact():
     n = 110
     x, y = geoinputs.jittered_grid(n, 35)
     z = geoinputs.normal_vector(n, 35)
-    xn, yn = geoinputs.uniform_points(13, 36)
+    miss = _miss(n, 6, 36)
     theta = (1.0, 0.15, 1.0)
-    exact, info = oracle.krige(x, y, z, xn, yn, theta)
+    o, m = miss == 0, miss != 0
+    exact, info = oracle.krige(x[o], y[o], z[o], x[m], y[m], theta)
     assert info == 0
     for block in (n, 3 * n):
-        got, info = oracle.krige_ind(x, y, z, xn, yn, theta, block)
+        got, info = oracle.krige_ind(x, y, z, miss, theta, block)
         assert info == 0 and np.array_equal(got, exact)
 
 
-def test_krige_ind_reports_first_failing_column():
+def test_krige_ind_reports_first_failing_location():
     x, y = geoinputs.jittered_grid(60, 37)
     x[45], y[45] = x[44], y[44]
     z = geoinputs.normal_vector(60, 37)
-    xn, yn = geoinputs.uniform_points(5, 38)
-    _, info = oracle.krige_ind(x, y, z, xn, yn, (1.0, 0.1, 0.5), 30)
+    miss = np.zeros(60, dtype=np.int32)
+    miss[[3, 50]] = 1
+    _, info = oracle.krige_ind(x, y, z, miss, (1.0, 0.1, 0.5), 30)
     assert info == 46

@@ -43,9 +43,10 @@ MUTANTS = {
     "variance_backward": ("oracle_forward(a, n, sk, w);", "oracle_backward(a, n, sk, w);"),
     "ind_stride": ("for (int64_t s = 0; s < n; s += block) {", "for (int64_t s = 0; s < n; s += block + 1) {"),
     "ind_sum_sign": ("        l += part[0];", "        l -= part[0];"),
-    "krige_ind_block_offset": ("oracle_forward(a, nb, z + s, w);", "oracle_forward(a, nb, z, w);"),
-    "krige_ind_no_backward": ("oracle_backward(a, nb, w, v + s);", "memcpy(v + s, w, (size_t)nb * sizeof(double));"),
-    "krige_ind_cov_offset": ("oracle_cov_symmetric(x + s, y + s, nb,", "oracle_cov_symmetric(x, y, nb,"),
+    "krige_ind_no_backward": ("oracle_backward(a, no, w, v);", "memcpy(v, w, (size_t)no * sizeof(double));"),
+    "krige_ind_block_edge": ("const int64_t e = (n - s < block) ? n : s + block;",
+                             "const int64_t e = (n - s < block) ? n : s + block - 1;"),
+    "krige_ind_own_point": ("(metric, radius, x[i], y[i], bx[j], by[j])", "(metric, radius, x[j], y[j], bx[j], by[j])"),
 }
 
 
@@ -76,7 +77,7 @@ def _build(tmp_path, name, mutation):
     lib.oracle_loglik_ind.restype = I64
     lib.oracle_loglik_ind.argtypes = [P, P, P, I64, D, D, D, INT, D, I64, P]
     lib.oracle_krige_ind.restype = I64
-    lib.oracle_krige_ind.argtypes = [P, P, P, I64, P, P, I64, D, D, D, INT, D, I64, P]
+    lib.oracle_krige_ind.argtypes = [P, P, P, P, I64, D, D, D, INT, D, I64, P]
     return lib
 
 
@@ -152,10 +153,13 @@ def _pins(lib):
     lib.oracle_loglik_ind(_p(x), _p(y), _p(z), n, *theta, 0, 1.0, 15, _p(out_ind))
     if not abs(out_ind[0] - ref_ind) <= 1e-9 * abs(ref_ind):
         failed.append("ind_masked")
-    # kriging under IND vs the block-masked dense solve
-    zi = np.zeros(4)
-    lib.oracle_krige_ind(_p(x), _p(y), _p(z), n, _p(xn), _p(yn), 4, *theta, 0, 1.0, 15, _p(zi))
-    if not np.allclose(zi, s12 @ np.linalg.solve(am, z), rtol=1e-8, atol=1e-10):
+    # kriging under IND vs the conditional mean of the block-masked covariance
+    miss = np.zeros(n, dtype=np.int32)
+    miss[[2, 9, 17, 31, 38]] = 1
+    o, mm = miss == 0, miss != 0
+    zi = np.zeros(int(miss.sum()))
+    lib.oracle_krige_ind(_p(x), _p(y), _p(z), _p(miss), n, *theta, 0, 1.0, 15, _p(zi))
+    if not np.allclose(zi, am[np.ix_(mm, o)] @ np.linalg.solve(am[np.ix_(o, o)], z[o]), rtol=1e-8, atol=1e-10):
         failed.append("krige_ind_masked")
     # synth vs LAPACK factor
     e = geoinputs.normal_vector(n, 8)
