@@ -197,7 +197,7 @@ int ind_krige(gl_context *ctx, const double *x, const double *y, const double *z
             count.push_back(kcount[B]);
         }
     }
-    const int64_t n = kstart[nblocks], m = mstart[nblocks];
+    const int64_t n = kstart[nblocks];
     IndPlan p;
     if (!start.empty()) {
         int rc = ind_factor(ctx, x, y, z, n, th, o, b, o.ind_tiles, start, count, false, s, p);
@@ -237,7 +237,6 @@ int ind_krige(gl_context *ctx, const double *x, const double *y, const double *z
     }
     GL_HIP_TRY(hipGetLastError());
     GL_HIP_TRY(hipFreeAsync(part, s));
-    (void)m;
     return GL_OK;
 }
 
