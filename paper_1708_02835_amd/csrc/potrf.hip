@@ -4,9 +4,9 @@
 // One workgroup of 256 threads factors the b×b tile A_kk = L_kk L_kkᵀ in place
 // (lower triangle), right-looking over 64-column panels s:
 //   1. the 64×64 diagonal block D is copied to LDS, factored by one wave
-//      (lane r owns row r; column multipliers travel by lane shuffles), and
-//      inverted by the same wave (lane j builds column j of D⁻¹ by forward
-//      substitution).  D⁻¹ is also written to `dinv` for the panel TRSM and
+//      (lane r owns row r; each column of the factor is broadcast through
+//      LDS), and inverted by the same wave (lane j builds column j of D⁻¹ by
+//      column-oriented forward substitution).  D⁻¹ is also written to `dinv` for the panel TRSM and
 //      the forward solve of this step;
 //   2. the rows below the block are solved on the matrix cores as
 //      P = A[s+64:, s:s+64] · D⁻ᵀ, each wave owning whole 16-row groups;
@@ -40,6 +40,7 @@ __device__ __forceinline__ void potrf_body(double *__restrict__ tiles, int64_t k
     __shared__ double Ds[PB][PB + 1];  // Ds[c][r] = D[r][c]
     __shared__ double Xi[PB][PB + 1];  // Xi[c][r] = (D⁻¹)[r][c]
     __shared__ double rdiag[PB];
+    __shared__ double colb[PB];  // the current column of the 64×64 factor, for broadcast reads
     __shared__ double red[4];
     __shared__ int fail;
 
@@ -66,9 +67,15 @@ __device__ __forceinline__ void potrf_body(double *__restrict__ tiles, int64_t k
                 const double inv = 1.0 / d;
                 if (lane == c) rv = inv;
                 a[c] = (lane == c) ? d : a[c] * inv;
-                // entries above the diagonal (lane < j) receive harmless values that are never stored
+                // column c goes through LDS (one store, then broadcast reads: the
+                // wave's LDS accesses complete in order) for the rank-1 update;
+                // entries above the diagonal (lane < j) receive harmless values
+                // that are never stored
+                colb[lane] = a[c];
+                __builtin_amdgcn_wave_barrier();
 #pragma unroll
-                for (int j = c + 1; j < PB; ++j) a[j] -= a[c] * readlane_f64(a[c], j);
+                for (int j = c + 1; j < PB; ++j) a[j] -= a[c] * colb[j];
+                __builtin_amdgcn_wave_barrier();
             }
             if (fcol >= 0) {
                 if (lane == 0) {
@@ -84,14 +91,18 @@ __device__ __forceinline__ void potrf_body(double *__restrict__ tiles, int64_t k
         __syncthreads();
         if (fail) return;  // uniform: shared flag read after the barrier
         if (wave == 0) {
-            // column `lane` of D⁻¹: X[i][j] = (δ_ij - Σ_{m<i} D[i][m] X[m][j]) / D[i][i]
+            // column `lane` of D⁻¹: X[i][j] = (δ_ij - Σ_{m<i} D[i][m] X[m][j]) / D[i][i],
+            // column-oriented: once X[m][j] is final it is subtracted from every
+            // later row, so the updates of one step are independent (the same
+            // operations in the same order per entry as row by row)
             double x[PB];
 #pragma unroll
-            for (int i = 0; i < PB; ++i) {
-                double acc = (i == lane) ? 1.0 : 0.0;
+            for (int i = 0; i < PB; ++i) x[i] = (i == lane) ? 1.0 : 0.0;
 #pragma unroll
-                for (int m = 0; m < i; ++m) acc -= Ds[m][i] * x[m];
-                x[i] = acc * rdiag[i];
+            for (int m = 0; m < PB; ++m) {
+                x[m] *= rdiag[m];
+#pragma unroll
+                for (int i = m + 1; i < PB; ++i) x[i] -= Ds[m][i] * x[m];
             }
 #pragma unroll
             for (int i = 0; i < PB; ++i) Xi[lane][i] = x[i];
