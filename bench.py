@@ -401,7 +401,7 @@ def main():
         calibrate_copy(args.calibrate_copy)
         return
     if args.gpus != 1:
-        print(json.dumps({"error": "this benchmark runs on one GPU only; multi-GPU runs are not part of this build",
+        print(json.dumps({"error": "this benchmark runs on one GPU only: the library has no multi-GPU path (use --gpus 1)",
                           "n_gpus": args.gpus}))
         sys.exit(2)
     import numpy as np
