@@ -66,6 +66,17 @@ __device__ __forceinline__ void trailing_core(const double *__restrict__ At, con
     const int lc = tid >> 4;        // chunk column 0..15
     const int le = (tid & 15) * 2;  // rows le + 32 q, le + 32 q + 1 (q = 0..3)
 
+    // the C block's loads go first, so their latency overlaps the staging of
+    // the first chunk; the accumulators are negated once both have arrived
+    d4 acc[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            const int row = wm * 64 + a * 16 + mfma_col(lane);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) acc[a][b][r] = C[(int64_t)(wn * 64 + b * 16 + mfma_row(lane, r)) * B + row];
+        }
     d2 ra[4], rbv[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
@@ -77,17 +88,11 @@ __device__ __forceinline__ void trailing_core(const double *__restrict__ At, con
         *reinterpret_cast<d2 *>(&As[0][lc][le + 32 * q]) = ra[q];
         *reinterpret_cast<d2 *>(&Bs[0][lc][le + 32 * q]) = rbv[q];
     }
-    __syncthreads();
-    // the C block, loaded once the first chunk's staging registers are free
-    d4 acc[4][4];
 #pragma unroll
     for (int a = 0; a < 4; ++a)
 #pragma unroll
-        for (int b = 0; b < 4; ++b) {
-            const int row = wm * 64 + a * 16 + mfma_col(lane);
-#pragma unroll
-            for (int r = 0; r < 4; ++r) acc[a][b][r] = -C[(int64_t)(wn * 64 + b * 16 + mfma_row(lane, r)) * B + row];
-        }
+        for (int b = 0; b < 4; ++b) acc[a][b] = -acc[a][b];
+    __syncthreads();
 
     constexpr int NK = B / GK;
     for (int kc = 0; kc < NK; ++kc) {
