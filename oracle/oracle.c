@@ -74,14 +74,41 @@ double oracle_bessel_k(double nu, double x)
     return exp(-x) * oracle_bessel_k_scaled(nu, x);
 }
 
+/*
+ * x^ν K_ν(x) = ∫_0^∞ exp(ν log x - x cosh t) cosh(ν t) dt, the same integral
+ * with the power of x taken inside, by the same trapezoidal rule.  Each term
+ * is formed as ½ (exp(a + ν t) + exp(a - ν t)), a = ν log x - x cosh t, so
+ * neither x^ν (which underflows for large ν and small x) nor K_ν (which then
+ * overflows) is formed on its own; the product stays near 2^(ν-1) Γ(ν).  The
+ * log of the larger half, ν log x - x cosh t + ν t, is concave in t with its
+ * peak where x sinh t = ν, so a term below e^-745 relative to the largest one
+ * so far lies past the peak, and the sum stops there.
+ */
+double oracle_xnu_bessel_k(double nu, double x)
+{
+    double h = 0.08;
+    if (x > 0.0 && 0.4 / sqrt(x) < h) h = 0.4 / sqrt(x);
+    const double lx = log(x);
+    double peak = nu * lx - x;
+    double sum = 0.5 * exp(peak); /* t = 0, trapezoid half weight */
+    for (long k = 1;; ++k) {
+        double t = (double)k * h;
+        double a = nu * lx - x * cosh(t);
+        double top = a + nu * t;
+        if (top > peak) peak = top;
+        if (top < peak - 745.0 && t > 1.0) break;
+        sum += 0.5 * (exp(a + nu * t) + exp(a - nu * t));
+    }
+    return h * sum;
+}
+
 /* Matérn covariance at distance r, Sec. 2.2 Eq. (2). */
 double oracle_matern(double r, double theta1, double theta2, double theta3)
 {
     if (r == 0.0) return theta1; /* limit of x^ν K_ν(x) as x → 0 is 2^(ν-1) Γ(ν) */
     double x = r / theta2;
     double pref = theta1 / (pow(2.0, theta3 - 1.0) * tgamma(theta3));
-    /* (x^ν e^-x) is formed as one exponential so large x underflows cleanly */
-    return pref * exp(theta3 * log(x) - x) * oracle_bessel_k_scaled(theta3, x);
+    return pref * oracle_xnu_bessel_k(theta3, x);
 }
 
 /* ---------------------------------------------------------- distances ---- */

@@ -1,7 +1,8 @@
 """Pins for the oracle's K_ν and Matérn covariance (Sec. 2.2 Eq. (2)).
 
 The oracle integrates K_ν(x) = ∫_0^∞ exp(-x cosh t) cosh(νt) dt with the
-trapezoidal rule.  It is pinned here against sources that share nothing with
+trapezoidal rule, and the Matérn covariance from the same integral with x^ν
+taken inside.  It is pinned here against sources that share nothing with
 that method: mpmath's arbitrary-precision besselk, scipy's Amos-based kv, the
 three-term recurrence in ν, the x → 0 limit, and the elementary closed forms
 the paper lists for special smoothness values.
@@ -122,6 +123,22 @@ def test_matern_general_nu_vs_mpmath():
             ref = float(t1 / (mpmath.mpf(2) ** (nu - 1) * mpmath.gamma(nu)) * x ** nu * mpmath.besselk(nu, x))
             got = oracle.matern(r, (t1, t2, nu))
             assert abs(got - ref) <= 3e-14 * ref, (nu, r)
+
+
+@pytest.mark.parametrize("nu", [0.05, 0.3, 0.77, 1.0, 1.3, 2.2, 3.2, 10.0, 25.0, 45.0, 50.0])
+def test_matern_wide_range_vs_mpmath(nu):
+    """x = r/θ2 over [1e-8, 745] (both sides of x = 2, up to where x^ν e^-x
+    leaves the binary64 range), including large ν at small x, where x^ν
+    underflows and K_ν overflows on their own: 2e-13 relative wherever the
+    value is a normal number, within a few subnormal steps elsewhere."""
+    xs = list(np.geomspace(1e-8, 745.0, 61)) + [1.999999999, 2.0, 2.000000001, 700.0, 740.0, 745.0]
+    for x in xs:
+        ref = float(mpmath.mpf(2) ** (1 - nu) / mpmath.gamma(nu) * mpmath.mpf(x) ** nu * mpmath.besselk(nu, x))
+        got = oracle.matern(x, (1.0, 1.0, nu))
+        if ref >= 2.2250738585072014e-308:
+            assert abs(got - ref) <= 2e-13 * ref, (nu, x, got, ref)
+        else:
+            assert abs(got - ref) <= 64 * 5e-324, (nu, x, got, ref)
 
 
 def test_matern_at_zero_is_variance():

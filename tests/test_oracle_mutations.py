@@ -29,8 +29,11 @@ MUTANTS = {
                             "out[0] = -0.5 * quad - 0.5 * (double)n * log(2.0 * M_PI);"),
     "matern_gamma": ("tgamma(theta3)", "tgamma(theta3 + 1.0)"),
     "matern_power": ("pow(2.0, theta3 - 1.0)", "pow(2.0, theta3)"),
-    "bessel_nu": ("cosh(nu * t);", "cosh(0.5 * nu * t);"),
-    "bessel_halfweight": ("double sum = 0.5;", "double sum = 1.0;"),
+    "bessel_nu": ("sum += 0.5 * (exp(a + nu * t) + exp(a - nu * t));",
+                  "sum += 0.5 * (exp(a + 0.5 * nu * t) + exp(a - 0.5 * nu * t));"),
+    "bessel_halfweight": ("double sum = 0.5 * exp(peak);", "double sum = exp(peak);"),
+    "bessel_sinh": ("(exp(a + nu * t) + exp(a - nu * t))", "(exp(a + nu * t) - exp(a - nu * t))"),
+    "bessel_power": ("const double lx = log(x);", "const double lx = log(0.5 * x);"),
     "distance_sign": ("double dx = x1 - x2, dy = y1 - y2;", "double dx = x1 - x2, dy = y1 + y2;"),
     "krige_backward_skipped": ("oracle_backward(a, n, w, v);", "memcpy(v, w, (size_t)n * sizeof(double));"),
     "trmv_upper": ("for (int64_t k = 0; k <= i; ++k) s += l[i * n + k] * e[k];",
@@ -95,6 +98,15 @@ def _pins(lib):
             failed.append("matern_exp")
         if abs(lib.oracle_matern(r, 1.3, t2, 1.5) - 1.3 * (1 + x) * math.exp(-x)) > 1e-14:
             failed.append("matern_32")
+    # general and large smoothness against mpmath (x^ν K_ν near its x -> 0
+    # limit at large ν, where x^ν underflows and K_ν overflows on their own)
+    import mpmath
+    mpmath.mp.dps = 30
+    for nu, xx in [(0.77, 0.4), (2.2, 3.0), (13.0, 0.5), (45.0, 1e-8), (45.0, 30.0)]:
+        want = float(mpmath.mpf(2) ** (1 - nu) / mpmath.gamma(nu) * mpmath.mpf(xx) ** nu * mpmath.besselk(nu, xx))
+        if not abs(lib.oracle_matern(xx, 1.0, 1.0, nu) - want) <= 1e-12 * want:
+            failed.append("matern_mpmath")
+            break
     # l(θ) vs eigendecomposition on a jittered grid
     n = 40
     theta = (1.1, 0.15, 1.5)
