@@ -192,33 +192,56 @@ __host__ __device__ inline double matern_eval(const MaternSetup &s, double r, co
 {
     if (r == 0.0) return s.theta1;
     const double x = r / s.theta2;
+    // Past x = 2000 the correlation C/θ1 is below e^-1600 for every ν <= 50,
+    // so C underflows to 0 for any finite θ1; returning early also keeps
+    // the closed forms' polynomials and the recurrences below finite.
+    if (x > 2000.0) return 0.0;
     switch (s.kind) {
     case 1: return s.theta1 * exp(-x);
     case 2: return s.theta1 * (1.0 + x) * exp(-x);
     case 3: return s.theta1 * (1.0 + x + x * x / 3.0) * exp(-x);
     default: break;
     }
-    if (x > 760.0) return 0.0;  // x^ν e^-x is below the binary64 range for every ν <= 50
+    // Below 1e-150 the distance is far inside rounding of a repeated location;
+    // the clamp keeps K_μ+1 (about x^-3/2 at most) and the scaled recurrence
+    // below finite.
+    const double xc = fmax(x, 1e-150);
     double ka, kb;
-    const bool small = (x <= 2.0);
-    const double lgx = log(x);  // serves the series' log(2/x) and x^ν or x^ν e^-x
-    if (small) bessel_k_temme(s, x, M_LN2 - lgx, ka, kb, tab);
-    else bessel_k_miller_scaled(s, x, ka, kb, tab);
+    const bool small = (xc <= 2.0);
+    const double lgx = log(xc);  // serves the series' log(2/x) and x^ν or x^ν e^-x
+    if (small) bessel_k_temme(s, xc, M_LN2 - lgx, ka, kb, tab);
+    else bessel_k_miller_scaled(s, xc, ka, kb, tab);
     double knu;
+    double lsc = 0.0;  // natural log of the power of two divided out of (ka, kb)
     if (s.nl == 0) {
         knu = ka;
     } else {
-        // (ka, kb) = (K_μ+i-1, K_μ+i) → K_μ+nl
-        const double xi = 1.0 / x;
+        // (ka, kb) = (K_μ+i-1, K_μ+i) → K_μ+nl.  K grows with the order, like
+        // (2/x)^ν Γ(ν)/2 for small x, and overflows binary64 at large ν while
+        // x^ν underflows; the pair is rescaled by 2^-900 whenever it passes
+        // 2^500, so it stays below 2^124 after a rescale, one step multiplies
+        // it by at most 1 + 2ν/x < 2^505 (ν <= 50, x >= 1e-150), and the
+        // scale joins the exponent of x^ν at the end.
+        const double xi = 1.0 / xc;
+        if (kb > 0x1p500) {
+            ka *= 0x1p-900;
+            kb *= 0x1p-900;
+            lsc += 900.0 * M_LN2;
+        }
         for (int i = 1; i < s.nl; ++i) {
             double kc = ka + (2.0 * (s.mu + i) * xi) * kb;
             ka = kb;
             kb = kc;
+            if (kb > 0x1p500) {
+                ka *= 0x1p-900;
+                kb *= 0x1p-900;
+                lsc += 900.0 * M_LN2;
+            }
         }
         knu = kb;
     }
-    if (small) return s.pref * exp(s.nu * lgx) * knu;
-    return s.pref * exp(s.nu * lgx - x) * knu;
+    if (small) return s.pref * exp(s.nu * lgx + lsc) * knu;
+    return s.pref * exp(s.nu * lgx - xc + lsc) * knu;
 }
 
 __host__ __device__ inline double dist2d(double x1, double y1, double x2, double y2)

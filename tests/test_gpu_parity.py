@@ -140,6 +140,33 @@ def test_matern_generate_elementwise(g, ctx, nu):
     assert np.all(err <= 1e-300), float(np.max(np.abs(out - ref) / np.maximum(np.abs(ref), 1e-300)))
 
 
+NORMAL_MIN = 2.2250738585072014e-308
+
+
+@pytest.mark.parametrize("nu", [0.3, 0.77, 1.0, 1.3, 2.2, 3.2, 45.0])
+@pytest.mark.parametrize("theta2", [1.0, 0.013])
+def test_matern_generate_wide_range(g, ctx, nu, theta2):
+    """x = r/θ2 over [1e-8, 2500] through matern_generate: Temme's series
+    (x <= 2, both sides of 2), Miller's recurrence with its shallow depth at
+    large x, the far field (normal values past x = 745 at large ν, the cutoff
+    past 2000), and x < 1e-3; fixed coordinates on a line, θ2 scaling them.
+    ≤ 1e-12 relative to the oracle wherever its value is a normal number,
+    else within a few subnormal steps; no NaN."""
+    xs = np.concatenate([np.geomspace(1e-8, 745.0, 181), [1.999999999, 2.0, 2.000000001, 15.9, 16.1, 30.0],
+                         np.linspace(745.0, 765.0, 9), [900.0, 1200.0, 1999.0, 2001.0, 2500.0]])
+    x1, y1 = xs * theta2, np.zeros(xs.size)
+    x2 = np.array([0.0, 0.0, -0.25 * theta2])
+    y2 = np.array([0.0, 1e-3 * theta2, 0.5 * theta2])
+    theta = (1.0, theta2, nu)
+    ref = oracle.cov_matrix(x1, y1, x2, y2, theta)
+    out = g.matern_generate(ctx, dev(x1), dev(y1), dev(x2), dev(y2), theta).cpu().numpy().T
+    assert not np.any(np.isnan(out))
+    normal = np.abs(ref) >= NORMAL_MIN
+    relerr = np.abs(out - ref)[normal] / np.abs(ref)[normal]
+    assert np.all(relerr <= 1e-12), float(np.max(relerr))
+    assert np.all(np.abs(out - ref)[~normal] <= 64 * 5e-324)
+
+
 def test_matern_generate_zero_distance_and_far_field(g, ctx):
     x = np.array([0.25, 0.25, 500.0])
     y = np.array([0.5, 0.5, -300.0])
