@@ -154,6 +154,16 @@ const char *gl_status_string(int status);
  * (packed lower tiles plus vectors), b = 0 meaning the automatic choice. */
 size_t gl_footprint_bytes(int64_t n, int32_t tile, int32_t precision);
 
+/* The same footprint split into the workspace's three device allocations:
+ * packed lower tiles, vectors (padded locations and measurements, per-tile
+ * sums, inverses of the 64×64 diagonal blocks, result words, sort keys) and
+ * the mixed-precision side buffer (0 for GL_FP64), in bytes.  A workspace is
+ * reallocated only where a size grows.  Pure host arithmetic: needs no device.
+ * Errors: GL_EINVAL for n < 1 or a bad tile or precision.  Any output may be
+ * NULL. */
+int gl_workspace_layout(int64_t n, int32_t tile, int32_t precision, size_t *tiles_h, size_t *vecs_h,
+                        size_t *mix_h);
+
 /* --------------------------------------------------------- operations ---- */
 
 /*
@@ -213,13 +223,17 @@ int krige_predict(gl_context *ctx, gl_factor *factor, const double *xnew, const 
  * fields, so each held-out value is predicted by Eq. (5) from the observed
  * values of its own block (0 when the block observes nothing); reorder = 1 is
  * rejected there.  Synchronous with respect to `stream`.
+ * pred (device, n doubles, may be NULL): pred[i] receives the prediction of
+ * location i from the folds other than its own, in input order (the values
+ * the MSE of its fold is taken over); the entries of a fold whose Σ was not
+ * positive definite are left untouched.
  * Returns GL_OK; GL_NOT_SPD when some fold's Σ was not positive definite (its
  * mse_h is NaN, the other folds are still computed); GL_EINVAL for k < 2, a
  * fold id out of range, an empty fold or a fold holding every location.
  */
 int krige_cv(gl_context *ctx, const double *x, const double *y, const double *z, int64_t n,
              gl_theta theta, const gl_opts *opts, const int32_t *fold_h, int32_t k, double *mse_h,
-             void *stream);
+             double *pred, void *stream);
 
 /* Release a factor returned by loglik_eval. */
 int gl_factor_release(gl_context *ctx, gl_factor *factor);

@@ -78,10 +78,12 @@ _SIGNATURES = {
     "gl_opts_default": (None, [ctypes.POINTER(gl_opts)]),
     "gl_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "gl_footprint_bytes": (_SZ, [_I64, _I32, _I32]),
+    "gl_workspace_layout": (_I32, [_I64, _I32, _I32, ctypes.POINTER(_SZ), ctypes.POINTER(_SZ),
+                                   ctypes.POINTER(_SZ)]),
     "matern_generate": (_I32, [_P, _P, _P, _I64, _P, _P, _I64, gl_theta, _P, _P, _I64, _P]),
     "loglik_eval": (_I32, [_P, _P, _P, _P, _I64, gl_theta, ctypes.POINTER(gl_opts), ctypes.POINTER(gl_result), _P]),
     "krige_predict": (_I32, [_P, _P, _P, _P, _I64, _P, _P, _P]),
-    "krige_cv": (_I32, [_P, _P, _P, _P, _I64, gl_theta, _P, _P, _I32, _P, _P]),
+    "krige_cv": (_I32, [_P, _P, _P, _P, _I64, gl_theta, _P, _P, _I32, _P, _P, _P]),
     "gl_factor_release": (_I32, [_P, _P]),
     "gl_factor_to_dense": (_I32, [_P, _P, _P, _I64, _P]),
     "gl_factor_shape": (_I32, [_P, ctypes.POINTER(_I64), ctypes.POINTER(_I32)]),
@@ -179,6 +181,13 @@ def gl_footprint_bytes(n: int, tile: int = 0, precision: int = GL_FP64) -> int:
     return int(lib().gl_footprint_bytes(int(n), int(tile), int(precision)))
 
 
+def gl_workspace_layout(n: int, tile: int = 0, precision: int = GL_FP64) -> tuple[int, int, int]:
+    t, v, m = ctypes.c_size_t(), ctypes.c_size_t(), ctypes.c_size_t()
+    _check(lib().gl_workspace_layout(int(n), int(tile), int(precision), ctypes.byref(t), ctypes.byref(v),
+                                     ctypes.byref(m)), "gl_workspace_layout")
+    return t.value, v.value, m.value
+
+
 class Context:
     """Owns a gl_context; use as a context manager or call close()."""
 
@@ -257,18 +266,24 @@ def krige_predict(ctx: Context, factor, xnew, ynew, out=None, return_variance: b
     return (out, var) if return_variance else out
 
 
-def krige_cv(ctx: Context, x, y, z, theta, folds, opts: gl_opts | None = None, stream=None):
+def krige_cv(ctx: Context, x, y, z, theta, folds, opts: gl_opts | None = None, stream=None, pred=None):
     """k-fold cross-validation MSE of kriging; folds: n fold ids (0..k-1).
-    Returns (mse per fold as a list, status)."""
+    pred: optional float64 CUDA tensor of n values that receives each
+    location's prediction from the other folds.  Returns (mse per fold as a
+    list, status)."""
     import numpy as np
     f = np.ascontiguousarray(np.asarray(folds, dtype=np.int32))
-    if f.size != _same_len(x, y, z):
+    n = _same_len(x, y, z)
+    if f.size != n:
         raise ValueError("one fold id per location")
+    if pred is not None and pred.numel() != n:
+        raise ValueError("pred needs one value per location")
     k = int(f.max()) + 1 if f.size else 0
     mse = (ctypes.c_double * max(k, 1))()
     st = lib().krige_cv(ctx.handle, _ptr(x), _ptr(y), _ptr(z), x.numel(), _theta(theta),
                         ctypes.byref(opts) if opts is not None else None,
-                        f.ctypes.data_as(ctypes.c_void_p), k, mse, _stream(stream))
+                        f.ctypes.data_as(ctypes.c_void_p), k, mse,
+                        _ptr(pred) if pred is not None else None, _stream(stream))
     if st < 0:
         _check(st, "krige_cv")
     return [float(v) for v in mse[:k]], int(st)

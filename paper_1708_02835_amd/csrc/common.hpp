@@ -102,5 +102,6 @@ void launch_rhs_variance(const double *st, int b, int64_t nt, int64_t chunks, in
 void launch_gather3(const double *a, const double *b, const double *c, const int64_t *idx, int64_t m, double *oa,
                     double *ob, double *oc, hipStream_t s);
 void launch_mse(const double *p, const double *q, int64_t m, double *out, hipStream_t s);
+void launch_scatter(const double *a, const int64_t *idx, int64_t m, double *out, hipStream_t s);
 
 }  // namespace gl

@@ -72,11 +72,13 @@ void Work::release()
     mix = nullptr;
     tile_cap = vec_cap = mix_cap = 0;
     mv = MixedViews{};
+    ++gen;
 }
 
-static int grow(void *&p, size_t &cap, size_t need)
+static int grow(void *&p, size_t &cap, size_t need, uint64_t &gen)
 {
     if (need <= cap) return GL_OK;
+    ++gen;
     if (p) hipFree(p);
     p = nullptr;
     cap = 0;
@@ -95,10 +97,10 @@ int Work::ensure(gl_context *ctx, int64_t n_, int b_, int precision_)
                         (mneed > mix_cap ? mneed : mix_cap);
     if (want > old && ctx->used.load() - old + want > ctx->budget) return GL_ENOMEM;
     void *tp = tiles;
-    int rc = grow(tp, tile_cap, tneed);
+    int rc = grow(tp, tile_cap, tneed, gen);
     tiles = static_cast<double *>(tp);
-    if (rc == GL_OK) rc = grow(vecs, vec_cap, vneed);
-    if (rc == GL_OK && mneed) rc = grow(mix, mix_cap, mneed);
+    if (rc == GL_OK) rc = grow(vecs, vec_cap, vneed, gen);
+    if (rc == GL_OK && mneed) rc = grow(mix, mix_cap, mneed, gen);
     ctx->used += bytes() - old;
     if (rc != GL_OK) return rc;
     n = n_;
@@ -251,6 +253,20 @@ size_t gl_footprint_bytes(int64_t n, int32_t tile, int32_t precision)
     return work_bytes(n, pick_tile(n, tile), precision);
 }
 
+int gl_workspace_layout(int64_t n, int32_t tile, int32_t precision, size_t *tiles_h, size_t *vecs_h,
+                        size_t *mix_h)
+{
+    if (n < 1 || (tile != 0 && tile != 128 && tile != 256 && tile != 384 && tile != 512) ||
+        precision < GL_FP64 || precision > GL_MIXED_FP16)
+        return GL_EINVAL;
+    size_t t, v, m;
+    work_sizes(n, pick_tile(n, tile), precision, t, v, m);
+    if (tiles_h) *tiles_h = t;
+    if (vecs_h) *vecs_h = v;
+    if (mix_h) *mix_h = m;
+    return GL_OK;
+}
+
 int gl_context_create(int device, size_t budget, gl_context **out)
 {
     if (!out) return GL_EINVAL;
@@ -397,7 +413,6 @@ static void graph_drop(gl_context *ctx)
 {
     if (ctx->gexec) hipGraphExecDestroy(ctx->gexec);
     ctx->gexec = nullptr;
-    ctx->gkey_tiles = nullptr;
 }
 
 static int graph_eval(gl_context *ctx, Work &w, const double *x, const double *y, const double *z, gl_theta th,
@@ -417,7 +432,10 @@ static int graph_eval(gl_context *ctx, Work &w, const double *x, const double *y
     stage_inputs(w, x, y, z, o.reorder, g);
     *ctx->theta_h = th;  // the previous call synchronised, so the last upload is done
     GL_HIP_TRY(hipMemcpyAsync(ctx->theta_d, ctx->theta_h, sizeof(gl_theta), hipMemcpyHostToDevice, g));
-    const bool hit = ctx->gexec && ctx->gkey_tiles == w.tiles && ctx->gkey_n == w.n && ctx->gkey_b == w.b &&
+    // The graph holds pointers into the tiles and into the vectors (x, y, v,
+    // the per-tile sums, the diagonal-block inverses, info, result), so any
+    // reallocation of the workspace invalidates it, even when the tiles stay.
+    const bool hit = ctx->gexec && ctx->gkey_gen == w.gen && ctx->gkey_n == w.n && ctx->gkey_b == w.b &&
                      ctx->gkey_geo.metric == geo.metric && ctx->gkey_geo.radius == geo.radius;
     if (!hit) {
         graph_drop(ctx);
@@ -441,7 +459,7 @@ static int graph_eval(gl_context *ctx, Work &w, const double *x, const double *y
             ctx->gexec = nullptr;
             return GL_EHIP;
         }
-        ctx->gkey_tiles = w.tiles;
+        ctx->gkey_gen = w.gen;
         ctx->gkey_n = w.n;
         ctx->gkey_b = w.b;
         ctx->gkey_geo = geo;
@@ -614,7 +632,8 @@ int krige_predict(gl_context *ctx, gl_factor *f, const double *xnew, const doubl
 }
 
 int krige_cv(gl_context *ctx, const double *x, const double *y, const double *z, int64_t n, gl_theta th,
-             const gl_opts *opts, const int32_t *fold_h, int32_t k, double *mse_h, void *stream)
+             const gl_opts *opts, const int32_t *fold_h, int32_t k, double *mse_h, double *pred_out,
+             void *stream)
 {
     if (!ctx || !x || !y || !z || !fold_h || !mse_h || n < 2 || k < 2 || !valid_theta(th)) return GL_EINVAL;
     gl_opts o;
@@ -677,6 +696,7 @@ int krige_cv(gl_context *ctx, const double *x, const double *y, const double *z,
                 }
             }
             if (rc == GL_OK) {
+                if (pred_out) launch_scatter(pred, idx + nk, nm, pred_out, s);
                 launch_mse(pred, mz, nm, dmse, s);
                 if (hipMemcpyAsync(&mse_h[f], dmse, sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess ||
                     hipStreamSynchronize(s) != hipSuccess)

@@ -44,6 +44,7 @@ struct Work {
     void *vecs = nullptr;
     void *mix = nullptr;  // mixed-precision side buffer
     size_t tile_cap = 0, vec_cap = 0, mix_cap = 0;
+    uint64_t gen = 0;  // bumped whenever an allocation is replaced or released
     // views into vecs
     double *x = nullptr, *y = nullptr;  // padded locations
     double *v = nullptr;                // Z on entry, w = L⁻¹ Z after the evaluation
@@ -156,7 +157,7 @@ struct gl_context {
     hipStream_t gs = nullptr;        // stream the graph is captured on and replayed on
     hipEvent_t gev[2] = {nullptr, nullptr};
     hipGraphExec_t gexec = nullptr;
-    const void *gkey_tiles = nullptr;
+    uint64_t gkey_gen = 0;  // ws.gen at capture: the graph holds pointers into every allocation
     int64_t gkey_n = 0;
     int gkey_b = 0;
     gl::Geom gkey_geo{0, 0.0};

@@ -466,6 +466,20 @@ void launch_gather3(const double *a, const double *b, const double *c, const int
     gather3_kernel<<<(unsigned)ceil_div(m, 256), 256, 0, s>>>(a, b, c, idx, m, oa, ob, oc);
 }
 
+// out[idx[i]] = a[i]: the fold's predictions back to the input positions.
+__global__ void scatter_kernel(const double *__restrict__ a, const int64_t *__restrict__ idx, int64_t m,
+                               double *__restrict__ out)
+{
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= m) return;
+    out[idx[i]] = a[i];
+}
+
+void launch_scatter(const double *a, const int64_t *idx, int64_t m, double *out, hipStream_t s)
+{
+    scatter_kernel<<<(unsigned)ceil_div(m, 256), 256, 0, s>>>(a, idx, m, out);
+}
+
 __global__ __launch_bounds__(256) void mse_kernel(const double *__restrict__ p, const double *__restrict__ q,
                                                   int64_t m, double *__restrict__ out)
 {

@@ -118,3 +118,23 @@ def test_binding_rejects_unknown_option_names():
         g.lq_config_default(max_in_flight=3)
     o = g.gl_opts_default(tol_64=0.5, ind_tiles=2)
     assert o.tol_64 == 0.5 and o.ind_tiles == 2
+
+
+def test_workspace_layout_sequence_moves_only_the_vectors():
+    """The size sequence behind graph re-capture: with automatic tiles n = 3001
+    takes tile 256 and n = 3000 tile 128, so going 3001 -> 3000 grows the
+    vector allocation (64·b inverse words per diagonal tile) but not the tile
+    allocation.  A cached graph keyed on the tile allocation alone would replay
+    into freed vectors; the three parts must add up to the footprint."""
+    _ensure_built()
+    import paper_1708_02835_amd as g
+    t1, v1, m1 = g.gl_workspace_layout(3001)
+    t0, v0, m0 = g.gl_workspace_layout(3000)
+    assert t0 <= t1 and v0 > v1 and m0 == m1 == 0
+    for n in (3000, 3001, 40000):
+        for prec in (g.GL_FP64, g.GL_MIXED_BF16):
+            assert sum(g.gl_workspace_layout(n, 0, prec)) == g.gl_footprint_bytes(n, 0, prec)
+    with pytest.raises(g.GeolikError):
+        g.gl_workspace_layout(0)
+    with pytest.raises(g.GeolikError):
+        g.gl_workspace_layout(100, 100)

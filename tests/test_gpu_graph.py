@@ -79,3 +79,34 @@ def test_graph_not_spd_and_recovery(g):
         assert ok["status"] == g.GL_OK and same(ok, ref)
     finally:
         ctx.close()
+
+
+def test_graph_recaptures_after_vector_reallocation(g):
+    """Automatic tiles: n = 3001 takes tile 256, n = 3000 tile 128.  The eager
+    evaluation at n = 3000 needs a larger vector allocation (the 64·b inverse
+    blocks per diagonal tile grow with the tile count) but not larger tiles,
+    so only the vectors move.  The graph captured at n = 3001 holds pointers
+    into the old vectors; the third call must capture again instead of
+    replaying into freed memory."""
+    ctx = g.Context(0)
+    try:
+        th = (1.0, 0.1, 0.5)
+        sizes = [(3001, 1), (3000, 0), (3001, 1)]
+        t1, v1, _ = g.gl_workspace_layout(3001)
+        t0, v0, _ = g.gl_workspace_layout(3000)
+        assert t0 <= t1 and v0 > v1, (t0, t1, v0, v1)  # the sequence this test is for
+        for n, graph in sizes:
+            x, y = geoinputs.jittered_grid(n, 60 + n)
+            z = geoinputs.normal_vector(n, 61 + n)
+            xd, yd, zd = dev(x), dev(y), dev(z)
+            r_graph = g.loglik_eval(ctx, xd, yd, zd, th, g.gl_opts_default(graph=graph))
+            if n == 3000:
+                continue  # the eager call that reallocates the vectors
+            fresh = g.Context(0)
+            try:
+                r_eager = g.loglik_eval(fresh, xd, yd, zd, th, g.gl_opts_default())
+            finally:
+                fresh.close()
+            assert same(r_graph, r_eager), (n, r_graph, r_eager)
+    finally:
+        ctx.close()

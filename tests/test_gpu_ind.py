@@ -149,6 +149,47 @@ def test_ind_krige_cv_parity(g, ctx, s, tile, theta):
     assert np.all(np.abs(np.array(mse) - ref) <= 1e-9 * ref), (mse, ref)
 
 
+@pytest.mark.parametrize("s,tile", [(1, 128), (2, 128), (3, 128), (1, 256), (2, 256)])
+def test_ind_krige_cv_predictions_per_location(g, ctx, s, tile):
+    """Per-location IND predictions against oracle.krige_ind, element by
+    element.  n = 1100 leaves a ragged last block (1100 mod s·b locations);
+    every location of that block is put in fold 0, so when fold 0 is held out
+    the block observes nothing and its predictions must be exactly 0, and
+    when another fold is held out the block holds nothing to predict.
+    Tolerance: max(1e-10, 1e-15 κ) · max|z| with κ the largest condition
+    number of a block's observed covariance."""
+    n, k = 1100, 4
+    theta = (1.1, 0.09, 1.2)
+    x, y = geoinputs.jittered_grid(n, 48)
+    e = geoinputs.normal_vector(n, 48)
+    z, info = oracle.synth(x, y, e, theta)
+    assert info == 0
+    block = s * tile
+    folds = _folds(n, k, 49)
+    last = (n - 1) // block * block
+    assert n - last < block  # ragged
+    folds[last:] = 0
+    pred = torch.full((n,), float("nan"), dtype=torch.float64, device="cuda")
+    mse, st = g.krige_cv(ctx, dev(x), dev(y), dev(z), theta, folds,
+                         g.gl_opts_default(tile=tile, ind_tiles=s), pred=pred)
+    assert st == g.GL_OK
+    pred = pred.cpu().numpy()
+    assert np.all(np.isfinite(pred))
+    assert np.all(pred[last:] == 0.0)
+    for f in range(k):
+        miss = folds == f
+        ref, info = oracle.krige_ind(x, y, z, miss.astype(np.int32), theta, block)
+        assert info == 0
+        conds = []
+        for a in range(0, n, block):
+            kb = ~miss[a:a + block]
+            if kb.any():
+                conds.append(np.linalg.cond(oracle.cov_symmetric(x[a:a + block][kb], y[a:a + block][kb], theta)))
+        tol = max(1e-10, 1e-15 * max(conds)) * np.max(np.abs(z))
+        err = np.max(np.abs(pred[miss] - ref))
+        assert err <= tol, (f, err, tol)
+
+
 def test_ind_krige_cv_one_block_is_exact_and_blocks_cost_accuracy(g, ctx):
     """A super tile holding every location is the exact prediction; smaller
     super tiles predict worse (the trend the paper reports for its IND

@@ -186,6 +186,36 @@ def test_krige_cv_parity(g, ctx, metric):
         assert abs(mse[f] - ref) <= 1e-9 * ref, (f, mse[f], ref)
 
 
+@pytest.mark.parametrize("n,tile,theta", [(700, 128, (1.0, 0.1, 0.5)), (900, 256, (1.3, 0.07, 1.5)),
+                                          (650, 128, (0.8, 0.12, 1.0))])
+def test_krige_cv_predictions_per_location(g, ctx, n, tile, theta):
+    """Every held-out location's prediction (not only the per-fold MSE)
+    against the oracle's Eq. (5) on the same fold split, element by element;
+    tolerance as for krige_predict: max(1e-10, 1e-15 κ) · max|z| with κ the
+    condition number of the fold's observed covariance."""
+    k = 4
+    x, y = geoinputs.jittered_grid(n, 20 + n)
+    e = geoinputs.normal_vector(n, 20 + n)
+    z, info = oracle.synth(x, y, e, theta)
+    assert info == 0
+    folds = np.random.Generator(np.random.PCG64(n)).permutation(np.arange(n) % k).astype(np.int32)
+    pred = torch.full((n,), float("nan"), dtype=torch.float64, device="cuda")
+    mse, st = g.krige_cv(ctx, dev(x), dev(y), dev(z), theta, folds, g.gl_opts_default(tile=tile), pred=pred)
+    assert st == g.GL_OK
+    pred = pred.cpu().numpy()
+    assert np.all(np.isfinite(pred))
+    for f in range(k):
+        known, miss = folds != f, folds == f
+        ref, info = oracle.krige(x[known], y[known], z[known], x[miss], y[miss], theta)
+        assert info == 0
+        cond = np.linalg.cond(oracle.cov_symmetric(x[known], y[known], theta))
+        tol = max(1e-10, 1e-15 * cond) * np.max(np.abs(z))
+        err = np.max(np.abs(pred[miss] - ref))
+        assert err <= tol, (f, err, tol)
+        # the fold's MSE is the mean over exactly these predictions
+        assert abs(mse[f] - float(np.mean((pred[miss] - z[miss]) ** 2))) <= 1e-12 * mse[f]
+
+
 def test_krige_cv_rejects_bad_folds(g, ctx):
     x, y = geoinputs.jittered_grid(100, 12)
     z = geoinputs.normal_vector(100, 12)
