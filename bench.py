@@ -10,14 +10,18 @@ resident in HBM when the timed region starts.
 
 Printed as one JSON line: evals/s of the timed FP64 steps, effective Cholesky
 TFLOP/s (n³/3 per step), the trailing-update kernel's live roofline fraction
-(HIP events around each of its launches) with its HBM traffic from the
-committed counter record, and the oracle timed on one host core as the CPU
-baseline.  Legs outside the timed region, each skippable: mixed precision
-against FP64 at the same size for two θ, the independent-blocks
+(HIP events around each of its launches; also split into the bulk launches of
+the lookahead stream and the critical-column launches) with its HBM traffic
+from the committed counter record, and the oracle timed on one host core as
+the CPU baseline.  Legs outside the timed region, each skippable: mixed
+precision against FP64 at the same size for two θ, the independent-blocks
 approximation per super-tile size (l, and 10-fold prediction MSE against the
-exact prediction), small-n latency with and without graph
-replay, maximum-likelihood estimates FP64 vs mixed, and the request queue
-serving 64 concurrent clients against one-at-a-time evaluation.
+exact prediction), small-n latency with and without graph replay,
+maximum-likelihood estimates FP64 vs mixed, the 1,600-point evaluation
+(median latency, oracle agreement), n = 40,000 per tile size with the kernel
+time of each phase and 1,000-point kriging, 64 concurrent Nelder-Mead clients
+on the request queue against one-at-a-time evaluation, and n = 150,000 with
+BF16 off-band updates and 5,000-point kriging from the resident factor.
 """
 from __future__ import annotations
 
@@ -53,9 +57,15 @@ def parse():
     p.add_argument("--no-ind", action="store_true", help="skip the independent-blocks leg")
     p.add_argument("--no-graph", action="store_true", help="skip the small-n graph-replay latency leg")
     p.add_argument("--no-mle", action="store_true", help="skip the maximum-likelihood (FP64 vs mixed) leg")
+    p.add_argument("--no-small", action="store_true", help="skip the n = 1,600 latency leg")
+    p.add_argument("--no-n40k", action="store_true", help="skip the n = 40,000 tile-sweep and kriging leg")
+    p.add_argument("--no-n150k", action="store_true", help="skip the n = 150,000 BF16 and kriging leg")
     p.add_argument("--mle-n", type=int, default=8100)
     p.add_argument("--serve-clients", type=int, default=64)
-    p.add_argument("--serve-evals", type=int, default=5, help="l(theta) requests per client")
+    p.add_argument("--serve-evals", type=int, default=100,
+                   help="most l(theta) requests of one client's Nelder-Mead search")
+    p.add_argument("--serve-replay", type=int, default=10,
+                   help="first requests of every client replayed one at a time for comparison")
     p.add_argument("--serve-rate", type=float, default=400.0, help="client arrivals per second (Poisson)")
     p.add_argument("--serve-think-ms", type=float, default=1.0,
                    help="mean exponential pause of a client between a result and its next request")
@@ -78,30 +88,69 @@ def calibrate_copy(mib: int) -> None:
     print(json.dumps({"calibrate_copy_mib": mib, "copies": 3}), flush=True)
 
 
-def cpu_baseline(n_target: int, theta) -> dict:
-    """Time the oracle (single-threaded FP64 C) on two bounded samples and
-    extrapolate t(n) = a n² + b n³ to the benchmark size."""
+def host_info() -> dict:
+    """CPU model (from /proc/cpuinfo) and core counts of the machine the
+    oracle is timed on."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"cpu_model": model, "nproc": os.cpu_count(), "affinity_cores": len(os.sched_getaffinity(0))}
+
+
+CPU_SAMPLE_SIZES = (400, 1600, 2800, 4000)
+
+
+def fit_cubic(ns, ts):
+    """Least-squares t = a n³ + b n² through the timed sizes; returns (a, b)."""
+    import numpy as np
+    A = np.array([[float(n) ** 3, float(n) ** 2] for n in ns])
+    (a, b), *_ = np.linalg.lstsq(A, np.array(ts, dtype=float), rcond=None)
+    return float(a), float(b)
+
+
+def cpu_baseline(n_target: int, theta, sizes=CPU_SAMPLE_SIZES) -> dict:
+    """Time the oracle (single-threaded FP64 C, one call per size) pinned to
+    one host core at n = 400, 1,600, 2,800 and 4,000 (about 10-30 s), fit
+    t = a n³ + b n² on the first three sizes, check the fit against the fourth,
+    and extrapolate to the benchmark size (labelled as extrapolated).  The
+    n = 1,600 time is the 1,600-point single-evaluation workload timed directly."""
     import geoinputs
     import oracle
     oracle.build()
-    samples = (2000, 4000)  # about 17 s of single-core oracle work
+    info = host_info()
+    old = os.sched_getaffinity(0)
+    core = min(old)
+    os.sched_setaffinity(0, {core})
     times = []
-    for n in samples:
-        x, y = geoinputs.jittered_grid(n, 77)
-        z = geoinputs.normal_vector(n, 77)
-        t0 = time.perf_counter()
-        oracle.loglik(x, y, z, theta)
-        times.append(time.perf_counter() - t0)
-    (n1, n2), (t1, t2) = samples, times
-    # solve [n1² n1³; n2² n2³] [a b]ᵀ = [t1 t2]ᵀ
-    det = n1 ** 2 * n2 ** 3 - n2 ** 2 * n1 ** 3
-    a = (t1 * n2 ** 3 - t2 * n1 ** 3) / det
-    b = (n1 ** 2 * t2 - n2 ** 2 * t1) / det
-    t_target = a * n_target ** 2 + b * n_target ** 3
+    try:
+        for n in sizes:
+            x, y = geoinputs.jittered_grid(n, 77)
+            z = geoinputs.normal_vector(n, 77)
+            t0 = time.perf_counter()
+            oracle.loglik(x, y, z, theta)
+            times.append(time.perf_counter() - t0)
+    finally:
+        os.sched_setaffinity(0, old)
+    a, b = fit_cubic(sizes[:3], times[:3])
+    n4 = sizes[3]
+    pred4 = a * n4 ** 3 + b * n4 ** 2
+    t_target = a * n_target ** 3 + b * n_target ** 2
+    timed = ", ".join(f"n={n}: {t:.2f} s" for n, t in zip(sizes, times))
     return {"value": 1.0 / t_target, "unit": "evals/s", "cores": 1, "kind": "oracle",
-            "sample": (f"oracle l(theta) timed at n={n1} ({t1:.2f} s) and n={n2} ({t2:.2f} s) on one host core, "
-                       f"extrapolated to n={n_target} with t = a n^2 + b n^3 (t={t_target:.3g} s)"),
-            "seconds_timed": t1 + t2}
+            "sample": (f"oracle l(theta) (generation, unblocked Cholesky, solve) timed once per size on host "
+                       f"core {core} ({timed}); t = a n^3 + b n^2 fitted on the first three sizes predicts "
+                       f"{pred4:.2f} s at n={n4} (residual {(times[3] - pred4) / times[3]:+.1%}); "
+                       f"extrapolated to n={n_target}: {t_target:.3g} s per evaluation"),
+            "extrapolated": True, "pinned_core": core, **info,
+            "sizes": list(sizes), "seconds": times, "fit": {"a_n3": a, "b_n2": b},
+            "fit_residual_at_largest": (times[3] - pred4) / times[3],
+            "n1600_direct_s": times[1], "seconds_timed": sum(times)}
 
 
 def measured_traffic(n: int, tile: int):
@@ -138,7 +187,7 @@ def mixed_legs(g, ctx, xd, yd, ed, zd, theta, theta_b, args, res64, t64, log):
         stats = g.gl_precision_stats(ctx) if prec != g.GL_FP64 else None
         return r, dt, stats
 
-    for label, th, z, steps in (("theta_a", theta, zd, args.steps), ("theta_b", theta_b, None, 1)):
+    for label, th, z, steps in (("theta_a", theta, zd, min(args.steps, 3)), ("theta_b", theta_b, None, 1)):
         if z is None:
             z, info = g.synth_generate(ctx, xd, yd, ed, th, args.tile)
             if info != 0:
@@ -286,23 +335,209 @@ def mle_leg(g, ctx, args, log):
     return out
 
 
-def serving_leg(g, ctx, args, log):
-    """Many concurrent maximum-likelihood clients, each on its own synthetic
-    field (n uniform in 1,000..16,000, true θ drawn per client), arriving as a
-    Poisson process and each issuing a closed loop of l(θ) requests (the next
-    θ after the previous result and an exponential pause).  The same requests
-    are then evaluated one at a time with loglik_eval for comparison."""
-    import threading
-
+def small_leg(g, ctx, args, log):
+    """The 1,600-point single evaluation (40 x 40 jittered grid, θ = (1, 0.1,
+    0.5), Z = L e): latency as the median of 50 timed evaluations after 5
+    warm-ups, and l and log|Σ| against the oracle."""
     import numpy as np
     import torch
 
     import geoinputs
+    import oracle
+    n, theta = 1600, (1.0, 0.1, 0.5)
+    x, y = geoinputs.jittered_grid(n, 1000)
+    e = geoinputs.normal_vector(n, 1000)
+    xd, yd, ed = (torch.as_tensor(a).cuda() for a in (x, y, e))
+    zd, info = g.synth_generate(ctx, xd, yd, ed, theta)
+    if info != 0:
+        return {"error": f"field generation failed, info={info}"}
+    opts = g.gl_opts_default()
+    for _ in range(5):
+        g.loglik_eval(ctx, xd, yd, zd, theta, opts)
+    lat = []
+    for _ in range(50):
+        t0 = time.perf_counter()
+        r = g.loglik_eval(ctx, xd, yd, zd, theta, opts)
+        lat.append(time.perf_counter() - t0)
+    ref = oracle.loglik(x, y, zd.cpu().numpy(), theta)
+    out = {"n": n, "theta": list(theta), "tile": r["tile"], "median_ms": float(np.median(lat) * 1e3),
+           "p99_ms": float(np.percentile(lat, 99) * 1e3), "evals_per_s": 1.0 / float(np.median(lat)),
+           "loglik": r["loglik"], "logdet": r["logdet"],
+           "rel_err_loglik_vs_oracle": abs(r["loglik"] - ref[0]) / abs(ref[0]),
+           "rel_err_logdet_vs_oracle": abs(r["logdet"] - ref[1]) / abs(ref[1])}
+    log(f"n=1600: median {out['median_ms']:.3f} ms, rel err vs oracle {out['rel_err_loglik_vs_oracle']:.1e}")
+    return out
 
-    clients, evals = args.serve_clients, args.serve_evals
+
+def held_out_field(g, ctx, n, m, seed, theta, tile=0):
+    """n jittered-grid locations plus m extra ones ~ U[0,1]², Z simulated
+    jointly at all n + m (Alg. 1 on the device); returns device tensors of the
+    observed part and the held-out part with its true values."""
+    import numpy as np
+    import torch
+
+    import geoinputs
+    x, y = geoinputs.jittered_grid(n, seed)
+    xm, ym = geoinputs.uniform_points(m, seed)
+    xa, ya = np.concatenate([x, xm]), np.concatenate([y, ym])
+    e = geoinputs.normal_vector(n + m, seed)
+    xd, yd, ed = (torch.as_tensor(a).cuda() for a in (xa, ya, e))
+    zd, info = g.synth_generate(ctx, xd, yd, ed, theta, tile)
+    del ed
+    if info != 0:
+        return None
+    obs = (xd[:n].contiguous(), yd[:n].contiguous(), zd[:n].contiguous())
+    held = (xd[n:].contiguous(), yd[n:].contiguous(), zd[n:].cpu().numpy())
+    return obs, held
+
+
+def n40k_leg(g, ctx, args, log):
+    """The tiled path at n = 40,000 (200 x 200 jittered grid) for θ = (1, 0.1,
+    0.5) and (1, 0.03, 1.5): one timed evaluation per tile size 256, 384, 512
+    (after a warm-up) with the kernel time of every phase of Alg. 2, and
+    kriging of 1,000 held-out locations (Z simulated jointly with them) from the
+    tile-512 factor: time and MSE against the simulated truth."""
+    import numpy as np
+    import torch
+    n, m = 40000, 1000
+    out = {"n": n, "held_out": m, "runs": []}
+    for ti, theta in enumerate(((1.0, 0.1, 0.5), (1.0, 0.03, 1.5))):
+        fld = held_out_field(g, ctx, n, m, args.seed + 20 + ti, theta)
+        if fld is None:
+            out["runs"].append({"theta": list(theta), "error": "field generation failed"})
+            continue
+        (xd, yd, zd), (xh, yh, truth) = fld
+        for tile in (256, 384, 512):
+            opts = g.gl_opts_default(tile=tile)
+            g.loglik_eval(ctx, xd, yd, zd, theta, opts)
+            torch.cuda.synchronize()
+            g.gl_profile_enable(ctx, 2)
+            g.gl_profile_phases(ctx)
+            t0 = time.perf_counter()
+            r = g.loglik_eval(ctx, xd, yd, zd, theta, opts)
+            dt = time.perf_counter() - t0
+            ph = g.gl_profile_phases(ctx)
+            g.gl_profile_enable(ctx, 0)
+            t1 = time.perf_counter()
+            g.loglik_eval(ctx, xd, yd, zd, theta, opts)  # untimed phases: the plain wall time
+            dt_plain = time.perf_counter() - t1
+            run = {"theta": list(theta), "tile": tile, "seconds": dt_plain, "seconds_with_phase_events": dt,
+                   "cholesky_tflops": n ** 3 / 3.0 / dt_plain / 1e12, "loglik": r["loglik"], "status": r["status"],
+                   "phase_kernel_ms": {p: round(v["ms"], 3) for p, v in ph.items()}}
+            tr = ph["trail_bulk"]
+            if tr["ms"] > 0:
+                run["trail_bulk_tflops"] = tr["flops"] / (tr["ms"] * 1e-3) / 1e12
+            out["runs"].append(run)
+            log(f"n=40000 theta={theta} tile={tile}: {dt_plain:.3f} s, phases {run['phase_kernel_ms']}")
+        r = g.loglik_eval(ctx, xd, yd, zd, theta, g.gl_opts_default(tile=512, keep_factor=1))
+        if r["status"] == g.GL_OK:
+            try:
+                g.krige_predict(ctx, r["factor"], xh, yh)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                pred = g.krige_predict(ctx, r["factor"], xh, yh)
+                torch.cuda.synchronize()
+                dt = time.perf_counter() - t0
+            finally:
+                g.gl_factor_release(ctx, r["factor"])
+            pred = pred.cpu().numpy()
+            out["runs"].append({"theta": list(theta), "kriging_points": m, "kriging_ms": dt * 1e3,
+                                "mse_vs_truth": float(np.mean((pred - truth) ** 2)),
+                                "truth_variance": float(np.var(truth))})
+            log(f"n=40000 theta={theta}: kriging {m} points {dt * 1e3:.2f} ms, "
+                f"MSE {out['runs'][-1]['mse_vs_truth']:.4e}")
+        del xd, yd, zd, xh, yh
+        torch.cuda.empty_cache()
+    return out
+
+
+def n150k_leg(g, args, log):
+    """n = 150,000 jittered locations plus 5,000 held out (Z simulated jointly
+    at 155,000 points in FP64), θ = (1, 0.1, 0.5): time-to-l with BF16 off-band
+    updates, kriging of the 5,000 points from the device-resident BF16 factor
+    (the factor reused: no new factorisation), and the same with the FP64
+    factor; MSE of the BF16 predictions against the FP64 ones and against the
+    simulated truth."""
+    import numpy as np
+    import torch
+    n, m, theta = 150000, 5000, (1.0, 0.1, 0.5)
+    out = {"n": n, "held_out": m, "theta": list(theta)}
+    ctx = g.Context(0)
+    try:
+        t0 = time.perf_counter()
+        fld = held_out_field(g, ctx, n, m, args.seed + 30, theta)
+        log(f"n=150000: field of {n + m} points simulated ({time.perf_counter() - t0:.1f} s)")
+        if fld is None:
+            return {"error": "field generation failed"}
+        (xd, yd, zd), (xh, yh, truth) = fld
+        ctx.close()
+        ctx = g.Context(0)  # release the simulation's workspace
+        torch.cuda.empty_cache()
+        preds = {}
+        for name, prec in (("bf16", g.GL_MIXED_BF16), ("fp64", g.GL_FP64)):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            r = g.loglik_eval(ctx, xd, yd, zd, theta, g.gl_opts_default(precision=prec, keep_factor=1))
+            t_l = time.perf_counter() - t0
+            if r["status"] != g.GL_OK:
+                out[name] = {"status": r["status"]}
+                continue
+            try:
+                t0 = time.perf_counter()
+                pred = g.krige_predict(ctx, r["factor"], xh, yh)
+                torch.cuda.synchronize()
+                t_k = time.perf_counter() - t0
+                t0 = time.perf_counter()
+                pred = g.krige_predict(ctx, r["factor"], xh, yh)  # the factor reused again
+                torch.cuda.synchronize()
+                t_k2 = time.perf_counter() - t0
+            finally:
+                g.gl_factor_release(ctx, r["factor"])
+            preds[name] = pred.cpu().numpy()
+            out[name] = {"time_to_l_s": t_l, "loglik": r["loglik"], "logdet": r["logdet"],
+                         "kriging_ms": t_k * 1e3, "kriging_reuse_ms": t_k2 * 1e3,
+                         "mse_vs_truth": float(np.mean((preds[name] - truth) ** 2))}
+            log(f"n=150000 {name}: l in {t_l:.2f} s, kriging {m} points {t_k * 1e3:.1f} ms "
+                f"(again {t_k2 * 1e3:.1f} ms), MSE {out[name]['mse_vs_truth']:.4e}")
+            torch.cuda.empty_cache()
+        if "bf16" in preds and "fp64" in preds:
+            out["bf16"]["speedup_vs_fp64"] = out["fp64"]["time_to_l_s"] / out["bf16"]["time_to_l_s"]
+            out["bf16"]["rel_err_loglik"] = abs(out["bf16"]["loglik"] - out["fp64"]["loglik"]) / abs(out["fp64"]["loglik"])
+            out["bf16"]["mse_vs_fp64_kriging"] = float(np.mean((preds["bf16"] - preds["fp64"]) ** 2))
+        out["truth_variance"] = float(np.var(truth))
+    finally:
+        ctx.close()
+        torch.cuda.empty_cache()
+    return out
+
+
+SERVE_THETA0 = (1.0, 0.1, 1.0)
+SERVE_BOUNDS = ((0.01, 5.0), (0.005, 1.5), (0.1, 3.0))
+
+
+def serving_leg(g, ctx, args, log):
+    """Many concurrent maximum-likelihood clients on the request queue, each
+    on its own synthetic field (n uniform in 1,000..16,000, true θ drawn per
+    client), starting as a Poisson process.  Each client runs a bounded
+    Nelder-Mead search over log θ from θ0 = (1, 0.1, 1.0) (a derivative-free
+    stand-in for the paper's BOBYQA) in closed loop: every objective value is
+    one l(θ) request, issued after the previous result and an exponential
+    pause, up to --serve-evals requests.  Reported: evals/s over the makespan,
+    submit-to-result latency percentiles, and, for the first requests of every
+    client replayed one at a time with loglik_eval, the one-at-a-time rate and
+    the largest difference of l."""
+    import threading
+
+    import numpy as np
+    import torch
+    from scipy import optimize
+
+    import geoinputs
+
+    clients, maxfev = args.serve_clients, args.serve_evals
     fields = geoinputs.serving_fields(clients, args.seed)
     rng = np.random.Generator(np.random.PCG64([args.seed, 77]))
-    data, dss, plans = [], [], []
+    data, dss = [], []
     t_s = time.perf_counter()
     for c, f in enumerate(fields):
         n, th = f["n"], f["theta"]
@@ -314,36 +549,44 @@ def serving_leg(g, ctx, args, log):
             z = ed  # Σ(θ) not numerically SPD at the true θ: serve white noise
         data.append((xd, yd, z))
         dss.append(g.gl_dataset_register(ctx, xd, yd, z))
-        # proposals of a derivative-free optimiser around the true θ
-        steps = np.exp(rng.normal(0.0, [0.15, 0.15, 0.1], size=(evals, 3)))
-        plans.append([tuple(float(v) for v in np.array(th) * s_) for s_ in steps])
     starts = geoinputs.arrival_times(clients, args.serve_rate, args.seed)
-    pauses = rng.exponential(args.serve_think_ms * 1e-3, size=(clients, evals))
+    pauses = rng.exponential(args.serve_think_ms * 1e-3, size=(clients, maxfev + 8))
+    lo = np.log([b[0] for b in SERVE_BOUNDS])
+    hi = np.log([b[1] for b in SERVE_BOUNDS])
     log(f"serving: {clients} fields ready ({time.perf_counter() - t_s:.2f} s)")
 
     q = g.lq_create(ctx, g.lq_config_default())
     try:
         # warm-up: one request per client, all at once (workspace pool, code objects)
-        for t in [g.lq_submit(q, ds, plans[c][0]) for c, ds in enumerate(dss)]:
+        for t in [g.lq_submit(q, ds, SERVE_THETA0) for ds in dss]:
             g.lq_wait(q, t)
         lat = [[] for _ in range(clients)]
-        res = [[None] * evals for _ in range(clients)]
+        hist = [[] for _ in range(clients)]
+        found = [None] * clients
         errors = []
         t0 = time.perf_counter()
 
         def client(c):
             try:
-                due = t0 + starts[c]
-                for k in range(evals):
+                due = [t0 + starts[c]]
+
+                def negl(v):
                     now = time.perf_counter()
-                    if due > now:
-                        time.sleep(due - now)
+                    if due[0] > now:
+                        time.sleep(due[0] - now)
+                    th = tuple(float(t) for t in np.exp(np.clip(v, lo, hi)))
                     s0 = time.perf_counter()
-                    r = g.lq_wait(q, g.lq_submit(q, dss[c], plans[c][k]))
+                    r = g.lq_wait(q, g.lq_submit(q, dss[c], th))
                     done = time.perf_counter()
                     lat[c].append(done - s0)
-                    res[c][k] = r
-                    due = done + pauses[c][k]
+                    hist[c].append((th, r))
+                    due[0] = done + pauses[c][min(len(hist[c]), maxfev + 7)]
+                    return -r["loglik"] if r["status"] == g.GL_OK else 1e300
+
+                res = optimize.minimize(negl, np.log(SERVE_THETA0), method="Nelder-Mead",
+                                        bounds=list(zip(lo, hi)),
+                                        options={"maxfev": maxfev, "xatol": 1e-5, "fatol": 1e-7})
+                found[c] = [float(t) for t in np.exp(res.x)]
             except Exception as exc:  # noqa: BLE001
                 errors.append(repr(exc))
 
@@ -354,44 +597,60 @@ def serving_leg(g, ctx, args, log):
             th_.join()
         wall = time.perf_counter() - t0
         stats = g.lq_stats(q)
+        ticks = g.lq_tick_stats(q)
     finally:
         g.lq_destroy(q)
     if errors:
         raise SystemExit(f"serving clients failed: {errors[:3]}")
     all_lat = np.array([v for c in lat for v in c])
-    total = clients * evals
+    total = int(all_lat.size)
     log(f"serving: {total} evals in {wall:.2f} s, p50 {np.median(all_lat) * 1e3:.1f} ms")
 
-    # the same requests, one at a time
+    # the first requests of every client, one at a time
+    replay = min(args.serve_replay, min(len(h) for h in hist))
     opts = g.gl_opts_default()
     for c in range(clients):
-        g.loglik_eval(ctx, *data[c], plans[c][0], opts)
+        g.loglik_eval(ctx, *data[c], hist[c][0][0], opts)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    single = [[g.loglik_eval(ctx, *data[c], plans[c][k], opts) for k in range(evals)] for c in range(clients)]
+    single = [[g.loglik_eval(ctx, *data[c], hist[c][k][0], opts) for k in range(replay)] for c in range(clients)]
     torch.cuda.synchronize()
     t_single = time.perf_counter() - t1
     for ds in dss:
         g.gl_dataset_release(ctx, ds)
     worst, statuses = 0.0, {}
     for c in range(clients):
-        for k in range(evals):
-            a, b = res[c][k], single[c][k]
+        for th, a in hist[c]:
             statuses[str(a["status"])] = statuses.get(str(a["status"]), 0) + 1
+        for k in range(replay):
+            a, b = hist[c][k][1], single[c][k]
             if a["status"] == g.GL_OK and b["status"] == g.GL_OK:
                 worst = max(worst, abs(a["loglik"] - b["loglik"]) / abs(b["loglik"]))
             elif a["status"] != b["status"]:
                 statuses["mismatch"] = statuses.get("mismatch", 0) + 1
     ns = [f["n"] for f in fields]
-    log(f"serving: one at a time {total / t_single:.1f} evals/s")
-    return {"clients": clients, "evals_per_client": evals, "evals": total,
+    single_rate = clients * replay / t_single
+    log(f"serving: one at a time {single_rate:.1f} evals/s ({clients * replay} replayed)")
+    rel_theta = [float(np.max(np.abs(np.array(found[c]) - np.array(fields[c]["theta"])) /
+                              np.array(fields[c]["theta"]))) for c in range(clients)]
+    return {"clients": clients, "max_evals_per_client": maxfev, "evals": total,
+            "evals_per_client": {"min": min(len(h) for h in hist), "max": max(len(h) for h in hist)},
+            "optimizer": "bounded Nelder-Mead on log theta from (1, 0.1, 1.0), closed loop",
             "n_range": [min(ns), max(ns)], "n_mean": float(np.mean(ns)),
-            "evals_per_s": total / wall, "p50_ms": float(np.percentile(all_lat, 50) * 1e3),
+            "makespan_s": wall, "evals_per_s": total / wall,
+            "p50_ms": float(np.percentile(all_lat, 50) * 1e3),
             "p99_ms": float(np.percentile(all_lat, 99) * 1e3), "max_ms": float(all_lat.max() * 1e3),
-            "one_at_a_time_evals_per_s": total / t_single, "speedup_vs_one_at_a_time": t_single / wall,
+            "one_at_a_time_evals_per_s": single_rate, "one_at_a_time_sample": clients * replay,
+            "speedup_vs_one_at_a_time": total / wall / single_rate,
             "status_counts": statuses, "max_rel_diff_vs_one_at_a_time": worst,
+            "theta_hat_max_rel_err_vs_truth": {"median": float(np.median(rel_theta)), "max": float(np.max(rel_theta))},
             "peak_inflight": stats["peak_inflight"], "peak_bytes": stats["peak_bytes"],
             "fused_launches": stats["fused_launches"],
+            "ticks": {"count": ticks["ticks"],
+                      "host_us_per_tick": ticks["host_us"] / max(ticks["ticks"], 1),
+                      "device_us_per_tick": ticks["device_ms"] * 1e3 / max(ticks["ticks"], 1),
+                      "launches_per_tick": stats["fused_launches"] / max(ticks["ticks"], 1),
+                      "idle_between_ticks_frac": ticks["gap_ms"] * 1e-3 / wall},
             "arrivals": f"Poisson, {args.serve_rate:g} clients/s; pause {args.serve_think_ms:g} ms mean"}
 
 
@@ -430,8 +689,8 @@ def main():
         g.loglik_eval(ctx, xd, yd, zd, theta, opts)
         log(f"warmup {i} {time.perf_counter() - s0:.3f} s")
     torch.cuda.synchronize()
-    g.gl_profile_enable(ctx, True)
-    g.gl_profile_read(ctx)  # reset
+    g.gl_profile_enable(ctx, 1)
+    g.gl_profile_phases(ctx)  # reset
     lat = []
     res = None
     torch.cuda.synchronize()
@@ -443,12 +702,23 @@ def main():
         log(f"step {len(lat) - 1} {lat[-1]:.3f} s l={res['loglik']:.10g}")
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
-    prof = g.gl_profile_read(ctx)
-    g.gl_profile_enable(ctx, False)
+    ph = g.gl_profile_phases(ctx)
+    g.gl_profile_enable(ctx, 0)
+    crit, bulk = ph["trail_crit"], ph["trail_bulk"]
+    prof = {k: crit[k] + bulk[k] for k in ("ms", "flops", "launches")}
     if res["status"] != g.GL_OK:
         raise SystemExit(f"evaluation failed: {res}")
 
     step_s = elapsed / args.steps
+
+    def rate(p):
+        """Roofline of one kind of trailing launch: the bulk update of the
+        remaining columns (lookahead stream) or the next column's update
+        (critical stream)."""
+        a = p["flops"] / (p["ms"] * 1e-3) / 1e12 if p["ms"] > 0 else 0.0
+        return {"achieved": a, "frac": a / PEAK_FP64_TFLOPS, "launches": p["launches"],
+                "avg_launch_ms": p["ms"] / max(p["launches"], 1), "flops_per_launch": p["flops"] / max(p["launches"], 1),
+                "busy_frac_of_wall": p["ms"] * 1e-3 / elapsed}
     chol_flops = n ** 3 / 3.0
     launches = max(prof["launches"], 1)
     avg_ms = prof["ms"] / launches
@@ -478,7 +748,8 @@ def main():
                      "frac": achieved / PEAK_FP64_TFLOPS, "traffic": measured_traffic(n, args.tile),
                      "traffic_unit": "bytes per launch (HBM, rocprofv3 FETCH_SIZE x2.0 + WRITE_SIZE x1.0)",
                      "launches": prof["launches"], "avg_launch_ms": avg_ms,
-                     "flops_per_launch": avg_flops},
+                     "flops_per_launch": avg_flops,
+                     "bulk_only": rate(bulk), "critical_column_only": rate(crit)},
     }
     if not args.no_mixed:
         out["mixed"] = mixed_legs(g, ctx, xd, yd, ed, zd, theta, tuple(args.theta_b), args, res, step_s, log)
@@ -489,9 +760,17 @@ def main():
         out["graph_replay"] = graph_leg(g, ctx, args, log)
     if not args.no_mle:
         out["mle"] = mle_leg(g, ctx, args, log)
+    if not args.no_small:
+        out["n1600"] = small_leg(g, ctx, args, log)
+    if not args.no_n40k:
+        out["n40000"] = n40k_leg(g, ctx, args, log)
     if not args.no_serve:
         out["serving"] = serving_leg(g, ctx, args, log)
     ctx.close()
+    if not args.no_n150k:
+        del xd, yd, ed, zd
+        torch.cuda.empty_cache()
+        out["n150000"] = n150k_leg(g, args, log)
     if not args.no_cpu_baseline:
         log("timing the oracle on the host")
         out["cpu_baseline"] = cpu_baseline(n, theta)

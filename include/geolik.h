@@ -47,7 +47,8 @@ typedef enum {
     GL_EBUSY = -4,      /* lq_poll: request still pending */
     GL_ECANCELED = -5,  /* request cancelled or queue destroyed */
     GL_ETIMEDOUT = -6,  /* lq_wait: timeout elapsed */
-    GL_ENODEV = -7      /* no usable gfx950 device */
+    GL_ENODEV = -7,     /* no usable gfx950 device */
+    GL_EVICTED = -9     /* a factor kept through the queue was released by its admission */
 } gl_status;
 
 typedef enum {
@@ -203,8 +204,9 @@ int loglik_eval(gl_context *ctx, const double *x, const double *y, const double 
  * covariances between new location k and the n observed ones; the m
  * right-hand sides are solved together on the matrix cores, 512 at a time.
  * Asynchronous on `stream`.
- * Errors: GL_EINVAL for a NULL factor, m < 1 or NULL pointers; GL_ENOMEM
- * when the variance workspace (n·min(m, 512) doubles) does not fit.
+ * Errors: GL_EINVAL for a NULL or unknown factor, m < 1 or NULL pointers;
+ * GL_ENOMEM when the variance workspace (n·min(m, 512) doubles) does not fit;
+ * GL_EVICTED for a queue-kept factor whose memory the queue released.
  */
 int krige_predict(gl_context *ctx, gl_factor *factor, const double *xnew, const double *ynew,
                   int64_t m, double *znew, double *var, void *stream);
@@ -235,7 +237,8 @@ int krige_cv(gl_context *ctx, const double *x, const double *y, const double *z,
              gl_theta theta, const gl_opts *opts, const int32_t *fold_h, int32_t k, double *mse_h,
              double *pred, void *stream);
 
-/* Release a factor returned by loglik_eval. */
+/* Release a factor returned by loglik_eval or through the request queue
+ * (also one the queue has evicted). */
 int gl_factor_release(gl_context *ctx, gl_factor *factor);
 
 /* Copy the lower-triangular factor L of `factor` into a dense column-major
@@ -286,7 +289,16 @@ void lq_config_default(lq_config *cfg);
 int lq_create(gl_context *ctx, const lq_config *cfg, lq_queue **q_h);
 
 /* Enqueue l(θ) on dataset ds; thread-safe.  *ticket_h identifies the request.
- * opts may be NULL (defaults; keep_factor and graph are ignored by the queue).
+ * opts may be NULL (defaults; graph is ignored by the queue).
+ * keep_factor = 1: a successful request's result carries its factor (for
+ * krige_predict, Alg. 3), owned by the caller until gl_factor_release.  Its
+ * device memory counts against the queue's HBM budget; when admitting a
+ * request needs room, the queue first drops idle workspaces, then releases
+ * the memory of the factors it handed out, least recently used first (a
+ * kriging call marks a use), waiting for kernels still reading them.  Calls on
+ * a released factor return GL_EVICTED; its handle stays valid until
+ * gl_factor_release.  Factors outlive the queue (lq_destroy makes them
+ * permanent).
  * Errors: GL_EINVAL for an unknown dataset, bad θ or options, or ind_tiles != 0
  * (the independent-blocks approximation is a direct call only); GL_ECANCELED
  * once the queue is being destroyed. */
@@ -308,6 +320,13 @@ int lq_cancel(lq_queue *q, uint64_t ticket);
  * requests resident at once, fused launches issued. Any pointer may be NULL. */
 int lq_stats(lq_queue *q, uint64_t *completed, size_t *peak_bytes, int32_t *peak_inflight,
              uint64_t *fused_launches);
+
+/* Overhead of the fused path since creation: ticks issued, host time spent
+ * building and enqueuing them (µs, summed), device time from a tick's first
+ * to its last command (ms, summed over retired ticks; the two cohorts overlap,
+ * so the sum may exceed the wall time) and device idle time between
+ * consecutive ticks of one cohort (ms, summed).  Any pointer may be NULL. */
+int lq_tick_stats(lq_queue *q, uint64_t *ticks, double *host_us, double *device_ms, double *gap_ms);
 
 /* Stop the scheduler: requests not yet started are cancelled, running ones are
  * drained, then the thread exits and the queue is freed. */
@@ -336,13 +355,30 @@ int gl_precision_stats(gl_context *ctx, int64_t *tiles_h, double *work_h, double
  * 3 = FP16 16x16x32. */
 int gl_selftest(gl_context *ctx, int32_t which, double *out_h, int64_t cap);
 
-/* Kernel timing of the trailing-update launches (the dominant kernel family).
- * While enabled, every trailing launch of the direct calls is bracketed by
- * HIP events on the stream it runs on.  gl_profile_read synchronises the
- * device and returns the summed launch durations (ms), the algorithmic flops
- * of those launches (2b³ per off-diagonal tile update, b²(b+1) per diagonal
- * tile update) and the launch count since the last read, then resets them. */
+/* Kernel timing of binary64 evaluations by phase of Alg. 2.  While enabled,
+ * kernel launches of the direct calls are bracketed by HIP events on the
+ * stream they run on: on = 1 the trailing updates only (the dominant kernel
+ * family), on = 2 every phase below; 0 switches timing off.  Mixed-precision
+ * evaluations are timed in no phase.  Phases run on two streams (critical
+ * path and lookahead), so summed durations may exceed the wall time. */
+enum {
+    GL_PHASE_GEN = 0,        /* Σ(θ) tile generation (Eq. 2) */
+    GL_PHASE_POTRF = 1,      /* diagonal-tile factorisations (b³/3 flops each) */
+    GL_PHASE_TRSM = 2,       /* panel solves (b³ flops per panel tile) */
+    GL_PHASE_SOLVE = 3,      /* forward solve w = L⁻¹Z (2b² flops per tile) */
+    GL_PHASE_TRAIL_CRIT = 4, /* trailing update of the next tile column, critical path */
+    GL_PHASE_TRAIL_BULK = 5, /* trailing update of the other columns, lookahead stream */
+    GL_PHASE_REDUCE = 6,     /* log|Σ|, ZᵀΣ⁻¹Z and l(θ) (Eq. 1) */
+    GL_NPHASE = 7
+};
 int gl_profile_enable(gl_context *ctx, int32_t on);
+/* Synchronises the device and returns, per phase (GL_NPHASE values each; any
+ * pointer may be NULL), the summed launch durations (ms), the algorithmic
+ * flops of those launches (trailing: 2b³ per off-diagonal tile update, b²(b+1)
+ * per diagonal tile update; generation and reduction: 0) and the launch count
+ * since the last read, then resets them. */
+int gl_profile_phases(gl_context *ctx, double *ms_h, double *flops_h, int64_t *launches_h);
+/* The same for the two trailing phases together (one value each). */
 int gl_profile_read(gl_context *ctx, double *ms_h, double *flops_h, int64_t *launches_h);
 
 #ifdef __cplusplus

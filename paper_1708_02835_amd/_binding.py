@@ -21,6 +21,7 @@ GL_EBUSY = -4
 GL_ECANCELED = -5
 GL_ETIMEDOUT = -6
 GL_ENODEV = -7
+GL_EVICTED = -9
 
 GL_FP64 = 0
 GL_MIXED_FP32 = 1
@@ -96,6 +97,7 @@ _SIGNATURES = {
     "lq_poll": (_I32, [_P, _U64, ctypes.POINTER(gl_result)]),
     "lq_wait": (_I32, [_P, _U64, ctypes.POINTER(gl_result), _I64]),
     "lq_cancel": (_I32, [_P, _U64]),
+    "lq_tick_stats": (_I32, [_P, ctypes.POINTER(_U64), ctypes.POINTER(_D), ctypes.POINTER(_D), ctypes.POINTER(_D)]),
     "lq_stats": (_I32, [_P, ctypes.POINTER(_U64), ctypes.POINTER(_SZ), ctypes.POINTER(_I32), ctypes.POINTER(_U64)]),
     "lq_destroy": (_I32, [_P]),
     "gl_selftest": (_I32, [_P, _I32, ctypes.POINTER(_D), _I64]),
@@ -103,6 +105,7 @@ _SIGNATURES = {
     "gl_morton_order": (_I32, [_P, _P, _P, _I64, _P, _P]),
     "gl_precision_stats": (_I32, [_P, ctypes.POINTER(_I64), ctypes.POINTER(_D), ctypes.POINTER(_D)]),
     "gl_profile_read": (_I32, [_P, ctypes.POINTER(_D), ctypes.POINTER(_D), ctypes.POINTER(_I64)]),
+    "gl_profile_phases": (_I32, [_P, _P, _P, _P]),
 }
 
 
@@ -395,6 +398,13 @@ def lq_stats(q: int) -> dict:
             "fused_launches": int(fl.value)}
 
 
+def lq_tick_stats(q: int) -> dict:
+    t, h, d, gp = _U64(), _D(), _D(), _D()
+    _check(lib().lq_tick_stats(q, ctypes.byref(t), ctypes.byref(h), ctypes.byref(d), ctypes.byref(gp)),
+           "lq_tick_stats")
+    return {"ticks": int(t.value), "host_us": h.value, "device_ms": d.value, "gap_ms": gp.value}
+
+
 def lq_destroy(q: int) -> None:
     _check(lib().lq_destroy(q), "lq_destroy")
 
@@ -406,8 +416,20 @@ def gl_selftest(ctx: Context, which: int):
     return np.frombuffer(out, dtype=np.float64).copy()
 
 
-def gl_profile_enable(ctx: Context, on: bool = True) -> None:
-    _check(lib().gl_profile_enable(ctx.handle, 1 if on else 0), "gl_profile_enable")
+PHASES = ("gen", "potrf", "trsm", "solve", "trail_crit", "trail_bulk", "reduce")  # GL_PHASE_* order
+
+
+def gl_profile_enable(ctx: Context, on=True) -> None:
+    """on: False/0 off, True/1 the trailing updates, 2 every phase."""
+    _check(lib().gl_profile_enable(ctx.handle, int(on)), "gl_profile_enable")
+
+
+def gl_profile_phases(ctx: Context) -> dict:
+    """Per phase (PHASES): summed launch ms, algorithmic flops and launches since the last read."""
+    k = len(PHASES)
+    ms, fl, n = (_D * k)(), (_D * k)(), (_I64 * k)()
+    _check(lib().gl_profile_phases(ctx.handle, ms, fl, n), "gl_profile_phases")
+    return {p: {"ms": ms[i], "flops": fl[i], "launches": int(n[i])} for i, p in enumerate(PHASES)}
 
 
 def gl_profile_read(ctx: Context) -> dict:

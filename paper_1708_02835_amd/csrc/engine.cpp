@@ -144,19 +144,55 @@ void Lanes::destroy()
     fork = panel = bulk = join = nullptr;
 }
 
-int Prof::bracket(hipStream_t s, bool start)
+hipEvent_t Prof::take()
 {
-    (void)start;
-    hipEvent_t e;
+    hipEvent_t e = nullptr;
     if (!pool.empty()) {
         e = pool.back();
         pool.pop_back();
-    } else {
-        GL_HIP_TRY(hipEventCreate(&e));
+    } else if (hipEventCreate(&e) != hipSuccess) {
+        e = nullptr;
     }
-    GL_HIP_TRY(hipEventRecord(e, s));
-    pending.push_back(e);
-    return GL_OK;
+    return e;
+}
+
+// Timing is best effort: a mark whose events could not be created or
+// recorded is dropped, the launch itself is unaffected.
+void Prof::begin(hipStream_t s, Mark &m)
+{
+    m.a = take();
+    if (m.a && hipEventRecord(m.a, s) != hipSuccess) {
+        pool.push_back(m.a);
+        m.a = nullptr;
+    }
+}
+
+void Prof::end(hipStream_t s, Mark &m, int phase, double flops)
+{
+    if (!m.a) return;
+    m.b = take();
+    if (!m.b || hipEventRecord(m.b, s) != hipSuccess) {
+        pool.push_back(m.a);
+        if (m.b) pool.push_back(m.b);
+        return;
+    }
+    m.phase = phase;
+    m.flops = flops;
+    pending.push_back(m);
+}
+
+// Runs launch() on s, bracketed by timing events when phase is profiled.
+template <class F>
+static void timed(Prof *prof, int phase, double flops, hipStream_t s, F &&launch)
+{
+    if (!prof || !prof->wants(phase)) {
+        launch();
+        return;
+    }
+    Prof::Mark m;
+    prof->begin(s, m);
+    launch();
+    prof->end(s, m, phase, flops);
 }
 
 // Algorithmic flops of the trailing update of step k over tile columns
@@ -171,13 +207,8 @@ static double trailing_flops(int64_t nt, int64_t jbeg, int64_t jend, int b)
 
 static void trailing(Lanes &ln, Work &w, int64_t k, int64_t jbeg, int64_t jend, hipStream_t s, bool critical)
 {
-    if (ln.prof) ln.prof->bracket(s, true);
-    launch_trailing(w.tiles, w.b, w.nt, k, jbeg, jend, w.info, critical, s);
-    if (ln.prof) {
-        ln.prof->bracket(s, false);
-        ln.prof->flops += trailing_flops(w.nt, jbeg, jend, w.b);
-        ln.prof->launches += 1;
-    }
+    timed(ln.prof, critical ? GL_PHASE_TRAIL_CRIT : GL_PHASE_TRAIL_BULK, trailing_flops(w.nt, jbeg, jend, w.b), s,
+          [&] { launch_trailing(w.tiles, w.b, w.nt, k, jbeg, jend, w.info, critical, s); });
 }
 
 int factorize(Lanes &ln, Work &w, hipStream_t s, bool solve)
@@ -185,13 +216,24 @@ int factorize(Lanes &ln, Work &w, hipStream_t s, bool solve)
     hipStream_t la = ln.la;
     GL_HIP_TRY(hipEventRecord(ln.fork, s));
     GL_HIP_TRY(hipStreamWaitEvent(la, ln.fork, 0));
+    const double b3 = (double)w.b * w.b * w.b;
     for (int64_t k = 0; k < w.nt; ++k) {
-        launch_potrf(w.tiles, w.b, k, w.n, w.info, w.logsum, w.dinv_k(k), s);
-        if (solve) launch_fwd_diag(w.tiles, w.b, k, w.n, w.v, w.quad, w.dinv_k(k), w.info, s);
-        launch_trsm(w.tiles, w.b, w.nt, k, w.dinv_k(k), w.info, s);
-        if (solve) launch_fwd_update(w.tiles, w.b, w.nt, k, w.v, w.info, s);
+        const double below = (double)(w.nt - k - 1);
+        timed(ln.prof, GL_PHASE_POTRF, b3 / 3.0, s,
+              [&] { launch_potrf(w.tiles, w.b, k, w.n, w.info, w.logsum, w.dinv_k(k), s); });
+        timed(ln.prof, GL_PHASE_TRSM, b3 * below, s,
+              [&] { launch_trsm(w.tiles, w.b, w.nt, k, w.dinv_k(k), w.info, s); });
+        // Panel k is final here: the bulk update may start.  The forward solve
+        // of step k only reads column k (and owns v), so it follows the panel
+        // event, off the path that feeds the lookahead stream.
+        if (k + 1 < w.nt) GL_HIP_TRY(hipEventRecord(ln.panel, s));
+        if (solve) {
+            timed(ln.prof, GL_PHASE_SOLVE, (double)w.b * w.b, s,
+                  [&] { launch_fwd_diag(w.tiles, w.b, k, w.n, w.v, w.quad, w.dinv_k(k), w.info, s); });
+            timed(ln.prof, GL_PHASE_SOLVE, 2.0 * w.b * w.b * below, s,
+                  [&] { launch_fwd_update(w.tiles, w.b, w.nt, k, w.v, w.info, s); });
+        }
         if (k + 1 < w.nt) {
-            GL_HIP_TRY(hipEventRecord(ln.panel, s));
             if (k > 0) GL_HIP_TRY(hipStreamWaitEvent(s, ln.bulk, 0));
             trailing(ln, w, k, k + 1, k + 1, s, true);
             if (k + 2 < w.nt) {
@@ -225,6 +267,7 @@ const char *gl_status_string(int status)
     case GL_ECANCELED: return "request cancelled";
     case GL_ETIMEDOUT: return "timed out";
     case GL_ENODEV: return "no usable gfx950 device";
+    case GL_EVICTED: return "factor released by the request queue's memory admission";
     default: return "unknown status";
     }
 }
@@ -301,6 +344,8 @@ void gl_context_destroy(gl_context *c)
     hipDeviceSynchronize();
     c->ws.release();
     if (c->ind_buf) hipFree(c->ind_buf);
+    if (c->ind_host) hipHostFree(c->ind_host);
+    if (c->ind_done) hipEventDestroy(c->ind_done);
     graph_drop(c);
     if (c->gs) hipStreamDestroy(c->gs);
     for (hipEvent_t e : c->gev)
@@ -309,13 +354,17 @@ void gl_context_destroy(gl_context *c)
     if (c->theta_d) hipFree(c->theta_d);
     for (gl_factor *f : c->factors) {
         f->w.release();
+        if (f->used) hipEventDestroy(f->used);
         delete f;
     }
     c->factors.clear();
     serve_context_cleanup(c);
     c->lanes.destroy();
     for (hipEvent_t e : c->prof.pool) hipEventDestroy(e);
-    for (hipEvent_t e : c->prof.pending) hipEventDestroy(e);
+    for (const Prof::Mark &m : c->prof.pending) {
+        hipEventDestroy(m.a);
+        hipEventDestroy(m.b);
+    }
     if (c->res_h) hipHostFree(c->res_h);
     delete c;
 }
@@ -350,13 +399,15 @@ int eval_launch(Lanes &ln, Work &w, gl_theta th, const gl_opts &o, hipStream_t s
     launch_fill(reinterpret_cast<double *>(w.info), 1, 0.0, s);
     int rc;
     if (o.precision == GL_FP64) {
-        launch_gen_tiles(w.tiles, w.x, w.y, w.n, w.b, w.nt, th, geom_of(o), nullptr, s);
+        timed(ln.prof, GL_PHASE_GEN, 0.0, s,
+              [&] { launch_gen_tiles(w.tiles, w.x, w.y, w.n, w.b, w.nt, th, geom_of(o), nullptr, s); });
         rc = factorize(ln, w, s, true);
     } else {
         rc = mixed_factorize(ln, w, th, o, s, plan_out);
     }
     if (rc != GL_OK) return rc;
-    launch_final_reduce(w.logsum, w.quad, w.nt, w.n, w.info, w.res, s);
+    timed(o.precision == GL_FP64 ? ln.prof : nullptr, GL_PHASE_REDUCE, 0.0, s,
+          [&] { launch_final_reduce(w.logsum, w.quad, w.nt, w.n, w.info, w.res, s); });
     GL_HIP_TRY(hipGetLastError());
     GL_HIP_TRY(hipMemcpyAsync(out_h, w.res, sizeof(DevResult), hipMemcpyDeviceToHost, s));
     return GL_OK;
@@ -472,6 +523,61 @@ static int graph_eval(gl_context *ctx, Work &w, const double *x, const double *y
     return GL_OK;
 }
 
+gl_factor *factor_adopt(gl_context *ctx, const Work &w, gl_theta th, const gl_opts &o, const void *queue)
+{
+    gl_factor *f = new (std::nothrow) gl_factor();
+    if (!f) return nullptr;
+    if (hipEventCreateWithFlags(&f->used, hipEventDisableTiming) != hipSuccess) {
+        delete f;
+        return nullptr;
+    }
+    f->ctx = ctx;
+    f->theta = th;
+    f->opts = o;
+    f->opts.keep_factor = 1;
+    f->w = w;
+    f->queue = queue;
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    f->last_use = ++ctx->use_clock;
+    ctx->factors.push_back(f);
+    return f;
+}
+
+size_t kept_bytes(gl_context *ctx, const void *queue)
+{
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    size_t t = 0;
+    for (const gl_factor *f : ctx->factors)
+        if (f->queue == queue && !f->evicted) t += f->w.bytes();
+    return t;
+}
+
+size_t evict_factors(gl_context *ctx, const void *queue, size_t want)
+{
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    size_t freed = 0;
+    while (freed < want) {
+        gl_factor *lru = nullptr;
+        for (gl_factor *f : ctx->factors)
+            if (f->queue == queue && !f->evicted && (!lru || f->last_use < lru->last_use)) lru = f;
+        if (!lru) break;
+        if (lru->used) (void)hipEventSynchronize(lru->used);  // kernels still reading it
+        const size_t b = lru->w.bytes();
+        ctx->used -= b;
+        lru->w.release();
+        lru->evicted = true;
+        freed += b;
+    }
+    return freed;
+}
+
+void detach_factors(gl_context *ctx, const void *queue)
+{
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    for (gl_factor *f : ctx->factors)
+        if (f->queue == queue) f->queue = nullptr;
+}
+
 void fill_result(gl_result *res, const DevResult &d, int b)
 {
     res->loglik = d.loglik;
@@ -564,6 +670,7 @@ int gl_factor_release(gl_context *ctx, gl_factor *f)
     hipDeviceSynchronize();
     ctx->used -= f->w.bytes();
     f->w.release();
+    if (f->used) hipEventDestroy(f->used);
     delete f;
     return GL_OK;
 }
@@ -578,17 +685,24 @@ int gl_factor_shape(const gl_factor *f, int64_t *n, int32_t *tile)
 
 int gl_factor_to_dense(gl_context *ctx, gl_factor *f, double *out, int64_t ld, void *stream)
 {
-    if (!ctx || !f || !out || ld < f->w.n) return GL_EINVAL;
+    if (!ctx || !f || !out) return GL_EINVAL;
+    FactorUse use(ctx, f);
+    if (use.status != GL_OK) return use.status;
+    if (ld < f->w.n) return GL_EINVAL;
     GL_HIP_TRY(hipSetDevice(ctx->device));
-    launch_tiles_to_dense(f->w.tiles, f->w.b, f->w.n, out, ld, static_cast<hipStream_t>(stream));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    launch_tiles_to_dense(f->w.tiles, f->w.b, f->w.n, out, ld, s);
     GL_HIP_TRY(hipGetLastError());
+    use.finish(s);
     return GL_OK;
 }
 
 int krige_predict(gl_context *ctx, gl_factor *f, const double *xnew, const double *ynew, int64_t m,
                   double *znew, double *var, void *stream)
 {
-    if (!ctx || !f || f->ctx != ctx || !xnew || !ynew || !znew || m < 1) return GL_EINVAL;
+    if (!ctx || !f || !xnew || !ynew || !znew || m < 1) return GL_EINVAL;
+    FactorUse use(ctx, f);
+    if (use.status != GL_OK) return use.status;
     GL_HIP_TRY(hipSetDevice(ctx->device));
     hipStream_t s = static_cast<hipStream_t>(stream);
     Work &w = f->w;
@@ -628,6 +742,7 @@ int krige_predict(gl_context *ctx, gl_factor *f, const double *xnew, const doubl
     }
     GL_HIP_TRY(hipGetLastError());
     GL_HIP_TRY(hipFreeAsync(scratch, s));
+    use.finish(s);
     return GL_OK;
 }
 
@@ -750,30 +865,48 @@ int synth_generate(gl_context *ctx, const double *x, const double *y, const doub
 
 int gl_profile_enable(gl_context *ctx, int32_t on)
 {
-    if (!ctx) return GL_EINVAL;
+    if (!ctx || on < 0 || on > 2) return GL_EINVAL;
     ctx->lanes.prof = on ? &ctx->prof : nullptr;
+    ctx->prof.all = (on == 2);
     return GL_OK;
 }
 
-int gl_profile_read(gl_context *ctx, double *ms_h, double *flops_h, int64_t *launches_h)
+int gl_profile_phases(gl_context *ctx, double *ms_h, double *flops_h, int64_t *launches_h)
 {
     if (!ctx) return GL_EINVAL;
     GL_HIP_TRY(hipSetDevice(ctx->device));
     GL_HIP_TRY(hipDeviceSynchronize());
     Prof &p = ctx->prof;
-    double ms = 0.0;
-    for (size_t i = 0; i + 1 < p.pending.size(); i += 2) {
+    double ms[GL_NPHASE] = {}, fl[GL_NPHASE] = {};
+    int64_t cnt[GL_NPHASE] = {};
+    int rc = GL_OK;
+    for (const Prof::Mark &m : p.pending) {
         float t = 0.f;
-        GL_HIP_TRY(hipEventElapsedTime(&t, p.pending[i], p.pending[i + 1]));
-        ms += t;
+        if (hipEventElapsedTime(&t, m.a, m.b) != hipSuccess) rc = GL_EHIP;
+        ms[m.phase] += t;
+        fl[m.phase] += m.flops;
+        cnt[m.phase] += 1;
+        p.pool.push_back(m.a);
+        p.pool.push_back(m.b);
     }
-    if (ms_h) *ms_h = ms;
-    if (flops_h) *flops_h = p.flops;
-    if (launches_h) *launches_h = p.launches;
-    for (hipEvent_t e : p.pending) p.pool.push_back(e);
     p.pending.clear();
-    p.flops = 0.0;
-    p.launches = 0;
+    for (int i = 0; i < GL_NPHASE; ++i) {
+        if (ms_h) ms_h[i] = ms[i];
+        if (flops_h) flops_h[i] = fl[i];
+        if (launches_h) launches_h[i] = cnt[i];
+    }
+    return rc;
+}
+
+int gl_profile_read(gl_context *ctx, double *ms_h, double *flops_h, int64_t *launches_h)
+{
+    double ms[GL_NPHASE], fl[GL_NPHASE];
+    int64_t cnt[GL_NPHASE];
+    const int rc = gl_profile_phases(ctx, ms, fl, cnt);
+    if (rc != GL_OK) return rc;
+    if (ms_h) *ms_h = ms[GL_PHASE_TRAIL_CRIT] + ms[GL_PHASE_TRAIL_BULK];
+    if (flops_h) *flops_h = fl[GL_PHASE_TRAIL_CRIT] + fl[GL_PHASE_TRAIL_BULK];
+    if (launches_h) *launches_h = cnt[GL_PHASE_TRAIL_CRIT] + cnt[GL_PHASE_TRAIL_BULK];
     return GL_OK;
 }
 

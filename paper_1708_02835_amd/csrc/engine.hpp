@@ -5,6 +5,7 @@
 #include <mutex>
 #include <vector>
 
+#include "batch.hpp"
 #include "common.hpp"
 
 namespace gl {
@@ -63,13 +64,21 @@ struct Work {
     void release();
 };
 
-// Optional timing of trailing-update launches.
+// Optional kernel timing of the binary64 evaluations: HIP events around
+// launches, summed per phase (GL_PHASE_* of geolik.h) when read.
 struct Prof {
+    struct Mark {
+        hipEvent_t a = nullptr, b = nullptr;
+        int phase = 0;
+        double flops = 0.0;
+    };
     std::vector<hipEvent_t> pool;
-    std::vector<hipEvent_t> pending;  // start, stop pairs in launch order
-    double flops = 0.0;
-    int64_t launches = 0;
-    int bracket(hipStream_t s, bool start);
+    std::vector<Mark> pending;  // in launch order
+    bool all = false;           // every phase; otherwise the trailing updates only
+    bool wants(int phase) const { return all || phase == GL_PHASE_TRAIL_CRIT || phase == GL_PHASE_TRAIL_BULK; }
+    hipEvent_t take();
+    void begin(hipStream_t s, Mark &m);
+    void end(hipStream_t s, Mark &m, int phase, double flops);
 };
 
 // Side stream and events of one evaluation's step schedule (lookahead).
@@ -116,6 +125,17 @@ void serve_stop_queues(gl_context *ctx);  // destroys the context's live queues
 
 void fill_result(gl_result *res, const DevResult &d, int b);
 
+// Factors kept by the request queue (engine.cpp).  factor_adopt takes over
+// the device memory of w (a finished evaluation) as a new registered factor
+// that `queue` may evict; kept_bytes sums the live ones of a queue;
+// evict_factors releases them, least recently used first, until at least
+// `want` bytes are free or none is left, and returns the bytes released;
+// detach_factors makes a queue's factors permanent (the queue is going away).
+gl_factor *factor_adopt(gl_context *ctx, const Work &w, gl_theta th, const gl_opts &o, const void *queue);
+size_t kept_bytes(gl_context *ctx, const void *queue);
+size_t evict_factors(gl_context *ctx, const void *queue, size_t want);
+void detach_factors(gl_context *ctx, const void *queue);
+
 // Independent-blocks approximation (ind.cpp); o resolved and validated.
 int ind_eval(gl_context *ctx, const double *x, const double *y, const double *z, int64_t n, gl_theta th,
              const gl_opts &o, gl_result *res, hipStream_t s);
@@ -136,6 +156,14 @@ struct gl_factor {
     gl_theta theta{};
     gl_opts opts{};  // options of the evaluation (distance, precision, order)
     gl::Work w;
+    // Factors kept through the request queue: when the queue's admission needs
+    // room it releases their device memory, least recently used first; the
+    // handle stays valid (calls on it return GL_EVICTED) until
+    // gl_factor_release.  All four fields are guarded by ctx->mu.
+    const void *queue = nullptr;  // the queue that may evict it (NULL: never)
+    uint64_t last_use = 0;        // ctx->use_clock at creation or the last kriging call
+    hipEvent_t used = nullptr;    // recorded after the last kernels that read it
+    bool evicted = false;
 };
 
 struct gl_context {
@@ -149,9 +177,13 @@ struct gl_context {
     gl::DevResult *res_h = nullptr;  // pinned host copy of the last result
     std::mutex mu;                   // guards factors and datasets
     std::vector<gl_factor *> factors;
+    uint64_t use_clock = 0;          // orders factor uses for least-recently-used release
     gl::ServeState *serve = nullptr;
     void *ind_buf = nullptr;  // workspace of the independent-blocks evaluations
     size_t ind_cap = 0;
+    gl::BatchReq *ind_host = nullptr;  // pinned step descriptors of the IND launches
+    size_t ind_host_cap = 0;           // entries
+    hipEvent_t ind_done = nullptr;     // recorded after the last IND step's launches
     // replayed evaluation graph (gl_opts.graph): one entry, keyed by the
     // workspace geometry and the distance
     hipStream_t gs = nullptr;        // stream the graph is captured on and replayed on
@@ -164,3 +196,33 @@ struct gl_context {
     gl_theta *theta_h = nullptr;  // pinned
     gl_theta *theta_d = nullptr;  // device
 };
+
+namespace gl {
+
+// Held by a direct call while it reads a factor: keeps the queue from
+// evicting it, checks that it is one of ctx's live factors and records its
+// use.  finish(s) records, on the stream of the call's last kernel, the event
+// an eviction waits for.
+struct FactorUse {
+    std::unique_lock<std::mutex> lk;
+    gl_factor *f;
+    int status = GL_OK;
+    FactorUse(gl_context *ctx, gl_factor *fac) : lk(ctx->mu), f(fac)
+    {
+        bool found = false;
+        for (gl_factor *g : ctx->factors) found = found || g == fac;
+        if (!found || fac->ctx != ctx) {
+            status = GL_EINVAL;
+        } else if (fac->evicted) {
+            status = GL_EVICTED;
+        } else {
+            fac->last_use = ++ctx->use_clock;
+        }
+    }
+    void finish(hipStream_t s)
+    {
+        if (status == GL_OK && f->used) (void)hipEventRecord(f->used, s);
+    }
+};
+
+}  // namespace gl

@@ -132,23 +132,39 @@ static int ind_factor(gl_context *ctx, const double *x, const double *y, const d
         d.nt = ntb[i];
         d.npad = npb;
     }
-    // one host array per step: each must outlive its asynchronous copy
-    std::vector<std::vector<BatchReq>> steps((size_t)bt);
+    // The descriptors of every step go to pinned host memory owned by the
+    // context (one region per step), which the asynchronous copies read until
+    // the stream passes them; the previous call's copies are waited for
+    // before the memory is rewritten or replaced.
+    const size_t entries = (size_t)bt * (size_t)nblk;
+    if (ctx->ind_done) GL_HIP_TRY(hipEventSynchronize(ctx->ind_done));
+    else GL_HIP_TRY(hipEventCreateWithFlags(&ctx->ind_done, hipEventDisableTiming));
+    if (entries > ctx->ind_host_cap) {
+        if (ctx->ind_host) GL_HIP_TRY(hipHostFree(ctx->ind_host));
+        ctx->ind_host = nullptr;
+        ctx->ind_host_cap = 0;
+        GL_HIP_TRY(hipHostMalloc(reinterpret_cast<void **>(&ctx->ind_host), entries * sizeof(BatchReq),
+                                 hipHostMallocDefault));
+        ctx->ind_host_cap = entries;
+    }
+    BatchReq *h = ctx->ind_host;
     for (int64_t k = 0; k < bt; ++k) {
-        std::vector<BatchReq> &h = steps[k];
+        int cnt = 0;
         for (int64_t i = 0; i < nblk; ++i) {
             if (k >= ntb[i]) continue;  // the last block may have fewer tile columns
-            BatchReq d = proto[i];
+            BatchReq &d = h[cnt++];
+            d = proto[i];
             d.dinv = proto[i].dinv + k * 64 * (int64_t)b;
             d.k = k;
             d.is_new = k == 0;
             d.finishing = k == ntb[i] - 1;
-            h.push_back(d);
         }
-        if (h.empty()) break;
-        const int rc = enqueue_step(h.data(), ddesc, (int)h.size(), b, s, nullptr);
+        if (cnt == 0) break;
+        const int rc = enqueue_step(h, ddesc, cnt, b, s, nullptr);
         if (rc != GL_OK) return rc;
+        h += cnt;
     }
+    GL_HIP_TRY(hipEventRecord(ctx->ind_done, s));
     ind_total_kernel<<<1, 64, 0, s>>>(bres, nblk, block, total);
     GL_HIP_TRY(hipGetLastError());
     p.b = b;

@@ -134,7 +134,8 @@ struct TickBuf {
     BatchReq *host = nullptr;  // pinned
     BatchReq *dev = nullptr;
     DevResult *res_h = nullptr;  // pinned, one per finishing request
-    hipEvent_t done = nullptr;
+    hipEvent_t start = nullptr;  // recorded before the tick's first command (timing)
+    hipEvent_t done = nullptr;   // recorded after its last (timing)
     bool busy = false;
     std::vector<Resident> finishing;
 };
@@ -150,6 +151,7 @@ struct Cohort {
     TickBuf ring[TICK_RING];
     int ring_next = 0;
     std::deque<int> ticks;  // ring indices in flight, oldest first
+    hipEvent_t last_done = nullptr;  // done event of the last retired tick (gap timing)
 };
 
 }  // namespace
@@ -171,6 +173,11 @@ struct lq_queue {
     int inflight = 0, peak_inflight = 0;
     size_t peak_bytes = 0;
     uint64_t completed = 0, fused = 0;
+    // tick overhead: host time spent building and enqueuing ticks, device time
+    // of the ticks (first to last command) and device idle time between
+    // consecutive ticks of a cohort
+    uint64_t ticks = 0;
+    double host_us = 0.0, device_ms = 0.0, gap_ms = 0.0;
     std::thread thr;
 };
 
@@ -190,7 +197,7 @@ size_t slot_bytes(const Slot &sl) { return sl.w.bytes(); }
 
 size_t held_bytes(const lq_queue *q)
 {
-    size_t t = 0;
+    size_t t = kept_bytes(q->ctx, q);  // factors handed out and not yet evicted
     for (const Slot &sl : q->slots) t += slot_bytes(sl);
     for (const Work *w : q->pool) t += w->bytes();
     for (const Cohort &c : q->co) {
@@ -235,6 +242,41 @@ int take_work(lq_queue *q, int64_t n, Work *&out)
     return GL_OK;
 }
 
+// A finished request that asked for its factor: the workspace w becomes a
+// registered factor the queue may evict (least recently used first) when its
+// admission needs room.  Returns false (w stays with the queue, the result
+// carries no factor) when the factor object cannot be made.
+bool hand_over(lq_queue *q, Request *r, Work &w)
+{
+    gl_factor *f = factor_adopt(q->ctx, w, r->th, r->o, q);
+    if (!f) return false;
+    r->res.factor = f;
+    w = Work{};
+    return true;
+}
+
+// Frees memory for a request needing `need` more bytes: idle pooled and slot
+// workspaces first (keep_slot's excepted), then factors handed out by this
+// queue, least recently used first.  Returns whether held + need now fits.
+bool make_room(lq_queue *q, size_t need, size_t mine, const Slot *keep_slot)
+{
+    for (Work *w : q->pool) {
+        q->ctx->used -= w->bytes();
+        w->release();
+        delete w;
+    }
+    q->pool.clear();
+    for (Slot &sl : q->slots)
+        if (!sl.req && &sl != keep_slot && slot_bytes(sl)) {
+            q->ctx->used -= slot_bytes(sl);
+            sl.w.release();
+        }
+    size_t held = held_bytes(q);
+    if (held - mine + need <= q->budget) return true;
+    evict_factors(q->ctx, q, held - mine + need - q->budget);
+    return held_bytes(q) - mine + need <= q->budget;
+}
+
 // Enqueue one tick of cohort c: every resident advances by one step.
 int build_tick(lq_queue *q, Cohort &co)
 {
@@ -269,6 +311,8 @@ int build_tick(lq_queue *q, Cohort &co)
     }
     hipStream_t s = co.s;
     int launches = 0;
+    const auto h0 = std::chrono::steady_clock::now();
+    GL_HIP_TRY(hipEventRecord(tb.start, s));
     const int rc = enqueue_step(tb.host, tb.dev, count, TICK_B, s, &launches);
     if (rc != GL_OK) return rc;
     tb.finishing.clear();
@@ -293,6 +337,8 @@ int build_tick(lq_queue *q, Cohort &co)
     co.ticks.push_back(co.ring_next);
     co.ring_next = (co.ring_next + 1) % TICK_RING;
     q->fused += launches;
+    q->ticks += 1;
+    q->host_us += std::chrono::duration<double, std::micro>(std::chrono::steady_clock::now() - h0).count();
     return GL_OK;
 }
 
@@ -303,6 +349,12 @@ void retire_ticks(lq_queue *q, Cohort &co)
         TickBuf &tb = co.ring[co.ticks.front()];
         hipError_t e = hipEventQuery(tb.done);
         if (e == hipErrorNotReady) return;
+        float ms = 0.f;
+        if (e == hipSuccess && hipEventElapsedTime(&ms, tb.start, tb.done) == hipSuccess) q->device_ms += ms;
+        if (e == hipSuccess && co.last_done && hipEventElapsedTime(&ms, co.last_done, tb.start) == hipSuccess &&
+            ms > 0.f)
+            q->gap_ms += ms;
+        co.last_done = tb.done;
         for (size_t i = 0; i < tb.finishing.size(); ++i) {
             Resident &r = tb.finishing[i];
             Request *req = r.req;
@@ -318,9 +370,13 @@ void retire_ticks(lq_queue *q, Cohort &co)
                 req->res.info = d.info;
                 req->res.tile = TICK_B;
                 req->res.factor = nullptr;
+                if (!d.info && req->o.keep_factor && hand_over(q, req, *r.w)) {
+                    delete r.w;  // its memory now belongs to the factor
+                    r.w = nullptr;
+                }
                 finish(q, req, d.info ? GL_NOT_SPD : GL_OK);
             }
-            q->pool.push_back(r.w);
+            if (r.w) q->pool.push_back(r.w);
         }
         tb.finishing.clear();
         tb.busy = false;
@@ -368,6 +424,7 @@ void scheduler(lq_queue *q)
             r->res.info = sl.res_h->info;
             r->res.tile = sl.w.b;
             r->res.factor = nullptr;
+            if (!sl.res_h->info && r->o.keep_factor) hand_over(q, r, sl.w);
             finish(q, r, sl.res_h->info ? GL_NOT_SPD : GL_OK);
         }
         for (Cohort &c : q->co) retire_ticks(q, c);
@@ -382,25 +439,11 @@ void scheduler(lq_queue *q)
                 const size_t need = work_bytes(head->ds->n, TICK_B, GL_FP64);
                 bool have = false;
                 for (Work *w : q->pool) have = have || w->bytes() >= need;
-                if (!have && held_bytes(q) + need > q->budget) {
-                    // give back idle memory: pooled workspaces and idle slots
-                    for (Work *w : q->pool) {
-                        q->ctx->used -= w->bytes();
-                        w->release();
-                        delete w;
-                    }
-                    q->pool.clear();
-                    for (Slot &sl : q->slots)
-                        if (!sl.req && slot_bytes(sl)) {
-                            q->ctx->used -= slot_bytes(sl);
-                            sl.w.release();
-                        }
-                    if (held_bytes(q) + need > q->budget) {
-                        if (q->inflight > 0) break;  // wait for running requests to free memory
-                        q->queue.pop_front();
-                        finish(q, head, GL_ENOMEM);  // larger than the whole budget
-                        continue;
-                    }
+                if (!have && held_bytes(q) + need > q->budget && !make_room(q, need, 0, nullptr)) {
+                    if (q->inflight > 0) break;  // wait for running requests to free memory
+                    q->queue.pop_front();
+                    finish(q, head, GL_ENOMEM);  // larger than the whole budget
+                    continue;
                 }
                 Work *w = nullptr;
                 int rc = take_work(q, head->ds->n, w);
@@ -431,20 +474,11 @@ void scheduler(lq_queue *q)
             const size_t need = work_bytes(n, pick_tile(n, r->o.tile), r->o.precision);
             size_t held = held_bytes(q);
             const size_t mine = slot_bytes(*free_slot);
-            if (need > mine && held - mine + need > q->budget) {
-                // give back the memory of idle slots first
-                for (Slot &sl : q->slots)
-                    if (!sl.req && &sl != free_slot && slot_bytes(sl)) {
-                        q->ctx->used -= slot_bytes(sl);
-                        sl.w.release();
-                    }
-                held = held_bytes(q);
-                if (held - mine + need > q->budget) {
-                    if (q->inflight > 0) break;  // wait for running requests to free memory
-                    q->queue.pop_front();
-                    finish(q, r, GL_ENOMEM);  // larger than the whole budget
-                    continue;
-                }
+            if (need > mine && held - mine + need > q->budget && !make_room(q, need, mine, free_slot)) {
+                if (q->inflight > 0) break;  // wait for running requests to free memory
+                q->queue.pop_front();
+                finish(q, r, GL_ENOMEM);  // larger than the whole budget
+                continue;
             }
             q->queue.pop_front();
             r->state = RUNNING;
@@ -605,7 +639,7 @@ int lq_create(gl_context *ctx, const lq_config *cfg, lq_queue **out)
                  hipMalloc(reinterpret_cast<void **>(&tb.dev), TICK_MAX * sizeof(BatchReq)) == hipSuccess &&
                  hipHostMalloc(reinterpret_cast<void **>(&tb.res_h), TICK_MAX * sizeof(DevResult),
                                hipHostMallocDefault) == hipSuccess &&
-                 hipEventCreateWithFlags(&tb.done, hipEventDisableTiming) == hipSuccess;
+                 hipEventCreate(&tb.start) == hipSuccess && hipEventCreate(&tb.done) == hipSuccess;
         if (!ok) {
             q->stop = true;
             lq_destroy(q);
@@ -628,7 +662,6 @@ int lq_submit(lq_queue *q, uint64_t ds, gl_theta th, const gl_opts *opts, uint64
     gl_opts o;
     gl_opts_default(&o);
     if (opts) o = *opts;
-    o.keep_factor = 0;
     o.graph = 0;  // the queue schedules its own launches
     if (!valid_opts(o) || !valid_theta_for(th, o) || o.ind_tiles != 0) return GL_EINVAL;
     o = resolved_opts(o);
@@ -727,6 +760,17 @@ int lq_stats(lq_queue *q, uint64_t *completed, size_t *peak_bytes, int32_t *peak
     return GL_OK;
 }
 
+int lq_tick_stats(lq_queue *q, uint64_t *ticks, double *host_us, double *device_ms, double *gap_ms)
+{
+    if (!q) return GL_EINVAL;
+    std::lock_guard<std::mutex> lk(q->mu);
+    if (ticks) *ticks = q->ticks;
+    if (host_us) *host_us = q->host_us;
+    if (device_ms) *device_ms = q->device_ms;
+    if (gap_ms) *gap_ms = q->gap_ms;
+    return GL_OK;
+}
+
 int lq_destroy(lq_queue *q)
 {
     if (!q) return GL_EINVAL;
@@ -764,6 +808,7 @@ int lq_destroy(lq_queue *q)
             if (tb.host) hipHostFree(tb.host);
             if (tb.dev) hipFree(tb.dev);
             if (tb.res_h) hipHostFree(tb.res_h);
+            if (tb.start) hipEventDestroy(tb.start);
             if (tb.done) hipEventDestroy(tb.done);
         }
         if (c.s) hipStreamDestroy(c.s);
@@ -778,6 +823,7 @@ int lq_destroy(lq_queue *q)
         if (sl.res_h) hipHostFree(sl.res_h);
     }
     for (auto &kv : q->reqs) delete kv.second;
+    detach_factors(q->ctx, q);  // factors already handed out stay with their owners
     delete q;
     return GL_OK;
 }

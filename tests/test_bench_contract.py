@@ -33,3 +33,25 @@ def test_traffic_record_matches_only_its_source(tmp_path, monkeypatch):
     (tmp_path / rec["source"]).write_bytes(open(os.path.join(ROOT, rec["source"]), "rb").read())
     monkeypatch.setattr(bench, "ROOT", str(tmp_path))
     assert bench.measured_traffic(100000, 512) is None
+
+
+def test_cpu_baseline_fit_and_record():
+    """The CPU-baseline leg on tiny sizes: pinned to one core, four timed
+    sizes, a fit on the first three checked against the fourth, host model
+    and core counts recorded, and the affinity restored afterwards."""
+    sys.path.insert(0, ROOT)
+    import bench
+    before = os.sched_getaffinity(0)
+    r = bench.cpu_baseline(2000, (1.0, 0.1, 0.5), sizes=(200, 400, 600, 800))
+    assert os.sched_getaffinity(0) == before
+    assert r["kind"] == "oracle" and r["cores"] == 1 and r["extrapolated"] is True
+    assert r["sizes"] == [200, 400, 600, 800] and len(r["seconds"]) == 4 and r["value"] > 0
+    assert r["pinned_core"] in before and r["nproc"] >= 1 and "cpu_model" in r
+    assert abs(r["fit_residual_at_largest"]) < 10
+
+
+def test_fit_cubic_recovers_exact_coefficients():
+    sys.path.insert(0, ROOT)
+    import bench
+    a, b = bench.fit_cubic((100, 200, 300), [2e-9 * n ** 3 + 3e-7 * n ** 2 for n in (100, 200, 300)])
+    assert abs(a - 2e-9) < 1e-15 and abs(b - 3e-7) < 1e-12

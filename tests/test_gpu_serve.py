@@ -268,3 +268,80 @@ def test_context_destroy_stops_live_queue(g):
         assert r["status"] == g.GL_OK
     finally:
         c2.close()
+
+
+# ------------------------------------------------------- kept factors ---
+
+def test_queue_kept_factor_kriging_matches_direct(g, ctx):
+    """keep_factor through the queue (fused path, tile 256, and a slot: a
+    mixed-precision request): kriging from the handed-out factor equals
+    krige_predict on loglik_eval's factor with the same options bit for bit,
+    and the oracle's Eq. (5) to the kriging tolerance."""
+    x, y, z = field(1300, 91)
+    xn, yn = geoinputs.uniform_points(40, 91)
+    theta = (1.1, 0.09, 1.5)
+    ds = register(g, ctx, x, y, z)
+    q = g.lq_create(ctx)
+    facs = []
+    try:
+        cases = [dict(keep_factor=1), dict(keep_factor=1, precision=g.GL_MIXED_FP32)]
+        res = wait_all(g, q, [g.lq_submit(q, ds, theta, g.gl_opts_default(**kw)) for kw in cases])
+        want, info = oracle.krige(x, y, z, xn, yn, theta)
+        assert info == 0
+        for kw, r in zip(cases, res):
+            assert r["status"] == g.GL_OK and r["factor"]
+            facs.append(r["factor"])
+            ref = g.loglik_eval(ctx, dev(x), dev(y), dev(z), theta, g.gl_opts_default(tile=r["tile"], **kw))
+            try:
+                assert ref["loglik"] == r["loglik"]
+                a = g.krige_predict(ctx, r["factor"], dev(xn), dev(yn)).cpu().numpy()
+                b = g.krige_predict(ctx, ref["factor"], dev(xn), dev(yn)).cpu().numpy()
+            finally:
+                g.gl_factor_release(ctx, ref["factor"])
+            assert np.array_equal(a, b)
+            tol = (1e-5 if kw.get("precision") else 1e-9) * np.max(np.abs(z))
+            assert np.max(np.abs(a - want)) <= tol, np.max(np.abs(a - want))
+    finally:
+        g.lq_destroy(q)
+        g.gl_dataset_release(ctx, ds)
+    # factors outlive their queue
+    a = g.krige_predict(ctx, facs[0], dev(xn), dev(yn)).cpu().numpy()
+    assert np.max(np.abs(a - want)) <= 1e-9 * np.max(np.abs(z))
+    for f in facs:
+        g.gl_factor_release(ctx, f)
+
+
+def test_queue_evicts_least_recently_used_factor(g, ctx):
+    """With a budget for about two kept factors plus one request, admitting a
+    third keep_factor request releases the least recently used factor (the
+    one not kriged since): kriging on it returns GL_EVICTED, the other still
+    works, and releasing both handles succeeds."""
+    n = 2000
+    x, y, z = field(n, 92)
+    xn, yn = geoinputs.uniform_points(8, 92)
+    theta = THETAS[0]
+    ds = register(g, ctx, x, y, z)
+    per = g.gl_footprint_bytes(n, 256)
+    q = g.lq_create(ctx, g.lq_config_default(hbm_budget_bytes=int(2.5 * per)))
+    facs = []
+    try:
+        for k in range(2):
+            r = wait_all(g, q, [g.lq_submit(q, ds, theta, g.gl_opts_default(keep_factor=1))])[0]
+            assert r["status"] == g.GL_OK and r["factor"]
+            facs.append(r["factor"])
+        g.krige_predict(ctx, facs[0], dev(xn), dev(yn))  # facs[1] is now the least recently used
+        torch.cuda.synchronize()
+        r = wait_all(g, q, [g.lq_submit(q, ds, THETAS[1], g.gl_opts_default(keep_factor=1))])[0]
+        assert r["status"] == g.GL_OK
+        facs.append(r["factor"])
+        with pytest.raises(g.GeolikError) as ei:
+            g.krige_predict(ctx, facs[1], dev(xn), dev(yn))
+        assert ei.value.status == g.GL_EVICTED
+        out = g.krige_predict(ctx, facs[0], dev(xn), dev(yn)).cpu().numpy()
+        want, _ = oracle.krige(x, y, z, xn, yn, theta)
+        assert np.max(np.abs(out - want)) <= 1e-9 * np.max(np.abs(z))
+    finally:
+        g.lq_destroy(q)
+        g.gl_dataset_release(ctx, ds)
+        for f in facs:
+            g.gl_factor_release(ctx, f)
