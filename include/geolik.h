@@ -48,7 +48,8 @@ typedef enum {
     GL_ECANCELED = -5,  /* request cancelled or queue destroyed */
     GL_ETIMEDOUT = -6,  /* lq_wait: timeout elapsed */
     GL_ENODEV = -7,     /* no usable gfx950 device */
-    GL_EVICTED = -9     /* a factor kept through the queue was released by its admission */
+    GL_EVICTED = -9,    /* a factor kept through the queue was released by its admission */
+    GL_E2BIG = -10      /* loglik_eval_noalloc: the workspace exceeds GL_SCRATCH_BYTES */
 } gl_status;
 
 typedef enum {
@@ -192,6 +193,28 @@ int matern_generate(gl_context *ctx, const double *x1, const double *y1, int64_t
  */
 int loglik_eval(gl_context *ctx, const double *x, const double *y, const double *z, int64_t n,
                 gl_theta theta, const gl_opts *opts, gl_result *res_h, void *stream);
+
+/*
+ * loglik_eval for callers that cannot allocate device memory (code under
+ * stream capture, tight serving loops, hosts that forbid hipMalloc): the same
+ * binary64 computation and kernels as loglik_eval, bit-identical results, but
+ * the workspace lives in a static device array of GL_SCRATCH_BYTES per device
+ * (held until the process ends) and the call allocates nothing, on the device
+ * or the host.  The context must have been created beforehand (that is where
+ * the array's device address is looked up).
+ * Limits: precision GL_FP64, keep_factor = 0, graph = 0, ind_tiles = 0
+ * (GL_EINVAL otherwise); the workspace of (n, tile) — gl_workspace_layout's
+ * tiles rounded up to 256 bytes, plus its vectors — must fit GL_SCRATCH_BYTES
+ * (GL_E2BIG otherwise, nothing launched): n <= 4,096 at every tile size.
+ * Kernel timing (gl_profile_enable) does not cover this call.
+ * Every call on one device shares that device's array, whatever the context:
+ * calls that overlap on one device race, and must be ordered by the caller.
+ * Synchronous with respect to `stream` like loglik_eval; return value equals
+ * res_h->status.
+ */
+#define GL_SCRATCH_BYTES ((size_t)96 << 20)
+int loglik_eval_noalloc(gl_context *ctx, const double *x, const double *y, const double *z, int64_t n,
+                        gl_theta theta, const gl_opts *opts, gl_result *res_h, void *stream);
 
 /*
  * Kriging, Sec. 2.3 Eq. (5) and Alg. 3: Z1 = Σ12 Σ22⁻¹ Z2 at m new locations,

@@ -22,6 +22,8 @@ GL_ECANCELED = -5
 GL_ETIMEDOUT = -6
 GL_ENODEV = -7
 GL_EVICTED = -9
+GL_E2BIG = -10
+GL_SCRATCH_BYTES = 96 << 20
 
 GL_FP64 = 0
 GL_MIXED_FP32 = 1
@@ -83,6 +85,8 @@ _SIGNATURES = {
                                    ctypes.POINTER(_SZ)]),
     "matern_generate": (_I32, [_P, _P, _P, _I64, _P, _P, _I64, gl_theta, _P, _P, _I64, _P]),
     "loglik_eval": (_I32, [_P, _P, _P, _P, _I64, gl_theta, ctypes.POINTER(gl_opts), ctypes.POINTER(gl_result), _P]),
+    "loglik_eval_noalloc": (_I32, [_P, _P, _P, _P, _I64, gl_theta, ctypes.POINTER(gl_opts), ctypes.POINTER(gl_result),
+                                   _P]),
     "krige_predict": (_I32, [_P, _P, _P, _P, _I64, _P, _P, _P]),
     "krige_cv": (_I32, [_P, _P, _P, _P, _I64, gl_theta, _P, _P, _I32, _P, _P, _P]),
     "gl_factor_release": (_I32, [_P, _P]),
@@ -249,6 +253,18 @@ def loglik_eval(ctx: Context, x, y, z, theta, opts: gl_opts | None = None, strea
     st = lib().loglik_eval(ctx.handle, _ptr(x), _ptr(y), _ptr(z), x.numel(), _theta(theta), ctypes.byref(o),
                            ctypes.byref(res), _stream(stream))
     _check(st, "loglik_eval")
+    return res.as_dict()
+
+
+def loglik_eval_noalloc(ctx: Context, x, y, z, theta, opts: gl_opts | None = None, stream=None) -> dict:
+    """loglik_eval with its workspace in the library's static device array
+    (no allocation; binary64, n up to GL_SCRATCH_BYTES of workspace)."""
+    res = gl_result()
+    o = opts if opts is not None else gl_opts_default()
+    _same_len(x, y, z)
+    st = lib().loglik_eval_noalloc(ctx.handle, _ptr(x), _ptr(y), _ptr(z), x.numel(), _theta(theta),
+                                   ctypes.byref(o), ctypes.byref(res), _stream(stream))
+    _check(st, "loglik_eval_noalloc")
     return res.as_dict()
 
 

@@ -103,6 +103,31 @@ int Work::ensure(gl_context *ctx, int64_t n_, int b_, int precision_)
     if (rc == GL_OK && mneed) rc = grow(mix, mix_cap, mneed, gen);
     ctx->used += bytes() - old;
     if (rc != GL_OK) return rc;
+    set_views(n_, b_, precision_);
+    return GL_OK;
+}
+
+// Point a workspace at caller-provided device memory of `cap` bytes (binary64
+// only): the tiles first, then the vectors.  Nothing is allocated, and
+// release() must never be called on such a view.
+int Work::bind(void *base, size_t cap, int64_t n_, int b_)
+{
+    size_t tneed, vneed, mneed;
+    work_sizes(n_, b_, GL_FP64, tneed, vneed, mneed);
+    tneed = (tneed + 255) & ~(size_t)255;
+    if (tneed + vneed > cap) return GL_ENOMEM;
+    tiles = static_cast<double *>(base);
+    vecs = static_cast<char *>(base) + tneed;
+    mix = nullptr;
+    tile_cap = tneed;
+    vec_cap = vneed;
+    mix_cap = 0;
+    set_views(n_, b_, GL_FP64);
+    return GL_OK;
+}
+
+void Work::set_views(int64_t n_, int b_, int precision_)
+{
     n = n_;
     b = b_;
     nt = ceil_div(n_, b_);
@@ -120,7 +145,6 @@ int Work::ensure(gl_context *ctx, int64_t n_, int b_, int precision_)
     res = reinterpret_cast<DevResult *>(info + 8);
     keys = reinterpret_cast<uint64_t *>(info + 16);
     mixed_views(*this);
-    return GL_OK;
 }
 
 int Lanes::create()
@@ -268,6 +292,7 @@ const char *gl_status_string(int status)
     case GL_ETIMEDOUT: return "timed out";
     case GL_ENODEV: return "no usable gfx950 device";
     case GL_EVICTED: return "factor released by the request queue's memory admission";
+    case GL_E2BIG: return "workspace exceeds the static scratch buffer (GL_SCRATCH_BYTES)";
     default: return "unknown status";
     }
 }
@@ -328,7 +353,8 @@ int gl_context_create(int device, size_t budget, gl_context **out)
     GL_HIP_TRY(hipMemGetInfo(&freeb, &total));
     c->budget = budget ? budget : (size_t)(0.9 * (double)freeb);
     if (c->lanes.create() != GL_OK ||
-        hipHostMalloc(&c->res_h, sizeof(DevResult), hipHostMallocDefault) != hipSuccess) {
+        hipHostMalloc(&c->res_h, sizeof(DevResult), hipHostMallocDefault) != hipSuccess ||
+        scratch_init(device, &c->scratch) != GL_OK) {
         gl_context_destroy(c);
         return GL_EHIP;
     }

@@ -59,6 +59,8 @@ struct Work {
     uint64_t *keys = nullptr;           // Morton sort keys (+ bounding box)
     MixedViews mv;
     int ensure(gl_context *ctx, int64_t n, int b, int precision);
+    int bind(void *base, size_t cap, int64_t n, int b);
+    void set_views(int64_t n, int b, int precision);
     size_t bytes() const { return tile_cap + vec_cap + mix_cap; }
     double *dinv_k(int64_t k) const { return dinv + k * 64 * (int64_t)b; }
     void release();
@@ -124,6 +126,10 @@ void serve_context_cleanup(gl_context *ctx);
 void serve_stop_queues(gl_context *ctx);  // destroys the context's live queues
 
 void fill_result(gl_result *res, const DevResult &d, int b);
+
+// Device address of the static workspace of loglik_eval_noalloc on `device`
+// (noalloc.hip), looked up once per device; the device must be current.
+int scratch_init(int device, void **out);
 
 // Factors kept by the request queue (engine.cpp).  factor_adopt takes over
 // the device memory of w (a finished evaluation) as a new registered factor
@@ -195,6 +201,7 @@ struct gl_context {
     gl::Geom gkey_geo{0, 0.0};
     gl_theta *theta_h = nullptr;  // pinned
     gl_theta *theta_d = nullptr;  // device
+    void *scratch = nullptr;      // this device's static workspace of loglik_eval_noalloc
 };
 
 namespace gl {

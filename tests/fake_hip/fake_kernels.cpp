@@ -138,6 +138,11 @@ void launch_morton_order(const double *x, const double *y, const double *z, int6
         for (int64_t i = 0; i < n; ++i) perm[i] = i;
 }
 int selftest_mfma(int, double *, int64_t) { return GL_EINVAL; }
+int scratch_init(int, void **out)
+{
+    *out = nullptr;
+    return GL_OK;
+}
 
 // mixed precision: no side buffer; the factorisation is the FP64 stand-in
 size_t mixed_extra_bytes(int64_t, int, int) { return 0; }

@@ -49,7 +49,8 @@ def test_status_strings_and_defaults():
     import paper_1708_02835_amd as g
     assert g.gl_status_string(g.GL_OK) == "ok"
     assert "positive definite" in g.gl_status_string(g.GL_NOT_SPD)
-    for st in [g.GL_EINVAL, g.GL_ENOMEM, g.GL_EHIP, g.GL_EBUSY, g.GL_ECANCELED, g.GL_ETIMEDOUT, g.GL_ENODEV]:
+    for st in [g.GL_EINVAL, g.GL_ENOMEM, g.GL_EHIP, g.GL_EBUSY, g.GL_ECANCELED, g.GL_ETIMEDOUT, g.GL_ENODEV,
+               g.GL_EVICTED, g.GL_E2BIG]:
         assert g.gl_status_string(st) != "unknown status"
     o = g.gl_opts_default()
     assert (o.precision, o.tile, o.keep_factor, o.band, o.reorder) == (g.GL_FP64, 0, 0, 2, -1)
@@ -138,3 +139,15 @@ def test_workspace_layout_sequence_moves_only_the_vectors():
         g.gl_workspace_layout(0)
     with pytest.raises(g.GeolikError):
         g.gl_workspace_layout(100, 100)
+
+
+def test_scratch_limit_matches_header():
+    """The binding's copy of the no-allocation workspace limit is the header's,
+    and the documented n <= 4,096 fits it at every tile size."""
+    import paper_1708_02835_amd as g
+    text = open(HEADER).read()
+    m = re.search(r"#define GL_SCRATCH_BYTES \(\(size_t\)(\d+) << (\d+)\)", text)
+    assert m and int(m.group(1)) << int(m.group(2)) == g.GL_SCRATCH_BYTES
+    for tile in (0, 128, 256, 384, 512):
+        t, v, _ = g.gl_workspace_layout(4096, tile, g.GL_FP64)
+        assert ((t + 255) // 256) * 256 + v <= g.GL_SCRATCH_BYTES
