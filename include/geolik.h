@@ -119,6 +119,13 @@ typedef struct {
                             inputs as a replayed hipGraph, captured on the first call for a
                             workspace geometry (n, tile) and distance and replayed while they
                             stay the same (θ is read from device memory); 0: direct launches */
+    int32_t near_tiles;  /* schedule of the trailing updates (results change by rounding only).
+                            GL_FP64 and the split-product classes of the mixed modes apply two
+                            panels per pass (K = 2b) to the columns beyond the nearest ones: at
+                            an even step k the next column and the nearest columns holding about
+                            near_tiles tiles get panel k alone, the others get panels k and k+1
+                            together at step k+1.  0: automatic, 512 (512/b)³ tiles (GL_FP64) or
+                            1536 (512/b)³ split-product tiles (mixed modes); > 0: that many */
 } gl_opts;
 
 /* Result of one likelihood evaluation, host memory. */
@@ -146,7 +153,7 @@ int gl_context_create(int device, size_t hbm_budget_bytes, gl_context **out);
 void gl_context_destroy(gl_context *ctx);
 
 /* Fill *opts with defaults: FP64, automatic tile, no factor kept, band 2,
- * automatic order, mode-default thresholds (-1). */
+ * automatic order, mode-default thresholds (-1), automatic near_tiles (0). */
 void gl_opts_default(gl_opts *opts);
 
 /* Static English description of a gl_status value. */

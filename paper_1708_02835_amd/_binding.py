@@ -49,7 +49,7 @@ class gl_opts(ctypes.Structure):
                 ("band", ctypes.c_int32), ("reorder", ctypes.c_int32), ("metric", ctypes.c_int32),
                 ("tol_hi", ctypes.c_double), ("tol_lo", ctypes.c_double), ("radius", ctypes.c_double),
                 ("tol_64", ctypes.c_double), ("accuracy", ctypes.c_double), ("ind_tiles", ctypes.c_int32),
-                ("graph", ctypes.c_int32)]
+                ("graph", ctypes.c_int32), ("near_tiles", ctypes.c_int32)]
 
 
 class gl_result(ctypes.Structure):

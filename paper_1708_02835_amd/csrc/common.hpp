@@ -63,7 +63,7 @@ void launch_potrf(double *tiles, int b, int64_t k, int64_t n, int64_t *info, dou
 void launch_trsm(double *tiles, int b, int64_t nt, int64_t k, const double *dinv, const int64_t *info,
                  hipStream_t s);
 void launch_trailing(double *tiles, int b, int64_t nt, int64_t k, int64_t jbeg, int64_t jend,
-                     const int64_t *info, bool critical, hipStream_t s);
+                     const int64_t *info, bool critical, bool pair, hipStream_t s);
 // Solves and reductions
 void launch_fwd_diag(const double *tiles, int b, int64_t k, int64_t n, double *v, double *quad_part,
                      const double *dinv, const int64_t *info, hipStream_t s);

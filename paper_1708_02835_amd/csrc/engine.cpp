@@ -229,18 +229,42 @@ static double trailing_flops(int64_t nt, int64_t jbeg, int64_t jend, int b)
     return f;
 }
 
-static void trailing(Lanes &ln, Work &w, int64_t k, int64_t jbeg, int64_t jend, hipStream_t s, bool critical)
+// pair: panels k-1 and k in one pass (K = 2b), twice the flops per tile.
+static void trailing(Lanes &ln, Work &w, int64_t k, int64_t jbeg, int64_t jend, hipStream_t s, bool critical,
+                     bool pair = false)
 {
-    timed(ln.prof, critical ? GL_PHASE_TRAIL_CRIT : GL_PHASE_TRAIL_BULK, trailing_flops(w.nt, jbeg, jend, w.b), s,
-          [&] { launch_trailing(w.tiles, w.b, w.nt, k, jbeg, jend, w.info, critical, s); });
+    timed(ln.prof, critical ? GL_PHASE_TRAIL_CRIT : GL_PHASE_TRAIL_BULK,
+          (pair ? 2.0 : 1.0) * trailing_flops(w.nt, jbeg, jend, w.b), s,
+          [&] { launch_trailing(w.tiles, w.b, w.nt, k, jbeg, jend, w.info, critical, pair, s); });
 }
 
-int factorize(Lanes &ln, Work &w, hipStream_t s, bool solve)
+int64_t near_tiles_for(int b, int32_t requested)
+{
+    if (requested > 0) return requested;
+    const double r = 512.0 / (double)b;
+    return (int64_t)(512.0 * r * r * r);
+}
+
+// Tiled right-looking Cholesky (Sec. 5.2) with a one-step lookahead, plus the
+// forward solve and the per-tile log-det and wᵀw parts when `solve` is set.
+//
+// Two panels per pass for the far columns: each trailing pass reads and
+// writes its C tile once, so applying panels k and k+1 together (K = 2b)
+// halves that traffic and the per-block start-up of the update kernel.  At
+// an even step k the next column (the critical path) and the nearest columns,
+// up to `near` tiles, get panel k alone: the near part keeps the lookahead
+// stream busy while step k+1's POTRF and TRSM run.  The columns beyond
+// (from js on) defer panel k to step k+1, whose bulk launch applies panels k
+// and k+1 in one pass.  Panels stay final in place, so the deferred launch
+// reads them from the tiles.  The order of the subtractions differs from the
+// one-panel schedule, the set of products does not.
+int factorize(Lanes &ln, Work &w, hipStream_t s, bool solve, int64_t near)
 {
     hipStream_t la = ln.la;
     GL_HIP_TRY(hipEventRecord(ln.fork, s));
     GL_HIP_TRY(hipStreamWaitEvent(la, ln.fork, 0));
     const double b3 = (double)w.b * w.b * w.b;
+    int64_t js = w.nt;  // columns >= js take the current pair of panels in one pass
     for (int64_t k = 0; k < w.nt; ++k) {
         const double below = (double)(w.nt - k - 1);
         timed(ln.prof, GL_PHASE_POTRF, b3 / 3.0, s,
@@ -258,11 +282,20 @@ int factorize(Lanes &ln, Work &w, hipStream_t s, bool solve)
                   [&] { launch_fwd_update(w.tiles, w.b, w.nt, k, w.v, w.info, s); });
         }
         if (k + 1 < w.nt) {
+            const bool odd = (k & 1) != 0;
+            if (!odd) {
+                // column j holds nt - j tiles
+                int64_t acc = 0;
+                js = k + 2;
+                while (js < w.nt && acc < near) acc += w.nt - js++;
+            }
             if (k > 0) GL_HIP_TRY(hipStreamWaitEvent(s, ln.bulk, 0));
-            trailing(ln, w, k, k + 1, k + 1, s, true);
+            trailing(ln, w, k, k + 1, k + 1, s, true, odd && k + 1 >= js);
             if (k + 2 < w.nt) {
                 GL_HIP_TRY(hipStreamWaitEvent(la, ln.panel, 0));
-                trailing(ln, w, k, k + 2, w.nt - 1, la, false);
+                const int64_t split = std::max(js, k + 2);
+                if (split > k + 2) trailing(ln, w, k, k + 2, split - 1, la, false);
+                if (split < w.nt && odd) trailing(ln, w, k, split, w.nt - 1, la, false, true);
                 GL_HIP_TRY(hipEventRecord(ln.bulk, la));
             }
         }
@@ -312,6 +345,7 @@ void gl_opts_default(gl_opts *o)
     o->accuracy = -1.0;
     o->ind_tiles = 0;
     o->graph = 0;
+    o->near_tiles = 0;
     o->radius = 6371.0;
 }
 
@@ -427,7 +461,7 @@ int eval_launch(Lanes &ln, Work &w, gl_theta th, const gl_opts &o, hipStream_t s
     if (o.precision == GL_FP64) {
         timed(ln.prof, GL_PHASE_GEN, 0.0, s,
               [&] { launch_gen_tiles(w.tiles, w.x, w.y, w.n, w.b, w.nt, th, geom_of(o), nullptr, s); });
-        rc = factorize(ln, w, s, true);
+        rc = factorize(ln, w, s, true, near_tiles_for(w.b, o.near_tiles));
     } else {
         rc = mixed_factorize(ln, w, th, o, s, plan_out);
     }
@@ -450,6 +484,7 @@ bool valid_opts(const gl_opts &o)
     if (!valid_metric(o)) return false;
     if (o.ind_tiles < 0 || (o.ind_tiles > 0 && (o.precision != GL_FP64 || o.keep_factor))) return false;
     if (o.graph < 0 || o.graph > 1) return false;
+    if (o.near_tiles < 0) return false;
     if (o.precision < GL_FP64 || o.precision > GL_MIXED_FP16) return false;
     if (o.tile != 0 && o.tile != 128 && o.tile != 256 && o.tile != 384 && o.tile != 512) return false;
     if (o.reorder < -1 || o.reorder > 1) return false;
@@ -512,8 +547,10 @@ static int graph_eval(gl_context *ctx, Work &w, const double *x, const double *y
     // The graph holds pointers into the tiles and into the vectors (x, y, v,
     // the per-tile sums, the diagonal-block inverses, info, result), so any
     // reallocation of the workspace invalidates it, even when the tiles stay.
+    const int64_t near = near_tiles_for(w.b, o.near_tiles);
     const bool hit = ctx->gexec && ctx->gkey_gen == w.gen && ctx->gkey_n == w.n && ctx->gkey_b == w.b &&
-                     ctx->gkey_geo.metric == geo.metric && ctx->gkey_geo.radius == geo.radius;
+                     ctx->gkey_geo.metric == geo.metric && ctx->gkey_geo.radius == geo.radius &&
+                     ctx->gkey_near == near;
     if (!hit) {
         graph_drop(ctx);
         Lanes ln = ctx->lanes;
@@ -521,7 +558,7 @@ static int graph_eval(gl_context *ctx, Work &w, const double *x, const double *y
         GL_HIP_TRY(hipStreamBeginCapture(g, hipStreamCaptureModeThreadLocal));
         launch_fill(reinterpret_cast<double *>(w.info), 1, 0.0, g);
         launch_gen_tiles_dev(w.tiles, w.x, w.y, w.n, w.b, w.nt, ctx->theta_d, geo, g);
-        int rc = factorize(ln, w, g, true);
+        int rc = factorize(ln, w, g, true, near);
         launch_final_reduce(w.logsum, w.quad, w.nt, w.n, w.info, w.res, g);
         hipGraph_t graph = nullptr;
         const hipError_t ec = hipStreamEndCapture(g, &graph);
@@ -540,6 +577,7 @@ static int graph_eval(gl_context *ctx, Work &w, const double *x, const double *y
         ctx->gkey_n = w.n;
         ctx->gkey_b = w.b;
         ctx->gkey_geo = geo;
+        ctx->gkey_near = near;
     }
     GL_HIP_TRY(hipGraphLaunch(ctx->gexec, g));
     GL_HIP_TRY(hipMemcpyAsync(ctx->res_h, w.res, sizeof(DevResult), hipMemcpyDeviceToHost, g));
@@ -876,7 +914,7 @@ int synth_generate(gl_context *ctx, const double *x, const double *y, const doub
     launch_copy_pad(e, n, w.v, w.npad, 0.0, s);
     launch_fill(reinterpret_cast<double *>(w.info), 1, 0.0, s);
     launch_gen_tiles(w.tiles, w.x, w.y, w.n, w.b, w.nt, th, geom_of(o), nullptr, s);
-    rc = factorize(ctx->lanes, w, s, false);
+    rc = factorize(ctx->lanes, w, s, false, near_tiles_for(w.b, o.near_tiles));
     if (rc != GL_OK) return rc;
     // z = L e: e is read from v, the padded product goes to the x buffer (no
     // longer needed once the tiles exist), then its first n values to z

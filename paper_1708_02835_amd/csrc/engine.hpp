@@ -96,7 +96,10 @@ int pick_tile(int64_t n, int32_t requested);
 bool valid_theta(const gl_theta &t);
 bool valid_theta_for(const gl_theta &t, const gl_opts &o);
 size_t work_bytes(int64_t n, int b, int precision);
-int factorize(Lanes &ln, Work &w, hipStream_t s, bool solve);
+int factorize(Lanes &ln, Work &w, hipStream_t s, bool solve, int64_t near);
+// Tiles updated one panel at a time at even steps (gl_opts.near_tiles; 0:
+// 512 (512/b)³, about 2 ms of binary64 update at tile 512).
+int64_t near_tiles_for(int b, int32_t requested);
 // Enqueue a whole evaluation on s (inputs already in w.x, w.y, w.v) and the
 // copy of its scalar results to out_h; does not wait.
 int eval_launch(Lanes &ln, Work &w, gl_theta th, const gl_opts &o, hipStream_t s, DevResult *out_h,
@@ -199,6 +202,7 @@ struct gl_context {
     int64_t gkey_n = 0;
     int gkey_b = 0;
     gl::Geom gkey_geo{0, 0.0};
+    int64_t gkey_near = 0;
     gl_theta *theta_h = nullptr;  // pinned
     gl_theta *theta_d = nullptr;  // device
     void *scratch = nullptr;      // this device's static workspace of loglik_eval_noalloc

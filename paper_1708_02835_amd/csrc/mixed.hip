@@ -709,7 +709,8 @@ int mixed_factorize(Lanes &ln, Work &w, gl_theta th, const gl_opts &o, hipStream
     for (int c = 0; c < NCLASS; ++c)
         if (paired_class(c))
             for (int64_t j = 0; j < w.nt; ++j) pcol[(size_t)j] += plan.start[c][j + 1] - plan.start[c][j];
-    const int64_t near_tiles = (int64_t)1536 * (512 / w.b) * (512 / w.b) * (512 / w.b);
+    const double rb = 512.0 / (double)w.b;
+    const int64_t near_tiles = o.near_tiles > 0 ? (int64_t)o.near_tiles : (int64_t)(1536.0 * rb * rb * rb);
     int64_t js = w.nt;  // columns >= js take the current pair of panels in one update
     GL_HIP_TRY(hipEventRecord(ln.fork, s));
     GL_HIP_TRY(hipStreamWaitEvent(la, ln.fork, 0));

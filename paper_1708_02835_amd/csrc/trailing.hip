@@ -48,12 +48,20 @@ __device__ inline void trailing_tile(int64_t t, int64_t jbeg, int64_t nt, int64_
 // operand read (rows k and k+1) fall in different banks.
 constexpr int GP = GB + 16;  // LDS row pitch (doubles)
 
-template <int B>
+//
+// With a second pair of operands (A2t, B2t non-null: PAIR) the K loop runs
+// over both, C -= A Bᵀ + A2 B2ᵀ with K = 2b: two panels applied with one read
+// and one write of C.
+template <int B, bool PAIR = false>
 __device__ __forceinline__ void trailing_core(const double *__restrict__ At, const double *__restrict__ Bt,
-                                              double *__restrict__ Ct, int rb, int cb)
+                                              double *__restrict__ Ct, int rb, int cb,
+                                              const double *__restrict__ A2t = nullptr,
+                                              const double *__restrict__ B2t = nullptr)
 {
     const double *Ap = At + rb * GB;
     const double *Bp = Bt + cb * GB;
+    const double *Ap2 = PAIR ? A2t + rb * GB : Ap;
+    const double *Bp2 = PAIR ? B2t + cb * GB : Bp;
     double *C = Ct + (int64_t)(cb * GB) * B + rb * GB;
 
     __shared__ double As[2][GK][GP];
@@ -94,15 +102,19 @@ __device__ __forceinline__ void trailing_core(const double *__restrict__ At, con
         for (int b = 0; b < 4; ++b) acc[a][b] = -acc[a][b];
     __syncthreads();
 
-    constexpr int NK = B / GK;
+    constexpr int NK1 = B / GK;
+    constexpr int NK = PAIR ? 2 * NK1 : NK1;
     for (int kc = 0; kc < NK; ++kc) {
         const int cur = kc & 1;
         if (kc + 1 < NK) {
-            const int64_t col = (int64_t)(kc + 1) * GK + lc;
+            const bool second = PAIR && kc + 1 >= NK1;
+            const double *An = second ? Ap2 : Ap;
+            const double *Bn = second ? Bp2 : Bp;
+            const int64_t col = (int64_t)((kc + 1) - (second ? NK1 : 0)) * GK + lc;
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                ra[q] = *reinterpret_cast<const d2 *>(Ap + col * B + le + 32 * q);
-                rbv[q] = *reinterpret_cast<const d2 *>(Bp + col * B + le + 32 * q);
+                ra[q] = *reinterpret_cast<const d2 *>(An + col * B + le + 32 * q);
+                rbv[q] = *reinterpret_cast<const d2 *>(Bn + col * B + le + 32 * q);
             }
         }
 #pragma unroll
@@ -140,16 +152,22 @@ __device__ __forceinline__ void trailing_core(const double *__restrict__ At, con
         }
 }
 
-// One 128×128 block (rb, cb) of the update of tile (i, j) by panel column k.
-template <int B>
+// One 128×128 block (rb, cb) of the update of tile (i, j) by panel column k
+// (PAIR: by panel columns k-1 and k).
+template <int B, bool PAIR = false>
 __device__ __forceinline__ void trailing_block_body(double *__restrict__ tiles, int64_t k, int64_t i,
                                                     int64_t j, int rb, int cb)
 {
-    trailing_core<B>(tiles + tile_offset(i, k, B), tiles + tile_offset(j, k, B), tiles + tile_offset(i, j, B),
-                     rb, cb);
+    if (PAIR)
+        trailing_core<B, true>(tiles + tile_offset(i, k - 1, B), tiles + tile_offset(j, k - 1, B),
+                               tiles + tile_offset(i, j, B), rb, cb, tiles + tile_offset(i, k, B),
+                               tiles + tile_offset(j, k, B));
+    else
+        trailing_core<B>(tiles + tile_offset(i, k, B), tiles + tile_offset(j, k, B), tiles + tile_offset(i, j, B),
+                         rb, cb);
 }
 
-template <int B>
+template <int B, bool PAIR = false>
 __global__ __launch_bounds__(256, 2) void trailing_f64_kernel(double *__restrict__ tiles, int64_t k,
                                                               int64_t jbeg, int64_t nt,
                                                               int64_t nblocks,
@@ -177,11 +195,12 @@ __global__ __launch_bounds__(256, 2) void trailing_f64_kernel(double *__restrict
     }
     const int rb = sub / SB, cb = sub % SB;
     if (i == j && cb > rb) return;
-    trailing_block_body<B>(tiles, k, i, j, rb, cb);
+    trailing_block_body<B, PAIR>(tiles, k, i, j, rb, cb);
 }
 
-void launch_trailing(double *tiles, int b, int64_t nt, int64_t k, int64_t jbeg, int64_t jend,
-                     const int64_t *info, bool critical, hipStream_t s)
+template <bool PAIR>
+static void launch_trailing_t(double *tiles, int b, int64_t nt, int64_t k, int64_t jbeg, int64_t jend,
+                              const int64_t *info, bool critical, hipStream_t s)
 {
     if (jbeg > jend || jbeg >= nt) return;
     // tiles in columns jbeg..jend, rows j..nt-1
@@ -191,12 +210,23 @@ void launch_trailing(double *tiles, int b, int64_t nt, int64_t k, int64_t jbeg, 
     const int64_t sub = (int64_t)(b / GB) * (b / GB);
     const int64_t nblocks = ntiles * sub;
     const int64_t grid = ceil_div(nblocks, 8) * 8;
+    const int crit = critical ? 1 : 0;
     switch (b) {
-    case 128: trailing_f64_kernel<128><<<(unsigned)grid, 256, 0, s>>>(tiles, k, jbeg, nt, nblocks, info, critical ? 1 : 0, nullptr); break;
-    case 256: trailing_f64_kernel<256><<<(unsigned)grid, 256, 0, s>>>(tiles, k, jbeg, nt, nblocks, info, critical ? 1 : 0, nullptr); break;
-    case 384: trailing_f64_kernel<384><<<(unsigned)grid, 256, 0, s>>>(tiles, k, jbeg, nt, nblocks, info, critical ? 1 : 0, nullptr); break;
-    default: trailing_f64_kernel<512><<<(unsigned)grid, 256, 0, s>>>(tiles, k, jbeg, nt, nblocks, info, critical ? 1 : 0, nullptr); break;
+    case 128: trailing_f64_kernel<128, PAIR><<<(unsigned)grid, 256, 0, s>>>(tiles, k, jbeg, nt, nblocks, info, crit, nullptr); break;
+    case 256: trailing_f64_kernel<256, PAIR><<<(unsigned)grid, 256, 0, s>>>(tiles, k, jbeg, nt, nblocks, info, crit, nullptr); break;
+    case 384: trailing_f64_kernel<384, PAIR><<<(unsigned)grid, 256, 0, s>>>(tiles, k, jbeg, nt, nblocks, info, crit, nullptr); break;
+    default: trailing_f64_kernel<512, PAIR><<<(unsigned)grid, 256, 0, s>>>(tiles, k, jbeg, nt, nblocks, info, crit, nullptr); break;
     }
+}
+
+// pair: apply panel columns k-1 and k together (k >= 1; both final).
+void launch_trailing(double *tiles, int b, int64_t nt, int64_t k, int64_t jbeg, int64_t jend,
+                     const int64_t *info, bool critical, bool pair, hipStream_t s)
+{
+    if (pair)
+        launch_trailing_t<true>(tiles, b, nt, k, jbeg, jend, info, critical, s);
+    else
+        launch_trailing_t<false>(tiles, b, nt, k, jbeg, jend, info, critical, s);
 }
 
 // Fused trailing updates of many requests, each at its own step k (columns

@@ -39,7 +39,7 @@ void launch_potrf(double *tiles, int b, int64_t k, int64_t n, int64_t *info, dou
     logsum[k] = (double)rows_of(n, b, k) * log(t1);
 }
 void launch_trsm(double *, int, int64_t, int64_t, const double *, const int64_t *, hipStream_t) {}
-void launch_trailing(double *, int, int64_t, int64_t, int64_t, int64_t, const int64_t *, bool, hipStream_t) {}
+void launch_trailing(double *, int, int64_t, int64_t, int64_t, int64_t, const int64_t *, bool, bool, hipStream_t) {}
 void launch_fwd_diag(const double *tiles, int b, int64_t k, int64_t n, double *v, double *quad, const double *,
                      const int64_t *, hipStream_t)
 {
