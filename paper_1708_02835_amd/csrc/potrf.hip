@@ -3,11 +3,11 @@
 //
 // One workgroup of 256 threads factors the b×b tile A_kk = L_kk L_kkᵀ in place
 // (lower triangle), right-looking over 64-column panels s:
-//   1. the 64×64 diagonal block D is copied to LDS, factored by one wave
-//      (lane r owns row r; each column of the factor is broadcast through
-//      LDS), and inverted by the same wave (lane j builds column j of D⁻¹ by
-//      column-oriented forward substitution).  D⁻¹ is also written to `dinv` for the panel TRSM and
-//      the forward solve of this step;
+//   1. the 64×64 diagonal block D is copied to LDS, factored and inverted in
+//      16×16 sub-blocks (factor_invert_64: small scalar factorisations and
+//      inverses of the diagonal sub-blocks, everything else on the matrix
+//      cores).  D⁻¹ is also written to `dinv` for the panel TRSM and the
+//      forward solve of this step;
 //   2. the rows below the block are solved on the matrix cores as
 //      P = A[s+64:, s:s+64] · D⁻ᵀ, each wave owning whole 16-row groups;
 //   3. the trailing lower triangle A[s+64:, s+64:] -= P Pᵀ is updated on the
@@ -26,6 +26,139 @@ namespace gl {
 
 constexpr int PB = 64;  // diagonal block edge
 
+// Factor the 64×64 block D held in Ds (Ds[c][r] = D[r][c], lower triangle
+// valid) as D = L Lᵀ in place and write X = L⁻¹ to Xi (Xi[c][r] = X[r][c];
+// its upper blocks must be zero on entry), in 16×16 sub-blocks, P = 0..3:
+//   (a) one wave factors the 16×16 diagonal block D_PP (lane r owns row r,
+//       each column broadcast through LDS) and inverts it (lane j builds
+//       column j of X_PP by forward substitution);
+//   (b) the blocks below, L_IP = D_IP X_PPᵀ, on the matrix cores, one wave
+//       per block;
+//   (c) the lower blocks to the right, D_IJ -= L_IP L_JPᵀ (P < J <= I), on
+//       the matrix cores.
+// Then the off-diagonal blocks of X by block diagonals d = I - J = 1, 2, 3:
+// X_IJ = -X_II Σ_{M=J}^{I-1} L_IM X_MJ.  The 16x16x4 products leave T = Σ
+// in the lane layout of their B operand, so the second product reads it from
+// registers.  A non-positive (or NaN) pivot stores the 1-based global column
+// (col0 + local column + 1) in *info; the function returns false on every
+// thread in that case and true otherwise.  Called by all 256 threads.
+__device__ __forceinline__ bool factor_invert_64(double (*Ds)[PB + 1], double (*Xi)[PB + 1], double *rdiag,
+                                                 double *colb, int *fail, int64_t col0, int64_t *info)
+{
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+    const int r16 = lane & 15;  // row (column) within a 16×16 block
+    const int q = lane >> 4;
+    for (int P = 0; P < 4; ++P) {
+        const int p0 = 16 * P;
+        if (wave == 0) {
+            // (a) lanes 16..63 repeat the work of lanes 0..15 and store nothing
+            double a[16];
+#pragma unroll
+            for (int m = 0; m < 16; ++m) a[m] = Ds[p0 + m][p0 + r16];
+            int fcol = -1;
+            double rv = 0.0;
+#pragma unroll
+            for (int c = 0; c < 16; ++c) {
+                const double piv = readlane_f64(a[c], c);
+                if (!(piv > 0.0) && fcol < 0) fcol = c;
+                const double d = sqrt(piv);
+                const double inv = 1.0 / d;
+                if (r16 == c) rv = inv;
+                a[c] = (r16 == c) ? d : a[c] * inv;
+                // column c through LDS (the wave's LDS accesses complete in
+                // order); entries above the diagonal receive values that are
+                // never stored
+                if (lane < 16) colb[lane] = a[c];
+                __builtin_amdgcn_wave_barrier();
+#pragma unroll
+                for (int j = c + 1; j < 16; ++j) a[j] -= a[c] * colb[j];
+                __builtin_amdgcn_wave_barrier();
+            }
+            if (fcol >= 0) {
+                if (lane == 0) {
+                    *fail = 1;
+                    *info = col0 + p0 + fcol + 1;
+                }
+            } else {
+                if (lane < 16) {
+#pragma unroll
+                    for (int m = 0; m < 16; ++m)
+                        if (m <= lane) Ds[p0 + m][p0 + lane] = a[m];
+                    rdiag[p0 + lane] = rv;
+                }
+                __builtin_amdgcn_wave_barrier();
+                double x[16];
+#pragma unroll
+                for (int i = 0; i < 16; ++i) x[i] = (i == r16) ? 1.0 : 0.0;
+#pragma unroll
+                for (int m = 0; m < 16; ++m) {
+                    x[m] *= rdiag[p0 + m];
+#pragma unroll
+                    for (int i = m + 1; i < 16; ++i) x[i] -= Ds[p0 + m][p0 + i] * x[m];
+                }
+                if (lane < 16) {
+#pragma unroll
+                    for (int i = 0; i < 16; ++i) Xi[p0 + lane][p0 + i] = x[i];
+                }
+            }
+        }
+        __syncthreads();
+        if (*fail) return false;  // uniform: shared flag read after the barrier
+        if (wave < 3 - P) {
+            // (b) block I = P + 1 + wave: L_IP[i][j] = Σ_m D_IP[i][m] X_PP[j][m]
+            const int i0 = 16 * (P + 1 + wave);
+            d4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int kc = 0; kc < 4; ++kc) {
+                const int m = 4 * kc + q;
+                acc = mfma_f64(Ds[p0 + m][i0 + r16], Xi[p0 + m][p0 + r16], acc);
+            }
+#pragma unroll
+            for (int r = 0; r < 4; ++r) Ds[p0 + r16][i0 + q + 4 * r] = acc[r];
+        }
+        __syncthreads();
+        const int nb = 3 - P;
+        for (int blk = wave; blk < nb * (nb + 1) / 2; blk += 4) {
+            // (c) block (I, J), P < J <= I
+            int bi = 0;
+            while ((bi + 1) * (bi + 2) / 2 <= blk) ++bi;
+            const int bj = blk - bi * (bi + 1) / 2;
+            const int i0 = 16 * (P + 1 + bi), j0 = 16 * (P + 1 + bj);
+            d4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int kc = 0; kc < 4; ++kc) {
+                const int m = 4 * kc + q;
+                acc = mfma_f64(Ds[p0 + m][i0 + r16], Ds[p0 + m][j0 + r16], acc);
+            }
+#pragma unroll
+            for (int r = 0; r < 4; ++r) Ds[j0 + r16][i0 + q + 4 * r] -= acc[r];
+        }
+        __syncthreads();
+    }
+    for (int dd = 1; dd < 4; ++dd) {
+        if (wave < 4 - dd) {
+            const int J = wave, I = wave + dd;
+            d4 t = {0.0, 0.0, 0.0, 0.0};
+            for (int M = J; M < I; ++M) {
+#pragma unroll
+                for (int kc = 0; kc < 4; ++kc) {
+                    const int m = 4 * kc + q;
+                    t = mfma_f64(Ds[16 * M + m][16 * I + r16], Xi[16 * J + r16][16 * M + m], t);
+                }
+            }
+            d4 x = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int kc = 0; kc < 4; ++kc) x = mfma_f64(Xi[16 * I + 4 * kc + q][16 * I + r16], t[kc], x);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) Xi[16 * J + r16][16 * I + q + 4 * r] = -x[r];
+        }
+        __syncthreads();
+    }
+    return true;
+}
+
 template <int B>
 __device__ __forceinline__ void potrf_body(double *__restrict__ tiles, int64_t k, int64_t n,
                                            int64_t *__restrict__ info, double *__restrict__ logsum,
@@ -40,7 +173,7 @@ __device__ __forceinline__ void potrf_body(double *__restrict__ tiles, int64_t k
     __shared__ double Ds[PB][PB + 1];  // Ds[c][r] = D[r][c]
     __shared__ double Xi[PB][PB + 1];  // Xi[c][r] = (D⁻¹)[r][c]
     __shared__ double rdiag[PB];
-    __shared__ double colb[PB];  // the current column of the 64×64 factor, for broadcast reads
+    __shared__ double colb[16];  // the current column of a 16×16 factor, for broadcast reads
     __shared__ double red[4];
     __shared__ int fail;
 
@@ -48,66 +181,11 @@ __device__ __forceinline__ void potrf_body(double *__restrict__ tiles, int64_t k
         for (int e = tid; e < PB * PB; e += 256) {
             const int c = e >> 6, r = e & 63;
             Ds[c][r] = A[(int64_t)(s + c) * B + s + r];
+            Xi[c][r] = 0.0;  // D⁻¹ is lower triangular: the upper blocks stay zero
         }
         if (tid == 0) fail = 0;
         __syncthreads();
-        if (wave == 0) {
-            // unblocked right-looking Cholesky of D with row `lane` in registers;
-            // the pivot and the column multipliers are broadcast by readlane
-            double a[PB];
-#pragma unroll
-            for (int m = 0; m < PB; ++m) a[m] = Ds[m][lane];
-            int fcol = -1;
-            double rv = 0.0;
-#pragma unroll
-            for (int c = 0; c < PB; ++c) {
-                const double piv = readlane_f64(a[c], c);
-                if (!(piv > 0.0) && fcol < 0) fcol = c;
-                const double d = sqrt(piv);
-                const double inv = 1.0 / d;
-                if (lane == c) rv = inv;
-                a[c] = (lane == c) ? d : a[c] * inv;
-                // column c goes through LDS (one store, then broadcast reads: the
-                // wave's LDS accesses complete in order) for the rank-1 update;
-                // entries above the diagonal (lane < j) receive harmless values
-                // that are never stored
-                colb[lane] = a[c];
-                __builtin_amdgcn_wave_barrier();
-#pragma unroll
-                for (int j = c + 1; j < PB; ++j) a[j] -= a[c] * colb[j];
-                __builtin_amdgcn_wave_barrier();
-            }
-            if (fcol >= 0) {
-                if (lane == 0) {
-                    fail = 1;
-                    *info = k * B + s + fcol + 1;
-                }
-            } else {
-#pragma unroll
-                for (int m = 0; m < PB; ++m) Ds[m][lane] = a[m];
-                rdiag[lane] = rv;
-            }
-        }
-        __syncthreads();
-        if (fail) return;  // uniform: shared flag read after the barrier
-        if (wave == 0) {
-            // column `lane` of D⁻¹: X[i][j] = (δ_ij - Σ_{m<i} D[i][m] X[m][j]) / D[i][i],
-            // column-oriented: once X[m][j] is final it is subtracted from every
-            // later row, so the updates of one step are independent (the same
-            // operations in the same order per entry as row by row)
-            double x[PB];
-#pragma unroll
-            for (int i = 0; i < PB; ++i) x[i] = (i == lane) ? 1.0 : 0.0;
-#pragma unroll
-            for (int m = 0; m < PB; ++m) {
-                x[m] *= rdiag[m];
-#pragma unroll
-                for (int i = m + 1; i < PB; ++i) x[i] -= Ds[m][i] * x[m];
-            }
-#pragma unroll
-            for (int i = 0; i < PB; ++i) Xi[lane][i] = x[i];
-        }
-        __syncthreads();
+        if (!factor_invert_64(Ds, Xi, rdiag, colb, &fail, k * B + s, info)) return;
         // L block back to the tile, D⁻¹ to the step's inverse buffer
         double *dv = dinv + (int64_t)(s / PB) * PB * PB;
         for (int e = tid; e < PB * PB; e += 256) {

@@ -69,22 +69,26 @@ def test_ind_morton_order_and_great_circle(g, ctx):
 
 
 def test_ind_not_spd_reports_global_column(g, ctx):
-    """A repeated location makes its block's Σ exactly singular: in exact
-    arithmetic the pivot of the repeat's column is 0, so a binary64
-    factorisation ends there with a pivot that is zero up to rounding, of
-    either sign.  Which sign comes out is rounding, not a property of the
-    method, so what is compared is the column: the device reports NOT_SPD at
-    the repeat's global column, and the oracle's factor of that block either
-    stops at the same (local) column or has a pivot there that vanishes to
+    """Repeated locations make their block's Σ exactly singular: in exact
+    arithmetic the pivot of each repeat's column is 0, so a binary64
+    factorisation meets pivots that are zero up to rounding, of either sign.
+    Which sign comes out is rounding, not a property of the method (a single
+    repeat is a coin flip), so 40 locations of the third block of 256 are
+    repeated and what is compared is the column: the device reports NOT_SPD at
+    the global column of one of the repeats, and the oracle's factor of that
+    block either stops at a repeat or has a pivot there that vanishes to
     rounding."""
     n = 900
     x, y = geoinputs.jittered_grid(n, 16)
-    x[600], y[600] = x[599], y[599]  # inside the third block of 256
+    x[600:640], y[600:640] = x[520:560], y[520:560]  # inside the third block of 256
     z = geoinputs.normal_vector(n, 16)
     r = g.loglik_eval(ctx, dev(x), dev(y), dev(z), (1.0, 0.1, 0.5), g.gl_opts_default(tile=128, ind_tiles=2))
-    assert r["status"] == g.GL_NOT_SPD and r["info"] == 601 and r["loglik"] == -math.inf
+    assert r["status"] == g.GL_NOT_SPD and 601 <= r["info"] <= 640 and r["loglik"] == -math.inf
+    c = r["info"] - 513  # 0-based column within the block
     L, info = oracle.cholesky(oracle.cov_symmetric(x[512:768], y[512:768], (1.0, 0.1, 0.5)))
-    assert info == 89 or (info == 0 and L[88, 88] ** 2 <= 1e-10), (info, L[88, 88])
+    assert info == 0 or 89 <= info <= 128, info
+    if info == 0 or info > c + 1:
+        assert L[c, c] ** 2 <= 1e-10, (info, c, L[c, c])
     # the other blocks are unaffected: the sum without the failing block matches
     ok = g.loglik_eval(ctx, dev(x[:512]), dev(y[:512]), dev(z[:512]), (1.0, 0.1, 0.5),
                        g.gl_opts_default(tile=128, ind_tiles=2))
