@@ -206,6 +206,26 @@ def mixed_legs(g, ctx, xd, yd, ed, zd, theta, theta_b, args, res64, t64, log):
                          "work_frac": {k: round(stats[k]["work_frac"], 4) for k in g.PRECISION_CLASSES},
                          "thresholds": stats["thresholds"]}
             log(f"mixed {label} {name}: {dt:.3f} s, x{t64b / dt:.2f}, rel err {leg[name]['rel_err_loglik']:.2e}")
+        if label == "theta_b":
+            # Why the adaptive rule keeps θ_b in binary64: forcing the
+            # FP32-grade two-part binary16 class on the tiles with normalised
+            # norm up to tol_64 (the rest binary64) puts little work in it
+            # already at the 1e-4 error level.
+            trade = []
+            for tol in (0.1, 0.3):
+                opts = g.gl_opts_default(precision=g.GL_MIXED_FP16, tile=args.tile, tol_64=tol, tol_lo=0.0)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                r = g.loglik_eval(ctx, xd, yd, z, th, opts)
+                torch.cuda.synchronize()
+                dt = time.perf_counter() - t0
+                st = g.gl_precision_stats(ctx)
+                err = abs(r["loglik"] - r64["loglik"]) / abs(r64["loglik"]) if r["status"] == g.GL_OK else None
+                trade.append({"tol_64": tol, "status": r["status"], "low_precision_work_frac": 1.0 - st["fp64"]["work_frac"],
+                              "rel_err_loglik": err, "speedup_vs_fp64": t64b / dt})
+                log(f"mixed theta_b fp16x3 forced up to nu={tol}: low-precision work "
+                    f"{trade[-1]['low_precision_work_frac']:.4f}, rel err {err}, x{t64b / dt:.2f}")
+            leg["forced_fp16x3"] = trade
         out[label] = leg
     return out
 

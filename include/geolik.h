@@ -305,7 +305,9 @@ int gl_dataset_release(gl_context *ctx, uint64_t ds);
 typedef struct {
     int32_t max_inflight;    /* requests resident on the device at once (1..64) */
     int32_t streams;         /* requests run one at a time per stream outside the fused
-                                launches; this many such streams (1..8) */
+                                launches; this many such streams (1..8), each created
+                                when its first request arrives (the fused launches use
+                                two streams of their own) */
     int32_t batch_small;     /* 1: FP64 requests with n <= small_n (tile 0 or 256, no
                                 reordering) advance together through fused launches,
                                 one factorisation step per launch, tile 256 */

@@ -258,7 +258,7 @@ int64_t near_tiles_for(int b, int32_t requested)
 // and k+1 in one pass.  Panels stay final in place, so the deferred launch
 // reads them from the tiles.  The order of the subtractions differs from the
 // one-panel schedule, the set of products does not.
-int factorize(Lanes &ln, Work &w, hipStream_t s, bool solve, int64_t near)
+int factorize(Lanes &ln, Work &w, hipStream_t s, bool solve, int64_t near, bool first_done)
 {
     hipStream_t la = ln.la;
     GL_HIP_TRY(hipEventRecord(ln.fork, s));
@@ -267,8 +267,9 @@ int factorize(Lanes &ln, Work &w, hipStream_t s, bool solve, int64_t near)
     int64_t js = w.nt;  // columns >= js take the current pair of panels in one pass
     for (int64_t k = 0; k < w.nt; ++k) {
         const double below = (double)(w.nt - k - 1);
-        timed(ln.prof, GL_PHASE_POTRF, b3 / 3.0, s,
-              [&] { launch_potrf(w.tiles, w.b, k, w.n, w.info, w.logsum, w.dinv_k(k), s); });
+        if (k > 0 || !first_done)
+            timed(ln.prof, GL_PHASE_POTRF, b3 / 3.0, s,
+                  [&] { launch_potrf(w.tiles, w.b, k, w.n, w.info, w.logsum, w.dinv_k(k), s); });
         timed(ln.prof, GL_PHASE_TRSM, b3 * below, s,
               [&] { launch_trsm(w.tiles, w.b, w.nt, k, w.dinv_k(k), w.info, s); });
         // Panel k is final here: the bulk update may start.  The forward solve

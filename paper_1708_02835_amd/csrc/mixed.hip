@@ -702,6 +702,12 @@ int mixed_factorize(Lanes &ln, Work &w, gl_theta th, const gl_opts &o, hipStream
     int rc = build_lists(w, o, s, plan);
     if (rc != GL_OK) return rc;
     if (plan_out) *plan_out = plan;
+    // Every tile binary64 (the thresholds found no tile whose class error
+    // stays within the accuracy target): the binary64 schedule, with its
+    // two-panel passes, continues after the POTRF of tile 0 done above.
+    bool all64 = true;
+    for (int c = 1; c < NCLASS; ++c) all64 = all64 && plan.tiles[c] == 0;
+    if (all64) return factorize(ln, w, s, true, near_tiles_for(w.b, o.near_tiles), true);
     hipStream_t la = ln.la;
     const bool pairs = w.precision == GL_MIXED_BF16 || w.precision == GL_MIXED_FP16;
     // Split-product tiles per column, for the split column of each pair below.

@@ -385,9 +385,26 @@ void retire_ticks(lq_queue *q, Cohort &co)
 }
 
 
+// A slot's stream, lookahead lane, event and pinned result are created on
+// its first request.  The usual serving load (binary64, n <= small_n) runs
+// through the fused launches on the two cohort streams only, so a queue adds
+// two streams to the process, within the four hardware queues a process gets
+// by default, and the cohorts do not share a hardware queue with idle slots.
+static int slot_open(Slot &sl)
+{
+    if (sl.s) return GL_OK;
+    GL_HIP_TRY(hipStreamCreateWithFlags(&sl.s, hipStreamNonBlocking));
+    if (sl.ln.create() != GL_OK) return GL_EHIP;
+    GL_HIP_TRY(hipEventCreateWithFlags(&sl.done, hipEventDisableTiming));
+    GL_HIP_TRY(hipHostMalloc(reinterpret_cast<void **>(&sl.res_h), sizeof(DevResult), hipHostMallocDefault));
+    return GL_OK;
+}
+
 // Launch request r on slot sl (queue lock released by the caller).
 int launch_on_slot(gl_context *ctx, Slot &sl, Request *r)
 {
+    int rc0 = slot_open(sl);
+    if (rc0 != GL_OK) return rc0;
     const int64_t n = r->ds->n;
     const int b = pick_tile(n, r->o.tile);
     int rc = sl.w.ensure(ctx, n, b, r->o.precision);
@@ -619,17 +636,7 @@ int lq_create(gl_context *ctx, const lq_config *cfg, lq_queue **out)
     q->ctx = ctx;
     q->cfg = c;
     q->budget = c.hbm_budget_bytes ? c.hbm_budget_bytes : ctx->budget;
-    q->slots.resize(c.streams);
-    for (Slot &sl : q->slots) {
-        if (hipStreamCreateWithFlags(&sl.s, hipStreamNonBlocking) != hipSuccess || sl.ln.create() != GL_OK ||
-            hipEventCreateWithFlags(&sl.done, hipEventDisableTiming) != hipSuccess ||
-            hipHostMalloc(reinterpret_cast<void **>(&sl.res_h), sizeof(DevResult), hipHostMallocDefault) !=
-                hipSuccess) {
-            q->stop = true;
-            lq_destroy(q);
-            return GL_EHIP;
-        }
-    }
+    q->slots.resize(c.streams);  // their streams are created on first use (slot_open)
     for (Cohort &c : q->co) {
         bool ok = hipStreamCreateWithFlags(&c.s, hipStreamNonBlocking) == hipSuccess;
         for (TickBuf &tb : c.ring)

@@ -47,6 +47,7 @@ __device__ inline void trailing_tile(int64_t t, int64_t jbeg, int64_t nt, int64_
 // rows are padded to 144 doubles so that the two 16-lane halves of an MFMA
 // operand read (rows k and k+1) fall in different banks.
 constexpr int GP = GB + 16;  // LDS row pitch (doubles)
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
 
 //
 // With a second pair of operands (A2t, B2t non-null: PAIR) the K loop runs
@@ -75,16 +76,21 @@ __device__ __forceinline__ void trailing_core(const double *__restrict__ At, con
     const int le = (tid & 15) * 2;  // rows le + 32 q, le + 32 q + 1 (q = 0..3)
 
     // the C block's loads go first, so their latency overlaps the staging of
-    // the first chunk; the accumulators are negated once both have arrived
+    // the first chunk; the accumulators are negated once both have arrived.
+    // C goes through buffer loads and stores: one per-lane offset register
+    // and uniform offsets per element, so no 64-bit address of the 64
+    // elements stays live across the k loop
+    const __amdgpu_buffer_rsrc_t crs = __builtin_amdgcn_make_buffer_rsrc(C, (short)0, B * B * 8, 0x00020000);
+    const int cvo = ((wn * 64 + mfma_row(lane, 0)) * B + wm * 64 + mfma_col(lane)) * 8;
     d4 acc[4][4];
 #pragma unroll
     for (int a = 0; a < 4; ++a)
 #pragma unroll
-        for (int b = 0; b < 4; ++b) {
-            const int row = wm * 64 + a * 16 + mfma_col(lane);
+        for (int b = 0; b < 4; ++b)
 #pragma unroll
-            for (int r = 0; r < 4; ++r) acc[a][b][r] = C[(int64_t)(wn * 64 + b * 16 + mfma_row(lane, r)) * B + row];
-        }
+            for (int r = 0; r < 4; ++r)
+                acc[a][b][r] = __builtin_bit_cast(
+                    double, __builtin_amdgcn_raw_buffer_load_b64(crs, cvo, ((b * 16 + 4 * r) * B + a * 16) * 8, 0));
     d2 ra[4], rbv[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
@@ -132,6 +138,10 @@ __device__ __forceinline__ void trailing_core(const double *__restrict__ At, con
 #pragma unroll
                 for (int b = 0; b < 4; ++b) acc[a][b] = mfma_f64(bv[b], av[a], acc[a][b]);
         }
+        // keep the staging of the next chunk after this chunk's products: its
+        // stores wait for global loads issued at the top of the iteration, and
+        // hoisted above the products they would expose that latency
+        __builtin_amdgcn_sched_barrier(0);
         if (kc + 1 < NK) {
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
@@ -145,11 +155,11 @@ __device__ __forceinline__ void trailing_core(const double *__restrict__ At, con
 #pragma unroll
     for (int a = 0; a < 4; ++a)
 #pragma unroll
-        for (int b = 0; b < 4; ++b) {
-            const int row = wm * 64 + a * 16 + mfma_col(lane);
+        for (int b = 0; b < 4; ++b)
 #pragma unroll
-            for (int r = 0; r < 4; ++r) C[(int64_t)(wn * 64 + b * 16 + mfma_row(lane, r)) * B + row] = -acc[a][b][r];
-        }
+            for (int r = 0; r < 4; ++r)
+                __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, -acc[a][b][r]), crs, cvo,
+                                                      ((b * 16 + 4 * r) * B + a * 16) * 8, 0);
 }
 
 // One 128×128 block (rb, cb) of the update of tile (i, j) by panel column k

@@ -245,3 +245,23 @@ def test_adaptive_thresholds_follow_first_tile_pivots(g, ctx):
         t16 = g.gl_precision_stats(ctx)["thresholds"]
         assert t16["rho"] == thr["rho"]
         assert t16["tol_64"] == er * 2.0 ** 22 and t16["tol_hi"] == t16["tol_64"] and t16["tol_lo"] == er * 2.0 ** 11
+
+
+@pytest.mark.parametrize("prec", [1, 2, 3])
+def test_mixed_all_binary64_map_runs_the_fp64_schedule(g, ctx, prec):
+    """When the precision map keeps every tile in binary64 (tol_64 = 0 here;
+    the adaptive thresholds do the same at θ = (1, 0.3, 1.0) and n = 100,000),
+    the mixed modes run the binary64 schedule after tile 0's POTRF: the result
+    equals the binary64 path in the same (Morton) order bit for bit, with the
+    two-panel passes forced on (near_tiles = 3)."""
+    theta = (1.0, 0.3, 1.0)
+    x, y, z, ref = _problem(theta)
+    xd, yd, zd = dev(x), dev(y), dev(z)
+    r = g.loglik_eval(ctx, xd, yd, zd, theta,
+                      g.gl_opts_default(precision=prec, tile=256, tol_64=0.0, near_tiles=3))
+    st = g.gl_precision_stats(ctx)
+    assert st["fp64"]["work_frac"] == 1.0
+    r64 = g.loglik_eval(ctx, xd, yd, zd, theta, g.gl_opts_default(precision=0, tile=256, reorder=1, near_tiles=3))
+    assert r["status"] == g.GL_OK
+    assert (r["loglik"], r["logdet"], r["quad"]) == (r64["loglik"], r64["logdet"], r64["quad"])
+    assert rel(r["loglik"], ref[0]) <= 1e-10
