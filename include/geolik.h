@@ -401,7 +401,9 @@ enum {
     GL_PHASE_TRAIL_CRIT = 4, /* trailing update of the next tile column, critical path */
     GL_PHASE_TRAIL_BULK = 5, /* trailing update of the other columns, lookahead stream */
     GL_PHASE_REDUCE = 6,     /* log|Σ|, ZᵀΣ⁻¹Z and l(θ) (Eq. 1) */
-    GL_NPHASE = 7
+    GL_PHASE_TRAIL_PAIR = 7, /* trailing updates of the far columns by two panels in one pass
+                                (lookahead stream; see gl_opts.near_tiles) */
+    GL_NPHASE = 8
 };
 int gl_profile_enable(gl_context *ctx, int32_t on);
 /* Synchronises the device and returns, per phase (GL_NPHASE values each; any
@@ -410,7 +412,7 @@ int gl_profile_enable(gl_context *ctx, int32_t on);
  * per diagonal tile update; generation and reduction: 0) and the launch count
  * since the last read, then resets them. */
 int gl_profile_phases(gl_context *ctx, double *ms_h, double *flops_h, int64_t *launches_h);
-/* The same for the two trailing phases together (one value each). */
+/* The same for the three trailing phases together (one value each). */
 int gl_profile_read(gl_context *ctx, double *ms_h, double *flops_h, int64_t *launches_h);
 
 #ifdef __cplusplus

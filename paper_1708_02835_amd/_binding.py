@@ -432,7 +432,7 @@ def gl_selftest(ctx: Context, which: int):
     return np.frombuffer(out, dtype=np.float64).copy()
 
 
-PHASES = ("gen", "potrf", "trsm", "solve", "trail_crit", "trail_bulk", "reduce")  # GL_PHASE_* order
+PHASES = ("gen", "potrf", "trsm", "solve", "trail_crit", "trail_bulk", "reduce", "trail_pair")  # GL_PHASE_* order
 
 
 def gl_profile_enable(ctx: Context, on=True) -> None:

@@ -233,7 +233,7 @@ static double trailing_flops(int64_t nt, int64_t jbeg, int64_t jend, int b)
 static void trailing(Lanes &ln, Work &w, int64_t k, int64_t jbeg, int64_t jend, hipStream_t s, bool critical,
                      bool pair = false)
 {
-    timed(ln.prof, critical ? GL_PHASE_TRAIL_CRIT : GL_PHASE_TRAIL_BULK,
+    timed(ln.prof, critical ? GL_PHASE_TRAIL_CRIT : pair ? GL_PHASE_TRAIL_PAIR : GL_PHASE_TRAIL_BULK,
           (pair ? 2.0 : 1.0) * trailing_flops(w.nt, jbeg, jend, w.b), s,
           [&] { launch_trailing(w.tiles, w.b, w.nt, k, jbeg, jend, w.info, critical, pair, s); });
 }
@@ -969,9 +969,9 @@ int gl_profile_read(gl_context *ctx, double *ms_h, double *flops_h, int64_t *lau
     int64_t cnt[GL_NPHASE];
     const int rc = gl_profile_phases(ctx, ms, fl, cnt);
     if (rc != GL_OK) return rc;
-    if (ms_h) *ms_h = ms[GL_PHASE_TRAIL_CRIT] + ms[GL_PHASE_TRAIL_BULK];
-    if (flops_h) *flops_h = fl[GL_PHASE_TRAIL_CRIT] + fl[GL_PHASE_TRAIL_BULK];
-    if (launches_h) *launches_h = cnt[GL_PHASE_TRAIL_CRIT] + cnt[GL_PHASE_TRAIL_BULK];
+    if (ms_h) *ms_h = ms[GL_PHASE_TRAIL_CRIT] + ms[GL_PHASE_TRAIL_BULK] + ms[GL_PHASE_TRAIL_PAIR];
+    if (flops_h) *flops_h = fl[GL_PHASE_TRAIL_CRIT] + fl[GL_PHASE_TRAIL_BULK] + fl[GL_PHASE_TRAIL_PAIR];
+    if (launches_h) *launches_h = cnt[GL_PHASE_TRAIL_CRIT] + cnt[GL_PHASE_TRAIL_BULK] + cnt[GL_PHASE_TRAIL_PAIR];
     return GL_OK;
 }
 

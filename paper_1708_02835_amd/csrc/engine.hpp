@@ -77,7 +77,10 @@ struct Prof {
     std::vector<hipEvent_t> pool;
     std::vector<Mark> pending;  // in launch order
     bool all = false;           // every phase; otherwise the trailing updates only
-    bool wants(int phase) const { return all || phase == GL_PHASE_TRAIL_CRIT || phase == GL_PHASE_TRAIL_BULK; }
+    bool wants(int phase) const
+    {
+        return all || phase == GL_PHASE_TRAIL_CRIT || phase == GL_PHASE_TRAIL_BULK || phase == GL_PHASE_TRAIL_PAIR;
+    }
     hipEvent_t take();
     void begin(hipStream_t s, Mark &m);
     void end(hipStream_t s, Mark &m, int phase, double flops);

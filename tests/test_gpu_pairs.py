@@ -91,7 +91,9 @@ def test_fp64_pairs_profile_flops_and_graph(g, ctx):
         g.gl_profile_enable(ctx, 0)
     b3 = float(tile) ** 3
     flops = sum(2 * b3 * (nt - j - 1) + tile * tile * (tile + 1) for k in range(nt - 1) for j in range(k + 1, nt))
-    assert ph["trail_crit"]["flops"] + ph["trail_bulk"]["flops"] == pytest.approx(flops, rel=1e-12)
+    assert ph["trail_crit"]["flops"] + ph["trail_bulk"]["flops"] + ph["trail_pair"]["flops"] == pytest.approx(
+        flops, rel=1e-12)
+    assert ph["trail_pair"]["launches"] > 0
     o = dict(tile=tile, near_tiles=1)
     eager = g.loglik_eval(ctx, xd, yd, zd, theta, g.gl_opts_default(**o))
     for _ in range(2):

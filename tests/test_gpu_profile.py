@@ -43,12 +43,13 @@ def test_phase_counts_flops_and_results(g, n, tile):
         off = g.gl_profile_phases(ctx)
     assert timed["loglik"] == plain["loglik"] and timed["logdet"] == plain["logdet"]
     want = {"gen": 1, "potrf": nt, "trsm": nt, "solve": 2 * nt, "trail_crit": nt - 1,
-            "trail_bulk": max(nt - 2, 0), "reduce": 1}
+            "trail_bulk": max(nt - 2, 0), "reduce": 1, "trail_pair": 0}
     assert {p: v["launches"] for p, v in ph.items()} == want
     assert all(v["ms"] > 0 for p, v in ph.items() if v["launches"])
     b3 = float(tile) ** 3
     flops = sum(2 * b3 * (nt - j - 1) + tile * tile * (tile + 1) for k in range(nt - 1) for j in range(k + 1, nt))
     assert ph["trail_crit"]["flops"] + ph["trail_bulk"]["flops"] == pytest.approx(flops, rel=1e-12)
+    assert ph["trail_pair"]["launches"] == 0  # no two-panel passes at this size
     assert {p: v["launches"] for p, v in trail_only.items()} == dict(
         {p: 0 for p in want}, trail_crit=nt - 1, trail_bulk=max(nt - 2, 0))
     assert all(v["launches"] == 0 for v in off.values())
