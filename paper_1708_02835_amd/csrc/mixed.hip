@@ -438,17 +438,21 @@ __global__ __launch_bounds__(256, 2) void trailing_bf16_kernel(float *__restrict
             }
     };
     if constexpr (NP <= 2) {
+        // the prefetches are unconditional (the last chunk is loaded again
+        // near the end and never stored): with a load count that does not
+        // depend on the path, the wait before storing one register set
+        // leaves the other set's loads in flight instead of draining them
         load(ra0, rb0, 0);
         load(ra1, rb1, 1);
         for (int kc = 0; kc < NKT; kc += 2) {
             store(ra0, rb0);
             __syncthreads();
-            if (kc + 2 < NKT) load(ra0, rb0, kc + 2);
+            load(ra0, rb0, kc + 2 < NKT ? kc + 2 : NKT - 1);
             compute();
             __syncthreads();
             store(ra1, rb1);
             __syncthreads();
-            if (kc + 3 < NKT) load(ra1, rb1, kc + 3);
+            load(ra1, rb1, kc + 3 < NKT ? kc + 3 : NKT - 1);
             compute();
             __syncthreads();
         }
