@@ -607,7 +607,7 @@ def serving_leg(g, ctx, args, log):
                 res = optimize.minimize(negl, np.log(SERVE_THETA0), method="Nelder-Mead",
                                         bounds=list(zip(lo, hi)),
                                         options={"maxfev": maxfev, "xatol": 1e-5, "fatol": 1e-7})
-                found[c] = [float(t) for t in np.exp(res.x)]
+                found[c] = ([float(t) for t in np.exp(res.x)], bool(res.success))
             except Exception as exc:  # noqa: BLE001
                 errors.append(repr(exc))
 
@@ -652,8 +652,11 @@ def serving_leg(g, ctx, args, log):
     ns = [f["n"] for f in fields]
     single_rate = clients * replay / t_single
     log(f"serving: one at a time {single_rate:.1f} evals/s ({clients * replay} replayed)")
-    rel_theta = [float(np.max(np.abs(np.array(found[c]) - np.array(fields[c]["theta"])) /
+    # statistical, not parity: θ̂ after at most --serve-evals evaluations
+    # (Nelder-Mead from (1, 0.1, 1.0) has often not converged by then)
+    rel_theta = [float(np.max(np.abs(np.array(found[c][0]) - np.array(fields[c]["theta"])) /
                               np.array(fields[c]["theta"]))) for c in range(clients)]
+    converged = sum(1 for c in range(clients) if found[c][1])
     return {"clients": clients, "max_evals_per_client": maxfev, "evals": total,
             "evals_per_client": {"min": min(len(h) for h in hist), "max": max(len(h) for h in hist)},
             "optimizer": "bounded Nelder-Mead on log theta from (1, 0.1, 1.0), closed loop",
@@ -664,7 +667,9 @@ def serving_leg(g, ctx, args, log):
             "one_at_a_time_evals_per_s": single_rate, "one_at_a_time_sample": clients * replay,
             "speedup_vs_one_at_a_time": total / wall / single_rate,
             "status_counts": statuses, "max_rel_diff_vs_one_at_a_time": worst,
-            "theta_hat_max_rel_err_vs_truth": {"median": float(np.median(rel_theta)), "max": float(np.max(rel_theta))},
+            "optimizers_converged_within_max_evals": converged,
+            "theta_at_end_max_rel_diff_vs_truth": {"median": float(np.median(rel_theta)),
+                                                   "max": float(np.max(rel_theta))},
             "peak_inflight": stats["peak_inflight"], "peak_bytes": stats["peak_bytes"],
             "fused_launches": stats["fused_launches"],
             "ticks": {"count": ticks["ticks"],
