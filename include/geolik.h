@@ -124,7 +124,7 @@ typedef struct {
                             panels per pass (K = 2b) to the columns beyond the nearest ones: at
                             an even step k the next column and the nearest columns holding about
                             near_tiles tiles get panel k alone, the others get panels k and k+1
-                            together at step k+1.  0: automatic, 512 (512/b)³ tiles (GL_FP64) or
+                            together at step k+1.  0: automatic, b tiles (GL_FP64) or
                             1536 (512/b)³ split-product tiles (mixed modes); > 0: that many */
 } gl_opts;
 

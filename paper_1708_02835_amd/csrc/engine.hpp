@@ -102,7 +102,7 @@ size_t work_bytes(int64_t n, int b, int precision);
 // first_done: the POTRF of tile 0 has already run (logsum[0], dinv of step 0).
 int factorize(Lanes &ln, Work &w, hipStream_t s, bool solve, int64_t near, bool first_done = false);
 // Tiles updated one panel at a time at even steps (gl_opts.near_tiles; 0:
-// 512 (512/b)³, about 2 ms of binary64 update at tile 512).
+// b tiles, about 2.6 ms of binary64 update at tile 512).
 int64_t near_tiles_for(int b, int32_t requested);
 // Enqueue a whole evaluation on s (inputs already in w.x, w.y, w.v) and the
 // copy of its scalar results to out_h; does not wait.

@@ -1,8 +1,9 @@
 """Two panels per trailing pass (gl_opts.near_tiles).
 
 The far columns of a step pair receive panels k and k+1 in one pass (K = 2b).
-At the default setting this only happens at large n (more than 512 (512/b)³
-tiles), so these tests force it at small n with a small near_tiles and check:
+At the default setting this starts once the tile count exceeds b tiles
+(from about n = 6,000 at tile 256), so these tests force it at small n with a
+small near_tiles and check:
 
 * binary64: the result against the oracle at the FP64 bound, and against the
   one-panel schedule (near_tiles beyond the tile count) to a few ulps of
