@@ -53,6 +53,7 @@ def parse():
     p.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision legs")
     p.add_argument("--theta-b", type=float, nargs=3, default=(1.0, 0.3, 1.0),
                    help="second parameter vector of the mixed-precision comparison")
+    p.add_argument("--no-theta-b", action="store_true", help="mixed leg: skip the second theta")
     p.add_argument("--no-serve", action="store_true", help="skip the serving leg")
     p.add_argument("--no-ind", action="store_true", help="skip the independent-blocks leg")
     p.add_argument("--no-graph", action="store_true", help="skip the small-n graph-replay latency leg")
@@ -187,7 +188,10 @@ def mixed_legs(g, ctx, xd, yd, ed, zd, theta, theta_b, args, res64, t64, log):
         stats = g.gl_precision_stats(ctx) if prec != g.GL_FP64 else None
         return r, dt, stats
 
-    for label, th, z, steps in (("theta_a", theta, zd, min(args.steps, 3)), ("theta_b", theta_b, None, 1)):
+    legs = [("theta_a", theta, zd, min(args.steps, 3))]
+    if not args.no_theta_b:
+        legs.append(("theta_b", theta_b, None, 1))
+    for label, th, z, steps in legs:
         if z is None:
             z, info = g.synth_generate(ctx, xd, yd, ed, th, args.tile)
             if info != 0:
