@@ -497,6 +497,146 @@ __global__ __launch_bounds__(256, 2) void trailing_bf16_kernel(float *__restrict
         }
 }
 
+// ---------------------------------- wide two-part split-product update ----
+
+// The same update for the two-part classes (BF16x3, FP16x3) with a 256×256
+// output block per workgroup: 512 threads (one workgroup per CU, two waves
+// per SIMD), eight waves of 128×64 in a 2×4 arrangement.  Every staged
+// operand byte feeds twice the products of the 128×128 kernel above, whose
+// operand streams bound it.  Staging: one register set holding the
+// next-but-one chunk and two LDS buffers (128 KB), swizzled as above.
+constexpr int WB = 256;
+
+template <int B, bool F16>
+__global__ __launch_bounds__(512, 1) void trailing_split2_wide_kernel(float *__restrict__ delta,
+                                                                      const uint16_t *__restrict__ planes,
+                                                                      const uint16_t *__restrict__ planes_prev,
+                                                                      int64_t plane_stride,
+                                                                      const int2 *__restrict__ list,
+                                                                      int64_t nblocks,
+                                                                      const int64_t *__restrict__ info,
+                                                                      int critical, float unscale)
+{
+    if (*info != 0) return;
+    if (critical) __builtin_amdgcn_s_setprio(3);
+    constexpr int NP = 2;
+    constexpr int SB = B / WB;
+    int64_t t;
+    int sub;
+    bool valid;
+    list_tile(list, gridDim.x, nblocks, SB * SB, t, sub, valid);
+    if (!valid) return;
+    const int2 ij = list[t];
+    const int rb = sub / SB, cb = sub % SB;
+    const int64_t aoff = (int64_t)ij.x * B * B + (int64_t)(rb * WB) * B;
+    const int64_t boff = (int64_t)ij.y * B * B + (int64_t)(cb * WB) * B;
+    const uint16_t *first = planes_prev ? planes_prev : planes;
+    float *C = delta + tile_offset(ij.x, ij.y, B) + (int64_t)(cb * WB) * B + rb * WB;
+
+    __shared__ uint16_t As[2][NP][WB][HP];
+    __shared__ uint16_t Bs[2][NP][WB][HP];
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+    const int wm = wave >> 2, wn = wave & 3;  // rows wm·128, columns wn·64
+    typedef uint32_t u4 __attribute__((ext_vector_type(4)));
+
+    f4 acc[8][4];
+#pragma unroll
+    for (int a = 0; a < 8; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] = (f4){0.f, 0.f, 0.f, 0.f};
+
+    // 256 rows × 4 pieces of 16 bytes per operand and part: two per thread
+    constexpr int NK = B / HK;
+    const int NKT = planes_prev ? 2 * NK : NK;
+    u4 ra[NP][2], rbv[NP][2];
+    auto load = [&](int kc) {
+        const bool second = kc >= NK;
+        const uint16_t *P = second ? planes : first;
+        const uint16_t *Ap = P + aoff, *Bp = P + boff;
+        const int k0 = (second ? kc - NK : kc) * HK;
+#pragma unroll
+        for (int p = 0; p < NP; ++p)
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int piece = tid + 512 * h;
+                const int row = piece >> 2, part = piece & 3;
+                ra[p][h] = *reinterpret_cast<const u4 *>(Ap + p * plane_stride + (int64_t)row * B + k0 + part * 8);
+                rbv[p][h] = *reinterpret_cast<const u4 *>(Bp + p * plane_stride + (int64_t)row * B + k0 + part * 8);
+            }
+    };
+    auto store = [&](int buf) {
+#pragma unroll
+        for (int p = 0; p < NP; ++p)
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int piece = tid + 512 * h;
+                const int row = piece >> 2, part = swz_part(row, piece & 3);
+                *reinterpret_cast<u4 *>(&As[buf][p][row][part * 8]) = ra[p][h];
+                *reinterpret_cast<u4 *>(&Bs[buf][p][row][part * 8]) = rbv[p][h];
+            }
+    };
+    auto mm = [](const bf16x8 &x, const bf16x8 &y, f4 c) {
+        if constexpr (F16) return mfma_f16(__builtin_bit_cast(f16x8, x), __builtin_bit_cast(f16x8, y), c);
+        else return mfma_bf16(x, y, c);
+    };
+    auto frag = [&](const uint16_t (*S)[HP], int row0, int q) {
+        const int r = row0 + q * 16 + (lane & 15);
+        return *reinterpret_cast<const bf16x8 *>(&S[r][8 * swz_part(r, lane >> 4)]);
+    };
+    auto compute = [&](int buf) {
+        // the wave's four B fragments of both parts stay in registers while
+        // its eight A fragments of both parts stream past them: products
+        // B_h A_h, B_l A_h, B_h A_l (operands swapped: result row = C column,
+        // lane % 16 = C row); four independent products separate two updates
+        // of one accumulator
+        bf16x8 bh[4], bl[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            bh[q] = frag(Bs[buf][0], wn * 64, q);
+            bl[q] = frag(Bs[buf][1], wn * 64, q);
+        }
+#pragma unroll
+        for (int a = 0; a < 8; ++a) {
+            const bf16x8 ah = frag(As[buf][0], wm * 128, a), al = frag(As[buf][1], wm * 128, a);
+#pragma unroll
+            for (int b = 0; b < 4; ++b) acc[a][b] = mm(bh[b], ah, acc[a][b]);
+#pragma unroll
+            for (int b = 0; b < 4; ++b) acc[a][b] = mm(bl[b], ah, acc[a][b]);
+#pragma unroll
+            for (int b = 0; b < 4; ++b) acc[a][b] = mm(bh[b], al, acc[a][b]);
+        }
+    };
+    // chunk kc is computed from buffer kc & 1; the registers hold chunk kc + 1
+    // while kc is computed and go to the other buffer after it
+    load(0);
+    store(0);
+    load(NKT > 1 ? 1 : 0);
+    __syncthreads();
+    for (int kc = 0; kc < NKT; ++kc) {
+        compute(kc & 1);
+        __builtin_amdgcn_sched_barrier(0);
+        if (kc + 1 < NKT) {
+            store((kc + 1) & 1);
+            load(kc + 2 < NKT ? kc + 2 : NKT - 1);
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int a = 0; a < 8; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            const int row = wm * 128 + a * 16 + mfma_col(lane);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int64_t col = wn * 64 + b * 16 + mfma32_row(lane, r);
+                const float v = F16 ? acc[a][b][r] * unscale : acc[a][b][r];  // exact: a power of two
+                C[col * B + row] -= v;
+            }
+        }
+}
+
 // ------------------------------------------------------------- launchers --
 
 // Split-product classes (bfloat16 and binary16 parts) can take the updates of
@@ -527,16 +667,28 @@ static void launch_class(int cls, double *tiles, int64_t k, const MixedViews &mv
                                                                  nblocks, info, crit, 1.0f);
         break;
     case CB3:
-        trailing_bf16_kernel<B, 2, false><<<grid, 256, 0, s>>>(mv.delta, mv.planes[par], prev, mv.plane_stride, list,
-                                                                 nblocks, info, crit, 1.0f);
+        if constexpr (B % WB == 0) {
+            const int64_t wblocks = count * (B / WB) * (B / WB);
+            trailing_split2_wide_kernel<B, false><<<(unsigned)(ceil_div(wblocks, 8) * 8), 512, 0, s>>>(
+                mv.delta, mv.planes[par], prev, mv.plane_stride, list, wblocks, info, crit, 1.0f);
+        } else {
+            trailing_bf16_kernel<B, 2, false><<<grid, 256, 0, s>>>(mv.delta, mv.planes[par], prev, mv.plane_stride,
+                                                                     list, nblocks, info, crit, 1.0f);
+        }
         break;
     case CB1:
         trailing_bf16_kernel<B, 1, false><<<grid, 256, 0, s>>>(mv.delta, mv.planes[par], prev, mv.plane_stride, list,
                                                                  nblocks, info, crit, 1.0f);
         break;
     case CH2:
-        trailing_bf16_kernel<B, 2, true><<<grid, 256, 0, s>>>(mv.delta, mv.planes[par], prev, mv.plane_stride, list,
-                                                                nblocks, info, crit, mv.f16_unscale);
+        if constexpr (B % WB == 0) {
+            const int64_t wblocks = count * (B / WB) * (B / WB);
+            trailing_split2_wide_kernel<B, true><<<(unsigned)(ceil_div(wblocks, 8) * 8), 512, 0, s>>>(
+                mv.delta, mv.planes[par], prev, mv.plane_stride, list, wblocks, info, crit, mv.f16_unscale);
+        } else {
+            trailing_bf16_kernel<B, 2, true><<<grid, 256, 0, s>>>(mv.delta, mv.planes[par], prev, mv.plane_stride,
+                                                                    list, nblocks, info, crit, mv.f16_unscale);
+        }
         break;
     default:
         trailing_bf16_kernel<B, 1, true><<<grid, 256, 0, s>>>(mv.delta, mv.planes[par], prev, mv.plane_stride, list,
