@@ -120,7 +120,7 @@ size_t mixed_extra_bytes(int64_t nt, int b, int precision);
 void mixed_views(Work &w);
 int mixed_factorize(Lanes &ln, Work &w, gl_theta th, const gl_opts &o, hipStream_t s, MixedPlan *plan_out);
 void launch_trailing_list(double *tiles, int b, int64_t k, const int2 *list, int64_t count,
-                          const int64_t *info, bool critical, hipStream_t s);
+                          const int64_t *info, bool critical, bool pair, hipStream_t s);
 // Morton reordering (reorder.hip); keys holds npow2(n) + 4 words
 int64_t npow2_of(int64_t n);
 void launch_morton_order(const double *x, const double *y, const double *z, int64_t n, int64_t npad,

@@ -641,8 +641,10 @@ __global__ __launch_bounds__(512, 1) void trailing_split2_wide_kernel(float *__r
 
 // Split-product classes (bfloat16 and binary16 parts) can take the updates of
 // steps k-1 and k in one launch (pair = true: the parts of both panels are
-// held, by parity).
-static bool paired_class(int cls) { return cls >= CB6; }
+// held, by parity); so can the binary64 class, whose panels stay in place in
+// the tiles (one read and write of a C tile per two panels, as in the
+// binary64 schedule).  FP32 tiles take one panel per step.
+static bool paired_class(int cls) { return cls == C64 || cls >= CB6; }
 
 template <int B>
 static void launch_class(int cls, double *tiles, int64_t k, const MixedViews &mv, const int2 *list,
@@ -657,7 +659,7 @@ static void launch_class(int cls, double *tiles, int64_t k, const MixedViews &mv
     const uint16_t *prev = pair ? mv.planes[par ^ 1] : nullptr;
     switch (cls) {
     case C64:
-        launch_trailing_list(tiles, B, k, list, count, info, critical, s);
+        launch_trailing_list(tiles, B, k, list, count, info, critical, pair, s);
         break;
     case C32:
         trailing_f32_kernel<B><<<grid, 256, 0, s>>>(mv.delta, mv.p32[par], list, nblocks, info, crit);

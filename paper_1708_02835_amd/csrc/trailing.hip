@@ -276,9 +276,11 @@ void launch_trailing_batched(int b, const BatchReq *d, int count, int64_t blocks
     }
 }
 
-// Trailing updates of the tiles listed in `list` (count tiles, (i, j) pairs).
-void launch_trailing_list(double *tiles, int b, int64_t k, const int2 *list, int64_t count,
-                          const int64_t *info, bool critical, hipStream_t s)
+// Trailing updates of the tiles listed in `list` (count tiles, (i, j) pairs);
+// pair: by panel columns k-1 and k in one pass.
+template <bool PAIR>
+static void launch_trailing_list_t(double *tiles, int b, int64_t k, const int2 *list, int64_t count,
+                                   const int64_t *info, bool critical, hipStream_t s)
 {
     if (count <= 0) return;
     const int64_t sub = (int64_t)(b / GB) * (b / GB);
@@ -286,11 +288,20 @@ void launch_trailing_list(double *tiles, int b, int64_t k, const int2 *list, int
     const int64_t grid = ceil_div(nblocks, 8) * 8;
     const int crit = critical ? 1 : 0;
     switch (b) {
-    case 128: trailing_f64_kernel<128><<<(unsigned)grid, 256, 0, s>>>(tiles, k, 0, 0, nblocks, info, crit, list); break;
-    case 256: trailing_f64_kernel<256><<<(unsigned)grid, 256, 0, s>>>(tiles, k, 0, 0, nblocks, info, crit, list); break;
-    case 384: trailing_f64_kernel<384><<<(unsigned)grid, 256, 0, s>>>(tiles, k, 0, 0, nblocks, info, crit, list); break;
-    default: trailing_f64_kernel<512><<<(unsigned)grid, 256, 0, s>>>(tiles, k, 0, 0, nblocks, info, crit, list); break;
+    case 128: trailing_f64_kernel<128, PAIR><<<(unsigned)grid, 256, 0, s>>>(tiles, k, 0, 0, nblocks, info, crit, list); break;
+    case 256: trailing_f64_kernel<256, PAIR><<<(unsigned)grid, 256, 0, s>>>(tiles, k, 0, 0, nblocks, info, crit, list); break;
+    case 384: trailing_f64_kernel<384, PAIR><<<(unsigned)grid, 256, 0, s>>>(tiles, k, 0, 0, nblocks, info, crit, list); break;
+    default: trailing_f64_kernel<512, PAIR><<<(unsigned)grid, 256, 0, s>>>(tiles, k, 0, 0, nblocks, info, crit, list); break;
     }
+}
+
+void launch_trailing_list(double *tiles, int b, int64_t k, const int2 *list, int64_t count,
+                          const int64_t *info, bool critical, bool pair, hipStream_t s)
+{
+    if (pair)
+        launch_trailing_list_t<true>(tiles, b, k, list, count, info, critical, s);
+    else
+        launch_trailing_list_t<false>(tiles, b, k, list, count, info, critical, s);
 }
 
 // Many right-hand sides, update after diagonal step k (layout of st as for
