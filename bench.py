@@ -108,10 +108,15 @@ CPU_SAMPLE_SIZES = (400, 1600, 2800, 4000)
 
 
 def fit_cubic(ns, ts):
-    """Least-squares t = a n³ + b n² through the timed sizes; returns (a, b)."""
+    """Least-squares t = a n³ + b n² through the timed sizes with a, b >= 0
+    (both terms are work, never negative; noisy small sizes could otherwise
+    give a negative cubic term); returns (a, b)."""
     import numpy as np
+    from scipy.optimize import nnls
     A = np.array([[float(n) ** 3, float(n) ** 2] for n in ns])
-    (a, b), *_ = np.linalg.lstsq(A, np.array(ts, dtype=float), rcond=None)
+    scale = A.max(axis=0)
+    coef, _ = nnls(A / scale, np.array(ts, dtype=float))
+    a, b = coef / scale
     return float(a), float(b)
 
 

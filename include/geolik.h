@@ -126,7 +126,11 @@ typedef struct {
                             near_tiles tiles get panel k alone, the others get panels k and k+1
                             together at step k+1.  0: automatic, b tiles (GL_FP64) or
                             1536 (512/b)³ split-product tiles (mixed modes); > 0: that many */
+    int32_t layout;      /* matern_generate only: GL_LAYOUT_DENSE (default) or
+                            GL_LAYOUT_LOWER_TILES (see there) */
 } gl_opts;
+
+enum { GL_LAYOUT_DENSE = 0, GL_LAYOUT_LOWER_TILES = 1 };
 
 /* Result of one likelihood evaluation, host memory. */
 typedef struct {
@@ -159,6 +163,12 @@ void gl_opts_default(gl_opts *opts);
 /* Static English description of a gl_status value. */
 const char *gl_status_string(int status);
 
+/* Tile size b a likelihood evaluation of size n uses for the requested tile
+ * (0 = automatic: 128 up to n = 3,000, 256 up to 24,000, 512 beyond).
+ * Returns b, or GL_EINVAL for n < 1 or a tile other than 0, 128, 256, 384,
+ * 512.  Host arithmetic only. */
+int32_t gl_pick_tile(int64_t n, int32_t tile);
+
 /* Device bytes a likelihood evaluation of size n at tile b holds
  * (packed lower tiles plus vectors), b = 0 meaning the automatic choice. */
 size_t gl_footprint_bytes(int64_t n, int32_t tile, int32_t precision);
@@ -177,12 +187,22 @@ int gl_workspace_layout(int64_t n, int32_t tile, int32_t precision, size_t *tile
 
 /*
  * Matérn covariance between point sets 1 and 2, Sec. 2.2 Eq. (2) with the
- * distance of opts->metric (NULL opts: Euclidean; other fields ignored)
- * (genDistanceMatrix + genCovMatrix of Alg. 1-3, the distance matrix is never
- * stored).  r == 0 gives θ1.
- * Output: column-major n1×n2, out[i + j*ld], ld >= n1; the caller owns it.
- * Errors: GL_EINVAL for n1 < 1, n2 < 1, ld < n1, NULL pointers, bad θ or a
- * bad metric/radius.
+ * distance of opts->metric (NULL opts: Euclidean, dense layout; other fields
+ * ignored except layout and tile) (genDistanceMatrix + genCovMatrix of
+ * Alg. 1-3, the distance matrix is never stored).  r == 0 gives θ1.
+ * opts->layout:
+ *   GL_LAYOUT_DENSE: column-major n1×n2, out[i + j*ld], ld >= n1.
+ *   GL_LAYOUT_LOWER_TILES: Σ of set 1 with itself (x2, y2 NULL, or equal to
+ *     x1, y1 with n2 == n1; ld ignored) in the packed lower-tile storage the
+ *     likelihood factors: tile size b = opts->tile (0: the automatic choice of
+ *     loglik_eval), NT = ceil(n1 / b) tile rows, tile (i, j), i >= j, a b×b
+ *     column-major block at out + (i(i+1)/2 + j)·b², NT(NT+1)/2·b² doubles in
+ *     all (gl_workspace_layout's tiles bytes / 8).  Diagonal tiles are written
+ *     in full (both triangles); rows and columns beyond n1 are padding, 1 on
+ *     the diagonal and 0 elsewhere.
+ * The caller owns out.
+ * Errors: GL_EINVAL for n1 < 1, NULL pointers, bad θ, a bad metric/radius,
+ * layout or tile, and for the dense layout n2 < 1 or ld < n1.
  */
 int matern_generate(gl_context *ctx, const double *x1, const double *y1, int64_t n1,
                     const double *x2, const double *y2, int64_t n2, gl_theta theta,

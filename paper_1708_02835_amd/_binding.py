@@ -33,6 +33,9 @@ GL_MIXED_FP16 = 3
 GL_EUCLIDEAN = 0
 GL_GREAT_CIRCLE = 1
 
+GL_LAYOUT_DENSE = 0
+GL_LAYOUT_LOWER_TILES = 1
+
 
 class GeolikError(RuntimeError):
     def __init__(self, status: int, what: str = ""):
@@ -49,7 +52,7 @@ class gl_opts(ctypes.Structure):
                 ("band", ctypes.c_int32), ("reorder", ctypes.c_int32), ("metric", ctypes.c_int32),
                 ("tol_hi", ctypes.c_double), ("tol_lo", ctypes.c_double), ("radius", ctypes.c_double),
                 ("tol_64", ctypes.c_double), ("accuracy", ctypes.c_double), ("ind_tiles", ctypes.c_int32),
-                ("graph", ctypes.c_int32), ("near_tiles", ctypes.c_int32)]
+                ("graph", ctypes.c_int32), ("near_tiles", ctypes.c_int32), ("layout", ctypes.c_int32)]
 
 
 class gl_result(ctypes.Structure):
@@ -81,6 +84,7 @@ _SIGNATURES = {
     "gl_opts_default": (None, [ctypes.POINTER(gl_opts)]),
     "gl_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "gl_footprint_bytes": (_SZ, [_I64, _I32, _I32]),
+    "gl_pick_tile": (_I32, [_I64, _I32]),
     "gl_workspace_layout": (_I32, [_I64, _I32, _I32, ctypes.POINTER(_SZ), ctypes.POINTER(_SZ),
                                    ctypes.POINTER(_SZ)]),
     "matern_generate": (_I32, [_P, _P, _P, _I64, _P, _P, _I64, gl_theta, _P, _P, _I64, _P]),
@@ -243,6 +247,35 @@ def matern_generate(ctx: Context, x1, y1, x2, y2, theta, opts: gl_opts | None = 
                                  ctypes.byref(opts) if opts is not None else None, _ptr(out), n1,
                                  _stream(stream)), "matern_generate")
     return out
+
+
+def matern_generate_tiles(ctx: Context, x, y, theta, opts: gl_opts | None = None, out=None, stream=None):
+    """Σ(θ) of one point set in the packed lower-tile storage (layout
+    GL_LAYOUT_LOWER_TILES of matern_generate); returns (tiles, b) with tiles a
+    flat float64 tensor of NT(NT+1)/2·b² values."""
+    import torch
+    n = _same_len(x, y)
+    o = gl_opts()
+    if opts is not None:
+        ctypes.memmove(ctypes.byref(o), ctypes.byref(opts), ctypes.sizeof(gl_opts))
+    else:
+        o = gl_opts_default()
+    o.layout = GL_LAYOUT_LOWER_TILES
+    t_bytes, _, _ = gl_workspace_layout(n, o.tile, GL_FP64)
+    if out is None:
+        out = torch.empty(t_bytes // 8, dtype=torch.float64, device=x.device)
+    if out.numel() * 8 < t_bytes:
+        raise ValueError("out must hold the packed lower tiles")
+    _check(lib().matern_generate(ctx.handle, _ptr(x), _ptr(y), n, None, None, 0, _theta(theta), ctypes.byref(o),
+                                 _ptr(out), 0, _stream(stream)), "matern_generate")
+    return out, gl_pick_tile(n, o.tile)
+
+
+def gl_pick_tile(n: int, tile: int = 0) -> int:
+    """The tile size loglik_eval uses for n locations (tile 0: automatic)."""
+    b = lib().gl_pick_tile(int(n), int(tile))
+    _check(b, "gl_pick_tile")
+    return b
 
 
 def loglik_eval(ctx: Context, x, y, z, theta, opts: gl_opts | None = None, stream=None) -> dict:

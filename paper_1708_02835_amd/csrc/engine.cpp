@@ -350,7 +350,14 @@ void gl_opts_default(gl_opts *o)
     o->ind_tiles = 0;
     o->graph = 0;
     o->near_tiles = 0;
+    o->layout = GL_LAYOUT_DENSE;
     o->radius = 6371.0;
+}
+
+int32_t gl_pick_tile(int64_t n, int32_t tile)
+{
+    if (n < 1 || (tile != 0 && tile != 128 && tile != 256 && tile != 384 && tile != 512)) return GL_EINVAL;
+    return pick_tile(n, tile);
 }
 
 size_t gl_footprint_bytes(int64_t n, int32_t tile, int32_t precision)
@@ -437,15 +444,27 @@ int matern_generate(gl_context *ctx, const double *x1, const double *y1, int64_t
                     const double *y2, int64_t n2, gl_theta th, const gl_opts *opts, double *out, int64_t ld,
                     void *stream)
 {
-    if (!ctx || !x1 || !y1 || !x2 || !y2 || !out || n1 < 1 || n2 < 1 || ld < n1 || !valid_theta(th))
-        return GL_EINVAL;
     gl_opts o;
     gl_opts_default(&o);
     if (opts) o = *opts;
-    if (!valid_metric(o)) return GL_EINVAL;
+    if (!ctx || !x1 || !y1 || !out || n1 < 1 || !valid_theta(th) || !valid_metric(o) ||
+        (o.layout != GL_LAYOUT_DENSE && o.layout != GL_LAYOUT_LOWER_TILES))
+        return GL_EINVAL;
+    if (o.layout == GL_LAYOUT_LOWER_TILES) {
+        // Σ of set 1 with itself: set 2 absent or the same arrays
+        if ((x2 || y2) && (x2 != x1 || y2 != y1 || n2 != n1)) return GL_EINVAL;
+        if (o.tile != 0 && o.tile != 128 && o.tile != 256 && o.tile != 384 && o.tile != 512) return GL_EINVAL;
+    } else if (!x2 || !y2 || n2 < 1 || ld < n1) {
+        return GL_EINVAL;
+    }
     GL_HIP_TRY(hipSetDevice(ctx->device));
     hipStream_t s = static_cast<hipStream_t>(stream);
-    launch_gen_dense(x1, y1, n1, x2, y2, n2, th, geom_of(o), out, ld, s);
+    if (o.layout == GL_LAYOUT_LOWER_TILES) {
+        const int b = pick_tile(n1, o.tile);
+        launch_gen_tiles(out, x1, y1, n1, b, ceil_div(n1, b), th, geom_of(o), nullptr, s);
+    } else {
+        launch_gen_dense(x1, y1, n1, x2, y2, n2, th, geom_of(o), out, ld, s);
+    }
     GL_HIP_TRY(hipGetLastError());
     return GL_OK;
 }

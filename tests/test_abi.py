@@ -151,3 +151,12 @@ def test_scratch_limit_matches_header():
     for tile in (0, 128, 256, 384, 512):
         t, v, _ = g.gl_workspace_layout(4096, tile, g.GL_FP64)
         assert ((t + 255) // 256) * 256 + v <= g.GL_SCRATCH_BYTES
+
+
+def test_pick_tile_matches_documented_rule():
+    import paper_1708_02835_amd as g
+    assert [g.gl_pick_tile(n) for n in (1, 3000, 3001, 24000, 24001, 100000)] == [128, 128, 256, 256, 512, 512]
+    assert g.gl_pick_tile(5000, 384) == 384
+    for bad in ((0, 0), (100, 200)):
+        with pytest.raises(g.GeolikError):
+            g.gl_pick_tile(*bad)

@@ -308,3 +308,38 @@ def test_synth_parity(g, ctx, n, tile):
     zg, ginfo = g.synth_generate(ctx, dev(x), dev(y), dev(e), theta, tile)
     assert ginfo == 0
     assert np.max(np.abs(zg.cpu().numpy() - ref)) <= 1e-12 * np.max(np.abs(ref))
+
+
+@pytest.mark.parametrize("n,tile", [(700, 128), (700, 256), (300, 0)])
+def test_matern_generate_lower_tiles(g, ctx, n, tile):
+    """Layout GL_LAYOUT_LOWER_TILES: the packed lower tiles of Σ(set 1) equal
+    the dense layout entry for entry (same evaluator), with the identity
+    padding beyond n; at n = 300 the entries also match the oracle's Eq. (2)."""
+    theta = (1.3, 0.07, 1.5)
+    x, y = geoinputs.jittered_grid(n, 61)
+    xd, yd = dev(x), dev(y)
+    tiles, b = g.matern_generate_tiles(ctx, xd, yd, theta, g.gl_opts_default(tile=tile))
+    assert b == g.gl_pick_tile(n, tile)
+    dense = g.matern_generate(ctx, xd, yd, xd, yd, theta).cpu().numpy().T
+    t = tiles.cpu().numpy()
+    nt = -(-n // b)
+    full = np.zeros((nt * b, nt * b))
+    for i in range(nt):
+        for j in range(i + 1):
+            off = (i * (i + 1) // 2 + j) * b * b
+            full[i * b:(i + 1) * b, j * b:(j + 1) * b] = t[off:off + b * b].reshape(b, b).T
+    low = np.tril_indices(n)
+    assert np.allclose(full[:n, :n][low], dense[low], rtol=1e-14, atol=0.0)
+    pad = full[n:, :]
+    assert np.array_equal(pad[:, :n], np.zeros((nt * b - n, n)))
+    assert np.array_equal(np.tril(full[n:, n:]), np.eye(nt * b - n))
+    if n <= 300:
+        ref = oracle.cov_symmetric(x, y, theta)
+        assert np.max(np.abs(full[:n, :n][low] - ref[low]) / np.abs(ref[low])) <= 1e-12
+    # Σ of one set only: another set 2, or a bad layout, is rejected
+    with pytest.raises(g.GeolikError):
+        bad = g.gl_opts_default(layout=g.GL_LAYOUT_LOWER_TILES)
+        g.matern_generate(ctx, xd, yd, xd[:10], yd[:10], theta, bad,
+                          out=torch.empty(n * 10, dtype=torch.float64, device="cuda"))
+    with pytest.raises(g.GeolikError):
+        g.matern_generate(ctx, xd, yd, xd, yd, theta, g.gl_opts_default(layout=7))
