@@ -26,6 +26,29 @@ namespace gl {
 
 constexpr int PB = 64;  // diagonal block edge
 
+// d = sqrt(p) and inv = 1/sqrt(p) for a pivot p > 0.  The generic binary64
+// square root and division are long dependent sequences on the critical
+// chain of the column loop below; here the hardware reciprocal square root
+// (about 2^-23 relative error) is refined by two coupled Newton steps of
+// Goldschmidt's iteration, g -> sqrt(p) and h -> 1/(2 sqrt(p)), each of which
+// squares the relative error, and the root gets one residual correction
+// d = g + (p - g²) h (Markstein's final step).  Both results are within a
+// few ulps of the correctly rounded values, well inside the spread of other
+// binary64 orderings of the factorisation.
+__device__ __forceinline__ void pivot_root(double p, double &d, double &inv)
+{
+    const double y = __builtin_amdgcn_rsq(p);
+    double g = p * y, h = 0.5 * y;
+    double r = fma(-g, h, 0.5);
+    g = fma(g, r, g);
+    h = fma(h, r, h);
+    r = fma(-g, h, 0.5);
+    g = fma(g, r, g);
+    h = fma(h, r, h);
+    d = fma(fma(-g, g, p), h, g);
+    inv = h + h;
+}
+
 // Factor the 64×64 block D held in Ds (Ds[c][r] = D[r][c], lower triangle
 // valid) as D = L Lᵀ in place and write X = L⁻¹ to Xi (Xi[c][r] = X[r][c];
 // its upper blocks must be zero on entry), in 16×16 sub-blocks, P = 0..3:
@@ -63,8 +86,8 @@ __device__ __forceinline__ bool factor_invert_64(double (*Ds)[PB + 1], double (*
             for (int c = 0; c < 16; ++c) {
                 const double piv = readlane_f64(a[c], c);
                 if (!(piv > 0.0) && fcol < 0) fcol = c;
-                const double d = sqrt(piv);
-                const double inv = 1.0 / d;
+                double d, inv;
+                pivot_root(piv, d, inv);
                 if (r16 == c) rv = inv;
                 a[c] = (r16 == c) ? d : a[c] * inv;
                 // column c through LDS (the wave's LDS accesses complete in
@@ -159,13 +182,125 @@ __device__ __forceinline__ bool factor_invert_64(double (*Ds)[PB + 1], double (*
     return true;
 }
 
-template <int B>
-__device__ __forceinline__ void potrf_body(double *__restrict__ tiles, int64_t k, int64_t n,
-                                           int64_t *__restrict__ info, double *__restrict__ logsum,
-                                           double *__restrict__ dinv)
+// b = 128: the whole lower tile fits in LDS (three 64×64 blocks: D0, the
+// rows below it, D1), so it is read once, both panels are factored there and
+// only the results go back; the steps and their arithmetic are those of
+// potrf_general below (a panel solve and one trailing update between the two
+// diagonal blocks), without the global-memory round trips between them.
+__device__ __forceinline__ void potrf_tile128(double *__restrict__ tiles, int64_t k, int64_t n,
+                                              int64_t *__restrict__ info, double *__restrict__ logsum,
+                                              double *__restrict__ dinv)
 {
-    if (*info != 0) return;
-    __builtin_amdgcn_s_setprio(3);  // critical path of the step schedule
+    constexpr int B = 128;
+    double *A = tiles + tile_offset(k, k, B);
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+    __shared__ double D0[PB][PB + 1];  // D0[c][r] = A[r][c]: first diagonal block, then L0
+    __shared__ double Pn[PB][PB + 1];  // Pn[c][r] = A[64 + r][c]: rows below, then the panel P
+    __shared__ double D1[PB][PB + 1];  // D1[c][r] = A[64 + r][64 + c]: second diagonal block
+    __shared__ double Xi[PB][PB + 1];
+    __shared__ double rdiag[PB];
+    __shared__ double colb[16];
+    __shared__ double red[4];
+    __shared__ int fail;
+
+    for (int e = tid; e < PB * PB; e += 256) {
+        const int c = e >> 6, r = e & 63;
+        D0[c][r] = A[(int64_t)c * B + r];
+        Pn[c][r] = A[(int64_t)c * B + PB + r];
+        D1[c][r] = A[(int64_t)(PB + c) * B + PB + r];
+        Xi[c][r] = 0.0;
+    }
+    if (tid == 0) fail = 0;
+    __syncthreads();
+    if (!factor_invert_64(D0, Xi, rdiag, colb, &fail, k * B, info)) return;
+    for (int e = tid; e < PB * PB; e += 256) {
+        const int c = e >> 6, r = e & 63;
+        if (r >= c) A[(int64_t)c * B + r] = D0[c][r];
+        dinv[c * PB + r] = Xi[c][r];
+    }
+    {
+        // panel P = A[64:128, 0:64] · D0⁻ᵀ, wave w owning rows 16w..16w+15; each
+        // wave reads its own rows of Pn before writing them
+        const int r0 = wave * 16;
+        double y[PB / 4];
+#pragma unroll
+        for (int kk = 0; kk < PB / 4; ++kk) y[kk] = Pn[4 * kk + (lane >> 4)][r0 + (lane & 15)];
+        d4 acc[4];
+#pragma unroll
+        for (int cb = 0; cb < 4; ++cb) {
+            acc[cb] = (d4){0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int kk = 0; kk < PB / 4; ++kk)
+                acc[cb] = mfma_f64(Xi[4 * kk + (lane >> 4)][cb * 16 + (lane & 15)], y[kk], acc[cb]);
+        }
+#pragma unroll
+        for (int cb = 0; cb < 4; ++cb)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int c = cb * 16 + mfma_row(lane, q), r = r0 + mfma_col(lane);
+                A[(int64_t)c * B + PB + r] = acc[cb][q];
+                Pn[c][r] = acc[cb][q];
+            }
+    }
+    __syncthreads();
+    // D1 -= P Pᵀ, lower triangle, in 32×32 blocks (0,0), (1,0), (1,1), K = 64 in two halves
+    if (wave < 3) {
+        const int bi = wave == 0 ? 0 : 1, bj = wave == 2 ? 1 : 0;
+        const int ra = bi * 32 + (lane & 15), rc = bj * 32 + (lane & 15);
+        d4 c00 = {0.0, 0.0, 0.0, 0.0}, c01 = c00, c10 = c00, c11 = c00;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            double a0[8], a1[8], b0[8], b1[8];
+#pragma unroll
+            for (int kk = 0; kk < 8; ++kk) {
+                const int col = 32 * h + 4 * kk + (lane >> 4);
+                a0[kk] = Pn[col][ra];
+                a1[kk] = Pn[col][ra + 16];
+                b0[kk] = Pn[col][rc];
+                b1[kk] = Pn[col][rc + 16];
+            }
+#pragma unroll
+            for (int kk = 0; kk < 8; ++kk) {
+                c00 = mfma_f64(b0[kk], a0[kk], c00);
+                c01 = mfma_f64(b1[kk], a0[kk], c01);
+                c10 = mfma_f64(b0[kk], a1[kk], c10);
+                c11 = mfma_f64(b1[kk], a1[kk], c11);
+            }
+        }
+        const int rr = bi * 32 + mfma_col(lane), cc = bj * 32;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int col = cc + mfma_row(lane, q);
+            D1[col][rr] -= c00[q];
+            D1[col + 16][rr] -= c01[q];
+            D1[col][rr + 16] -= c10[q];
+            D1[col + 16][rr + 16] -= c11[q];
+        }
+    }
+    for (int e = tid; e < PB * PB; e += 256) Xi[e >> 6][e & 63] = 0.0;
+    __syncthreads();
+    if (!factor_invert_64(D1, Xi, rdiag, colb, &fail, k * B + PB, info)) return;
+    for (int e = tid; e < PB * PB; e += 256) {
+        const int c = e >> 6, r = e & 63;
+        if (r >= c) A[(int64_t)(PB + c) * B + PB + r] = D1[c][r];
+        dinv[PB * PB + c * PB + r] = Xi[c][r];
+    }
+    // 2 Σ log L_rr over the rows that are not padding
+    double acc = 0.0;
+    if (tid < B && k * B + tid < n) acc = log(tid < PB ? D0[tid][tid] : D1[tid - PB][tid - PB]);
+    double w = wave_sum(acc);
+    if (lane == 0) red[wave] = w;
+    __syncthreads();
+    if (tid == 0) logsum[k] = 2.0 * ((red[0] + red[1]) + (red[2] + red[3]));
+}
+
+template <int B>
+__device__ __forceinline__ void potrf_general(double *__restrict__ tiles, int64_t k, int64_t n,
+                                              int64_t *__restrict__ info, double *__restrict__ logsum,
+                                              double *__restrict__ dinv)
+{
     double *A = tiles + tile_offset(k, k, B);
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -178,7 +313,9 @@ __device__ __forceinline__ void potrf_body(double *__restrict__ tiles, int64_t k
     __shared__ int fail;
 
     for (int s = 0; s < B; s += PB) {
-        for (int e = tid; e < PB * PB; e += 256) {
+#pragma unroll
+        for (int i = 0; i < PB * PB / 256; ++i) {
+            const int e = tid + 256 * i;
             const int c = e >> 6, r = e & 63;
             Ds[c][r] = A[(int64_t)(s + c) * B + s + r];
             Xi[c][r] = 0.0;  // D⁻¹ is lower triangular: the upper blocks stay zero
@@ -273,6 +410,17 @@ __device__ __forceinline__ void potrf_body(double *__restrict__ tiles, int64_t k
     if (lane == 0) red[wave] = w;
     __syncthreads();
     if (tid == 0) logsum[k] = 2.0 * ((red[0] + red[1]) + (red[2] + red[3]));
+}
+
+template <int B>
+__device__ __forceinline__ void potrf_body(double *__restrict__ tiles, int64_t k, int64_t n,
+                                           int64_t *__restrict__ info, double *__restrict__ logsum,
+                                           double *__restrict__ dinv)
+{
+    if (*info != 0) return;
+    __builtin_amdgcn_s_setprio(3);  // critical path of the step schedule
+    if constexpr (B == 128) potrf_tile128(tiles, k, n, info, logsum, dinv);
+    else potrf_general<B>(tiles, k, n, info, logsum, dinv);
 }
 
 template <int B>
