@@ -26,7 +26,11 @@ __device__ inline void tile_from_index(int64_t t, int64_t &i, int64_t &j)
 // consecutive threads write consecutive rows of one column.  When norm2 is not
 // NULL, the tile's squared Frobenius norm is written to norm2[t] by a
 // fixed-order block reduction.
-template <int B>
+// CLOSED: the smoothness is 1/2, 3/2 or 5/2 and the distance Euclidean
+// (checked by the launcher); the kernel then carries neither the Bessel
+// evaluator nor the great-circle trigonometry, which lets more waves share a
+// CU.  The values are those of the general kernel, bit for bit.
+template <int B, bool CLOSED = false>
 __device__ __forceinline__ void gen_tiles_body(double *__restrict__ tiles, const double *__restrict__ x,
                                                const double *__restrict__ y, int64_t n, gl_theta th, Geom geo,
                                                double *__restrict__ norm2, int64_t t)
@@ -34,14 +38,20 @@ __device__ __forceinline__ void gen_tiles_body(double *__restrict__ tiles, const
     int64_t ti, tj;
     tile_from_index(t, ti, tj);
     const MaternSetup ms = matern_setup(th.theta1, th.theta2, th.theta3);
-    __shared__ BesselTab tab;
     __shared__ double xcs[B], ycs[B];  // the tile's column locations
     for (int c = threadIdx.x; c < B; c += 256) {
         const int64_t gc = tj * B + c;
         xcs[c] = gc < n ? x[gc] : 0.0;
         ycs[c] = gc < n ? y[gc] : 0.0;
     }
-    bessel_tab_init(ms, tab);  // ends with the barrier the staging needs too
+    const BesselTab *tabp = nullptr;
+    if constexpr (CLOSED) {
+        __syncthreads();
+    } else {
+        __shared__ BesselTab tab;
+        bessel_tab_init(ms, tab);  // ends with the barrier the staging needs too
+        tabp = &tab;
+    }
     double *T = tiles + t * (int64_t)B * B;
     constexpr int RPT = (B + 255) / 256;
     double xr[RPT], yr[RPT];
@@ -65,8 +75,12 @@ __device__ __forceinline__ void gen_tiles_body(double *__restrict__ tiles, const
             int r = threadIdx.x + 256 * q;
             if (r >= B) continue;
             double v;
-            if (colok && gr[q] < n) v = matern_eval(ms, geo_dist(geo, xr[q], yr[q], xc, yc), &tab);
-            else v = (gr[q] == gc) ? 1.0 : 0.0;
+            if (colok && gr[q] < n) {
+                if constexpr (CLOSED) v = matern_eval_closed(ms, dist2d(xr[q], yr[q], xc, yc));
+                else v = matern_eval(ms, geo_dist(geo, xr[q], yr[q], xc, yc), tabp);
+            } else {
+                v = (gr[q] == gc) ? 1.0 : 0.0;
+            }
             T[(int64_t)c * B + r] = v;
             ss += v * v;
         }
@@ -80,24 +94,34 @@ __device__ __forceinline__ void gen_tiles_body(double *__restrict__ tiles, const
     }
 }
 
-template <int B>
+template <int B, bool CLOSED>
 __global__ __launch_bounds__(256) void gen_tiles_kernel(double *__restrict__ tiles,
                                                         const double *__restrict__ x,
                                                         const double *__restrict__ y, int64_t n,
                                                         gl_theta th, Geom geo, double *__restrict__ norm2)
 {
-    gen_tiles_body<B>(tiles, x, y, n, th, geo, norm2, blockIdx.x);
+    gen_tiles_body<B, CLOSED>(tiles, x, y, n, th, geo, norm2, blockIdx.x);
+}
+
+template <int B>
+static void launch_gen_tiles_b(double *tiles, const double *x, const double *y, int64_t n, int64_t nt,
+                               gl_theta th, Geom geo, double *norm2, hipStream_t s)
+{
+    dim3 grid((unsigned)tile_count(nt));
+    if (matern_setup(th.theta1, th.theta2, th.theta3).kind != 0 && geo.metric == GL_EUCLIDEAN)
+        gen_tiles_kernel<B, true><<<grid, 256, 0, s>>>(tiles, x, y, n, th, geo, norm2);
+    else
+        gen_tiles_kernel<B, false><<<grid, 256, 0, s>>>(tiles, x, y, n, th, geo, norm2);
 }
 
 void launch_gen_tiles(double *tiles, const double *x, const double *y, int64_t n, int b, int64_t nt,
                       gl_theta th, Geom geo, double *norm2, hipStream_t s)
 {
-    dim3 grid((unsigned)tile_count(nt));
     switch (b) {
-    case 128: gen_tiles_kernel<128><<<grid, 256, 0, s>>>(tiles, x, y, n, th, geo, norm2); break;
-    case 256: gen_tiles_kernel<256><<<grid, 256, 0, s>>>(tiles, x, y, n, th, geo, norm2); break;
-    case 384: gen_tiles_kernel<384><<<grid, 256, 0, s>>>(tiles, x, y, n, th, geo, norm2); break;
-    default: gen_tiles_kernel<512><<<grid, 256, 0, s>>>(tiles, x, y, n, th, geo, norm2); break;
+    case 128: launch_gen_tiles_b<128>(tiles, x, y, n, nt, th, geo, norm2, s); break;
+    case 256: launch_gen_tiles_b<256>(tiles, x, y, n, nt, th, geo, norm2, s); break;
+    case 384: launch_gen_tiles_b<384>(tiles, x, y, n, nt, th, geo, norm2, s); break;
+    default: launch_gen_tiles_b<512>(tiles, x, y, n, nt, th, geo, norm2, s); break;
     }
 }
 

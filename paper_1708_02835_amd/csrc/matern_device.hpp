@@ -186,6 +186,27 @@ __host__ __device__ inline void bessel_k_miller_scaled(const MaternSetup &s, dou
     k1 = k0 * (s.mu + 0.5 + x - (0.25 - mu2) * r0) / x;
 }
 
+// The half-integer closed forms at x = r/θ2 (s.kind 1, 2, 3).
+__host__ __device__ inline double matern_closed(const MaternSetup &s, double x)
+{
+    switch (s.kind) {
+    case 1: return s.theta1 * exp(-x);
+    case 2: return s.theta1 * (1.0 + x) * exp(-x);
+    default: return s.theta1 * (1.0 + x + x * x / 3.0) * exp(-x);
+    }
+}
+
+// Matérn covariance at distance r for a half-integer setup (s.kind != 0):
+// the same values as matern_eval, without the Bessel evaluator (so kernels
+// that only take this path keep few registers).
+__host__ __device__ inline double matern_eval_closed(const MaternSetup &s, double r)
+{
+    if (r == 0.0) return s.theta1;
+    const double x = r / s.theta2;
+    if (x > 2000.0) return 0.0;
+    return matern_closed(s, x);
+}
+
 // Matérn covariance at distance r (r >= 0); tab (may be NULL) from
 // bessel_tab_init for the same setup.
 __host__ __device__ inline double matern_eval(const MaternSetup &s, double r, const BesselTab *tab = nullptr)
@@ -196,12 +217,7 @@ __host__ __device__ inline double matern_eval(const MaternSetup &s, double r, co
     // so C underflows to 0 for any finite θ1; returning early also keeps
     // the closed forms' polynomials and the recurrences below finite.
     if (x > 2000.0) return 0.0;
-    switch (s.kind) {
-    case 1: return s.theta1 * exp(-x);
-    case 2: return s.theta1 * (1.0 + x) * exp(-x);
-    case 3: return s.theta1 * (1.0 + x + x * x / 3.0) * exp(-x);
-    default: break;
-    }
+    if (s.kind != 0) return matern_closed(s, x);
     // Below 1e-150 the distance is far inside rounding of a repeated location;
     // the clamp keeps K_μ+1 (about x^-3/2 at most) and the scaled recurrence
     // below finite.

@@ -313,9 +313,7 @@ __device__ __forceinline__ void potrf_general(double *__restrict__ tiles, int64_
     __shared__ int fail;
 
     for (int s = 0; s < B; s += PB) {
-#pragma unroll
-        for (int i = 0; i < PB * PB / 256; ++i) {
-            const int e = tid + 256 * i;
+        for (int e = tid; e < PB * PB; e += 256) {
             const int c = e >> 6, r = e & 63;
             Ds[c][r] = A[(int64_t)(s + c) * B + s + r];
             Xi[c][r] = 0.0;  // D⁻¹ is lower triangular: the upper blocks stay zero
