@@ -150,22 +150,24 @@ void Work::set_views(int64_t n_, int b_, int precision_)
 int Lanes::create()
 {
     GL_HIP_TRY(hipStreamCreateWithFlags(&la, hipStreamNonBlocking));
+    GL_HIP_TRY(hipStreamCreateWithFlags(&sv, hipStreamNonBlocking));
     GL_HIP_TRY(hipEventCreateWithFlags(&fork, hipEventDisableTiming));
     GL_HIP_TRY(hipEventCreateWithFlags(&panel, hipEventDisableTiming));
     GL_HIP_TRY(hipEventCreateWithFlags(&bulk, hipEventDisableTiming));
     GL_HIP_TRY(hipEventCreateWithFlags(&join, hipEventDisableTiming));
+    GL_HIP_TRY(hipEventCreateWithFlags(&ready, hipEventDisableTiming));
+    GL_HIP_TRY(hipEventCreateWithFlags(&solved, hipEventDisableTiming));
     return GL_OK;
 }
 
 void Lanes::destroy()
 {
     if (la) hipStreamDestroy(la);
-    if (fork) hipEventDestroy(fork);
-    if (panel) hipEventDestroy(panel);
-    if (bulk) hipEventDestroy(bulk);
-    if (join) hipEventDestroy(join);
-    la = nullptr;
-    fork = panel = bulk = join = nullptr;
+    if (sv) hipStreamDestroy(sv);
+    for (hipEvent_t e : {fork, panel, bulk, join, ready, solved})
+        if (e) (void)hipEventDestroy(e);
+    la = sv = nullptr;
+    fork = panel = bulk = join = ready = solved = nullptr;
 }
 
 hipEvent_t Prof::take()
@@ -266,6 +268,7 @@ int factorize(Lanes &ln, Work &w, hipStream_t s, bool solve, int64_t near, bool 
     hipStream_t la = ln.la;
     GL_HIP_TRY(hipEventRecord(ln.fork, s));
     GL_HIP_TRY(hipStreamWaitEvent(la, ln.fork, 0));
+    if (solve) GL_HIP_TRY(hipStreamWaitEvent(ln.sv, ln.fork, 0));
     const double b3 = (double)w.b * w.b * w.b;
     int64_t js = w.nt;  // columns >= js take the current pair of panels in one pass
     for (int64_t k = 0; k < w.nt; ++k) {
@@ -276,14 +279,12 @@ int factorize(Lanes &ln, Work &w, hipStream_t s, bool solve, int64_t near, bool 
         timed(ln.prof, GL_PHASE_TRSM, b3 * below, s,
               [&] { launch_trsm(w.tiles, w.b, w.nt, k, w.dinv_k(k), w.info, s); });
         // Panel k is final here: the bulk update may start.  The forward solve
-        // of step k only reads column k (and owns v), so it follows the panel
-        // event, off the path that feeds the lookahead stream.
+        // of step k reads only column k, which no later step changes, and
+        // owns v: it runs on its own stream, off the critical path.
         if (k + 1 < w.nt) GL_HIP_TRY(hipEventRecord(ln.panel, s));
         if (solve) {
-            timed(ln.prof, GL_PHASE_SOLVE, (double)w.b * w.b, s,
-                  [&] { launch_fwd_diag(w.tiles, w.b, k, w.n, w.v, w.quad, w.dinv_k(k), w.info, s); });
-            timed(ln.prof, GL_PHASE_SOLVE, 2.0 * w.b * w.b * below, s,
-                  [&] { launch_fwd_update(w.tiles, w.b, w.nt, k, w.v, w.info, s); });
+            const int rc = solve_step(ln, w, k, s);
+            if (rc != GL_OK) return rc;
         }
         if (k + 1 < w.nt) {
             const bool odd = (k & 1) != 0;
@@ -307,6 +308,25 @@ int factorize(Lanes &ln, Work &w, hipStream_t s, bool solve, int64_t near, bool 
     GL_HIP_TRY(hipGetLastError());
     GL_HIP_TRY(hipEventRecord(ln.join, la));
     GL_HIP_TRY(hipStreamWaitEvent(s, ln.join, 0));
+    return solve ? solve_join(ln, s) : GL_OK;
+}
+
+int solve_step(Lanes &ln, Work &w, int64_t k, hipStream_t s)
+{
+    GL_HIP_TRY(hipEventRecord(ln.ready, s));
+    GL_HIP_TRY(hipStreamWaitEvent(ln.sv, ln.ready, 0));
+    const double below = (double)(w.nt - k - 1);
+    timed(ln.prof, GL_PHASE_SOLVE, (double)w.b * w.b, ln.sv,
+          [&] { launch_fwd_diag(w.tiles, w.b, k, w.n, w.v, w.quad, w.dinv_k(k), w.info, ln.sv); });
+    timed(ln.prof, GL_PHASE_SOLVE, 2.0 * w.b * w.b * below, ln.sv,
+          [&] { launch_fwd_update(w.tiles, w.b, w.nt, k, w.v, w.info, ln.sv); });
+    return GL_OK;
+}
+
+int solve_join(Lanes &ln, hipStream_t s)
+{
+    GL_HIP_TRY(hipEventRecord(ln.solved, ln.sv));
+    GL_HIP_TRY(hipStreamWaitEvent(s, ln.solved, 0));
     return GL_OK;
 }
 

@@ -89,8 +89,10 @@ struct Prof {
 // Side stream and events of one evaluation's step schedule (lookahead).
 struct Lanes {
     Prof *prof = nullptr;
-    hipStream_t la = nullptr;
+    hipStream_t la = nullptr;  // bulk trailing updates (lookahead)
+    hipStream_t sv = nullptr;  // forward solve, off the critical path
     hipEvent_t fork = nullptr, panel = nullptr, bulk = nullptr, join = nullptr;
+    hipEvent_t ready = nullptr, solved = nullptr;  // column k final (for sv); sv drained
     int create();
     void destroy();
 };
@@ -101,6 +103,12 @@ bool valid_theta_for(const gl_theta &t, const gl_opts &o);
 size_t work_bytes(int64_t n, int b, int precision);
 // first_done: the POTRF of tile 0 has already run (logsum[0], dinv of step 0).
 int factorize(Lanes &ln, Work &w, hipStream_t s, bool solve, int64_t near, bool first_done = false);
+// Forward solve of step k (diagonal block and the update of the rows below)
+// on ln.sv once the work queued on s so far (column k final) is done; the
+// caller has made ln.sv wait for the inputs.  solve_join makes s wait for
+// every solve step queued.
+int solve_step(Lanes &ln, Work &w, int64_t k, hipStream_t s);
+int solve_join(Lanes &ln, hipStream_t s);
 // Tiles updated one panel at a time at even steps (gl_opts.near_tiles; 0:
 // b tiles, about 2.6 ms of binary64 update at tile 512).
 int64_t near_tiles_for(int b, int32_t requested);

@@ -893,12 +893,14 @@ int mixed_factorize(Lanes &ln, Work &w, gl_theta th, const gl_opts &o, hipStream
     int64_t js = w.nt;  // columns >= js take the current pair of panels in one update
     GL_HIP_TRY(hipEventRecord(ln.fork, s));
     GL_HIP_TRY(hipStreamWaitEvent(la, ln.fork, 0));
+    GL_HIP_TRY(hipStreamWaitEvent(ln.sv, ln.fork, 0));
     for (int64_t k = 0; k < w.nt; ++k) {
         if (k > 0) launch_potrf(w.tiles, w.b, k, w.n, w.info, w.logsum, w.dinv_k(k), s);
-        launch_fwd_diag(w.tiles, w.b, k, w.n, w.v, w.quad, w.dinv_k(k), w.info, s);
         launch_delta_flush(w, k, s);
         launch_trsm(w.tiles, w.b, w.nt, k, w.dinv_k(k), w.info, s);
-        launch_fwd_update(w.tiles, w.b, w.nt, k, w.v, w.info, s);
+        // column k is final: its forward solve runs on the solve stream
+        rc = solve_step(ln, w, k, s);
+        if (rc != GL_OK) return rc;
         if (k + 1 < w.nt) {
             // Split-product classes take two steps per update of their running
             // sums.  At an even step k the next column gets panel k (the
@@ -937,7 +939,7 @@ int mixed_factorize(Lanes &ln, Work &w, gl_theta th, const gl_opts &o, hipStream
     GL_HIP_TRY(hipGetLastError());
     GL_HIP_TRY(hipEventRecord(ln.join, la));
     GL_HIP_TRY(hipStreamWaitEvent(s, ln.join, 0));
-    return GL_OK;
+    return solve_join(ln, s);
 }
 
 }  // namespace gl
