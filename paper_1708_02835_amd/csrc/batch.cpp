@@ -9,7 +9,7 @@ int enqueue_step(BatchReq *d, BatchReq *dev, int count, int b, hipStream_t s, in
 {
     int64_t o_stage = 0, o_gen = 0, o_trsm = 0, o_tr = 0;
     const int64_t sub = (int64_t)(b / 128) * (b / 128);
-    bool any_new = false, any_fin = false;
+    bool any_new = false, any_fin = false, euclid = true;
     for (int i = 0; i < count; ++i) {
         BatchReq &q = d[i];
         q.o_stage = o_stage;
@@ -20,6 +20,7 @@ int enqueue_step(BatchReq *d, BatchReq *dev, int count, int b, hipStream_t s, in
             o_stage += ceil_div(q.npad, 256);
             o_gen += tile_count(q.nt);
             any_new = true;
+            euclid = euclid && q.geo.metric == GL_EUCLIDEAN;
         }
         const int64_t m = q.nt - q.k - 1;
         o_trsm += m * (b / 64);
@@ -30,7 +31,7 @@ int enqueue_step(BatchReq *d, BatchReq *dev, int count, int b, hipStream_t s, in
     int n = 0;
     if (any_new) {
         launch_stage_batched(dev, count, o_stage, s);
-        launch_gen_batched(b, dev, count, o_gen, s);
+        launch_gen_batched(b, dev, count, o_gen, euclid, s);
         n += 2;
     }
     launch_potrf_batched(b, dev, count, s);

@@ -33,7 +33,8 @@ struct BatchReq {
 // Launchers (b = 128, 256, 384, 512); grids come from the totals of the prefix
 // offsets.
 void launch_stage_batched(const BatchReq *d, int count, int64_t blocks, hipStream_t s);
-void launch_gen_batched(int b, const BatchReq *d, int count, int64_t tiles, hipStream_t s);
+// euclid: every request that generates in this launch uses the Euclidean distance.
+void launch_gen_batched(int b, const BatchReq *d, int count, int64_t tiles, bool euclid, hipStream_t s);
 void launch_potrf_batched(int b, const BatchReq *d, int count, hipStream_t s);
 void launch_fwd_diag_batched(int b, const BatchReq *d, int count, hipStream_t s);
 void launch_trsm_batched(int b, const BatchReq *d, int count, int64_t blocks, hipStream_t s);

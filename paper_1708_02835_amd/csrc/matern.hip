@@ -26,11 +26,14 @@ __device__ inline void tile_from_index(int64_t t, int64_t &i, int64_t &j)
 // consecutive threads write consecutive rows of one column.  When norm2 is not
 // NULL, the tile's squared Frobenius norm is written to norm2[t] by a
 // fixed-order block reduction.
-// CLOSED: the smoothness is 1/2, 3/2 or 5/2 and the distance Euclidean
-// (checked by the launcher); the kernel then carries neither the Bessel
-// evaluator nor the great-circle trigonometry, which lets more waves share a
-// CU.  The values are those of the general kernel, bit for bit.
-template <int B, bool CLOSED = false>
+// MODE (checked by the launchers): GEN_ANY any distance and smoothness;
+// GEN_EUCLID Euclidean distance, so the kernel carries no great-circle
+// trigonometry; GEN_CLOSED Euclidean distance and smoothness 1/2, 3/2 or
+// 5/2, so it carries no Bessel evaluator either.  Fewer registers let more
+// waves share a CU; the values are the same, bit for bit, in every mode.
+enum { GEN_ANY = 0, GEN_EUCLID = 1, GEN_CLOSED = 2 };
+
+template <int B, int MODE>
 __device__ __forceinline__ void gen_tiles_body(double *__restrict__ tiles, const double *__restrict__ x,
                                                const double *__restrict__ y, int64_t n, gl_theta th, Geom geo,
                                                double *__restrict__ norm2, int64_t t)
@@ -45,7 +48,7 @@ __device__ __forceinline__ void gen_tiles_body(double *__restrict__ tiles, const
         ycs[c] = gc < n ? y[gc] : 0.0;
     }
     const BesselTab *tabp = nullptr;
-    if constexpr (CLOSED) {
+    if constexpr (MODE == GEN_CLOSED) {
         __syncthreads();
     } else {
         __shared__ BesselTab tab;
@@ -76,7 +79,8 @@ __device__ __forceinline__ void gen_tiles_body(double *__restrict__ tiles, const
             if (r >= B) continue;
             double v;
             if (colok && gr[q] < n) {
-                if constexpr (CLOSED) v = matern_eval_closed(ms, dist2d(xr[q], yr[q], xc, yc));
+                if constexpr (MODE == GEN_CLOSED) v = matern_eval_closed(ms, dist2d(xr[q], yr[q], xc, yc));
+                else if constexpr (MODE == GEN_EUCLID) v = matern_eval(ms, dist2d(xr[q], yr[q], xc, yc), tabp);
                 else v = matern_eval(ms, geo_dist(geo, xr[q], yr[q], xc, yc), tabp);
             } else {
                 v = (gr[q] == gc) ? 1.0 : 0.0;
@@ -94,13 +98,13 @@ __device__ __forceinline__ void gen_tiles_body(double *__restrict__ tiles, const
     }
 }
 
-template <int B, bool CLOSED>
+template <int B, int MODE>
 __global__ __launch_bounds__(256) void gen_tiles_kernel(double *__restrict__ tiles,
                                                         const double *__restrict__ x,
                                                         const double *__restrict__ y, int64_t n,
                                                         gl_theta th, Geom geo, double *__restrict__ norm2)
 {
-    gen_tiles_body<B, CLOSED>(tiles, x, y, n, th, geo, norm2, blockIdx.x);
+    gen_tiles_body<B, MODE>(tiles, x, y, n, th, geo, norm2, blockIdx.x);
 }
 
 template <int B>
@@ -108,10 +112,12 @@ static void launch_gen_tiles_b(double *tiles, const double *x, const double *y, 
                                gl_theta th, Geom geo, double *norm2, hipStream_t s)
 {
     dim3 grid((unsigned)tile_count(nt));
-    if (matern_setup(th.theta1, th.theta2, th.theta3).kind != 0 && geo.metric == GL_EUCLIDEAN)
-        gen_tiles_kernel<B, true><<<grid, 256, 0, s>>>(tiles, x, y, n, th, geo, norm2);
+    if (geo.metric != GL_EUCLIDEAN)
+        gen_tiles_kernel<B, GEN_ANY><<<grid, 256, 0, s>>>(tiles, x, y, n, th, geo, norm2);
+    else if (matern_setup(th.theta1, th.theta2, th.theta3).kind != 0)
+        gen_tiles_kernel<B, GEN_CLOSED><<<grid, 256, 0, s>>>(tiles, x, y, n, th, geo, norm2);
     else
-        gen_tiles_kernel<B, false><<<grid, 256, 0, s>>>(tiles, x, y, n, th, geo, norm2);
+        gen_tiles_kernel<B, GEN_EUCLID><<<grid, 256, 0, s>>>(tiles, x, y, n, th, geo, norm2);
 }
 
 void launch_gen_tiles(double *tiles, const double *x, const double *y, int64_t n, int b, int64_t nt,
@@ -127,43 +133,58 @@ void launch_gen_tiles(double *tiles, const double *x, const double *y, int64_t n
 
 // The same, with θ read from device memory (replayed hipGraphs: the graph
 // stays valid while θ changes between replays).
-template <int B>
+template <int B, int MODE>
 __global__ __launch_bounds__(256) void gen_tiles_dev_kernel(double *__restrict__ tiles, const double *__restrict__ x,
                                                             const double *__restrict__ y, int64_t n,
                                                             const gl_theta *__restrict__ thp, Geom geo)
 {
-    gen_tiles_body<B>(tiles, x, y, n, *thp, geo, nullptr, blockIdx.x);
+    gen_tiles_body<B, MODE>(tiles, x, y, n, *thp, geo, nullptr, blockIdx.x);
+}
+
+template <int B>
+static void launch_gen_tiles_dev_b(double *tiles, const double *x, const double *y, int64_t n, int64_t nt,
+                                   const gl_theta *thp, Geom geo, hipStream_t s)
+{
+    dim3 grid((unsigned)tile_count(nt));
+    if (geo.metric == GL_EUCLIDEAN) gen_tiles_dev_kernel<B, GEN_EUCLID><<<grid, 256, 0, s>>>(tiles, x, y, n, thp, geo);
+    else gen_tiles_dev_kernel<B, GEN_ANY><<<grid, 256, 0, s>>>(tiles, x, y, n, thp, geo);
 }
 
 void launch_gen_tiles_dev(double *tiles, const double *x, const double *y, int64_t n, int b, int64_t nt,
                           const gl_theta *thp, Geom geo, hipStream_t s)
 {
-    dim3 grid((unsigned)tile_count(nt));
     switch (b) {
-    case 128: gen_tiles_dev_kernel<128><<<grid, 256, 0, s>>>(tiles, x, y, n, thp, geo); break;
-    case 256: gen_tiles_dev_kernel<256><<<grid, 256, 0, s>>>(tiles, x, y, n, thp, geo); break;
-    case 384: gen_tiles_dev_kernel<384><<<grid, 256, 0, s>>>(tiles, x, y, n, thp, geo); break;
-    default: gen_tiles_dev_kernel<512><<<grid, 256, 0, s>>>(tiles, x, y, n, thp, geo); break;
+    case 128: launch_gen_tiles_dev_b<128>(tiles, x, y, n, nt, thp, geo, s); break;
+    case 256: launch_gen_tiles_dev_b<256>(tiles, x, y, n, nt, thp, geo, s); break;
+    case 384: launch_gen_tiles_dev_b<384>(tiles, x, y, n, nt, thp, geo, s); break;
+    default: launch_gen_tiles_dev_b<512>(tiles, x, y, n, nt, thp, geo, s); break;
     }
 }
 
-template <int B>
+template <int B, int MODE>
 __global__ __launch_bounds__(256) void gen_batched_kernel(const BatchReq *__restrict__ d, int count)
 {
     const int64_t g = blockIdx.x;
     const int r = GL_BATCH_FIND(d, count, g, o_gen);
     const BatchReq &q = d[r];
-    gen_tiles_body<B>(q.tiles, q.x, q.y, q.n, q.th, q.geo, nullptr, g - q.o_gen);
+    gen_tiles_body<B, MODE>(q.tiles, q.x, q.y, q.n, q.th, q.geo, nullptr, g - q.o_gen);
 }
 
-void launch_gen_batched(int b, const BatchReq *d, int count, int64_t tiles, hipStream_t s)
+template <int B>
+static void launch_gen_batched_b(const BatchReq *d, int count, int64_t tiles, bool euclid, hipStream_t s)
+{
+    if (euclid) gen_batched_kernel<B, GEN_EUCLID><<<(unsigned)tiles, 256, 0, s>>>(d, count);
+    else gen_batched_kernel<B, GEN_ANY><<<(unsigned)tiles, 256, 0, s>>>(d, count);
+}
+
+void launch_gen_batched(int b, const BatchReq *d, int count, int64_t tiles, bool euclid, hipStream_t s)
 {
     if (tiles <= 0) return;
     switch (b) {
-    case 128: gen_batched_kernel<128><<<(unsigned)tiles, 256, 0, s>>>(d, count); break;
-    case 256: gen_batched_kernel<256><<<(unsigned)tiles, 256, 0, s>>>(d, count); break;
-    case 384: gen_batched_kernel<384><<<(unsigned)tiles, 256, 0, s>>>(d, count); break;
-    default: gen_batched_kernel<512><<<(unsigned)tiles, 256, 0, s>>>(d, count); break;
+    case 128: launch_gen_batched_b<128>(d, count, tiles, euclid, s); break;
+    case 256: launch_gen_batched_b<256>(d, count, tiles, euclid, s); break;
+    case 384: launch_gen_batched_b<384>(d, count, tiles, euclid, s); break;
+    default: launch_gen_batched_b<512>(d, count, tiles, euclid, s); break;
     }
 }
 

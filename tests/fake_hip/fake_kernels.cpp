@@ -179,7 +179,7 @@ void launch_stage_batched(const BatchReq *d, int count, int64_t, hipStream_t s)
             launch_copy_pad(d[i].sz, d[i].n, d[i].v, d[i].npad, 0.0, s);
         }
 }
-void launch_gen_batched(int b, const BatchReq *d, int count, int64_t, hipStream_t s)
+void launch_gen_batched(int b, const BatchReq *d, int count, int64_t, bool, hipStream_t s)
 {
     for (int i = 0; i < count; ++i)
         if (d[i].is_new) launch_gen_tiles(d[i].tiles, d[i].x, d[i].y, d[i].n, b, d[i].nt, d[i].th, d[i].geo, nullptr, s);
