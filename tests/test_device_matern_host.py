@@ -27,9 +27,10 @@ def evaluator(tmp_path_factory):
                            "-I", os.path.join(ROOT, "paper_1708_02835_amd", "csrc"),
                            os.path.join(ROOT, "tests", "matern_host_eval.cpp"), "-o", str(exe)])
 
-    def run(pairs):
+    def run(pairs, closed=False):
         inp = "".join(f"{nu!r} {x!r}\n" for nu, x in pairs)
-        out = subprocess.run([str(exe)], input=inp, capture_output=True, text=True, check=True).stdout
+        args = [str(exe)] + (["closed"] if closed else [])
+        out = subprocess.run(args, input=inp, capture_output=True, text=True, check=True).stdout
         return [float(v) for v in out.split()]
     return run
 
@@ -81,3 +82,19 @@ def test_device_evaluator_far_field(evaluator):
     assert all(v == 0.0 for v in evaluator(far))
     for nu in (0.5, 1.5, 2.5, 50.0):
         assert _ref(nu, 2000.0) == 0.0
+
+
+def test_half_integer_evaluator_matches_general_bit_for_bit(evaluator):
+    """The specialised tile generator (half-integer smoothness, Euclidean
+    distance) evaluates matern_eval_closed; it must give the general
+    evaluator's values exactly, including r = 0 and the far-field cut."""
+    xs = [0.0] + list(np.geomspace(1e-12, 2500.0, 301)) + [1.0, 2.0, 2000.0, 2000.0000001]
+    for nu in (0.5, 1.5, 2.5):
+        pairs = [(nu, x) for x in xs]
+        general, closed = evaluator(pairs), evaluator(pairs, closed=True)
+        assert all(a == b for a, b in zip(general, closed)), nu
+        ref = [float(mpmath.mpf(2) ** (1 - nu) / mpmath.gamma(nu) * mpmath.mpf(x) ** nu * mpmath.besselk(nu, x))
+               if 0 < x <= 700 else None for x in xs]
+        for x, v, r in zip(xs, closed, ref):
+            if r is not None and r >= NORMAL_MIN:
+                assert abs(v - r) <= _tol(nu, x) * r, (nu, x, v, r)
