@@ -411,8 +411,9 @@ int gl_selftest(gl_context *ctx, int32_t which, double *out_h, int64_t cap);
  * kernel launches of the direct calls are bracketed by HIP events on the
  * stream they run on: on = 1 the trailing updates only (the dominant kernel
  * family), on = 2 every phase below; 0 switches timing off.  Mixed-precision
- * evaluations are timed in no phase.  Phases run on two streams (critical
- * path and lookahead), so summed durations may exceed the wall time. */
+ * evaluations are timed in no phase.  Phases run on three streams (critical
+ * path, lookahead and forward solve), so summed durations may exceed the
+ * wall time. */
 enum {
     GL_PHASE_GEN = 0,        /* Σ(θ) tile generation (Eq. 2) */
     GL_PHASE_POTRF = 1,      /* diagonal-tile factorisations (b³/3 flops each) */

@@ -385,8 +385,8 @@ void retire_ticks(lq_queue *q, Cohort &co)
 }
 
 
-// A slot's stream, lookahead lane, event and pinned result are created on
-// its first request.  The usual serving load (binary64, n <= small_n) runs
+// A slot's stream, its lane (lookahead and forward-solve streams), event and
+// pinned result are created on its first request.  The usual serving load (binary64, n <= small_n) runs
 // through the fused launches on the two cohort streams only, so a queue adds
 // two streams to the process, within the four hardware queues a process gets
 // by default, and the cohorts do not share a hardware queue with idle slots.
