@@ -14,7 +14,8 @@ TFLOP/s (n³/3 per step), the trailing-update kernel's live roofline fraction
 the lookahead stream and the critical-column launches) with its HBM traffic
 from the committed counter record, and the oracle timed on one host core as
 the CPU baseline.  Legs outside the timed region, each skippable: mixed
-precision against FP64 at the same size for two θ, the independent-blocks
+precision against FP64 at the same size for two θ (with each precision
+class's in-situ matrix-core rate from per-class launch timing), the independent-blocks
 approximation per super-tile size (l, and 10-fold prediction MSE against the
 exact prediction), small-n latency with and without graph replay,
 maximum-likelihood estimates FP64 vs mixed, the 1,600-point evaluation
@@ -174,6 +175,39 @@ def measured_traffic(n: int, tile: int):
     return rec["hbm_bytes_per_launch"]
 
 
+# Dense matrix-core peaks (TFLOP/s) of the arithmetic each precision class
+# runs on, and the products one of its tile updates takes.
+CLASS_PEAK = {"fp64": 78.6, "fp32": 157.3, "bf16x6": 2500.0, "bf16x3": 2500.0, "bf16": 2500.0,
+              "fp16x3": 2500.0, "fp16": 2500.0}
+CLASS_PRODUCTS = {"fp64": 1, "fp32": 1, "bf16x6": 6, "bf16x3": 3, "bf16": 1, "fp16x3": 3, "fp16": 1}
+
+
+def class_utilisation(g, ctx, xd, yd, z, th, prec, tile):
+    """One more evaluation with the trailing updates timed per precision class
+    (HIP events around each launch): summed launch ms, algorithmic flops
+    (2b³ per tile update), TFLOP/s and the fraction of the class's matrix
+    peak, algorithmically and counting the products of the split classes.
+    Launches of different streams overlap, so the per-class figures are
+    in-situ rates, not a split of the wall time."""
+    g.gl_profile_enable(ctx, 1)
+    try:
+        g.loglik_eval(ctx, xd, yd, z, th, g.gl_opts_default(precision=prec, tile=tile))
+        ph = g.gl_profile_phases(ctx)
+    finally:
+        g.gl_profile_enable(ctx, 0)
+    out = {}
+    for cls in g.PRECISION_CLASSES:
+        v = ph["mixed_" + cls]
+        if not v["launches"]:
+            continue
+        tf = v["flops"] / (v["ms"] * 1e-3) / 1e12
+        out[cls] = {"launches": v["launches"], "ms": v["ms"], "flops": v["flops"], "tflops": tf,
+                    "peak_tflops": CLASS_PEAK[cls], "frac_of_peak": tf / CLASS_PEAK[cls],
+                    "products_per_update": CLASS_PRODUCTS[cls],
+                    "frac_of_peak_counting_products": tf * CLASS_PRODUCTS[cls] / CLASS_PEAK[cls]}
+    return out
+
+
 def mixed_legs(g, ctx, xd, yd, ed, zd, theta, theta_b, args, res64, t64, log):
     """Time-to-l(θ) of the mixed-precision modes against FP64 at the same
     size, with the relative error of l and log|Σ| against the FP64 result,
@@ -215,6 +249,8 @@ def mixed_legs(g, ctx, xd, yd, ed, zd, theta, theta_b, args, res64, t64, log):
                          "work_frac": {k: round(stats[k]["work_frac"], 4) for k in g.PRECISION_CLASSES},
                          "thresholds": stats["thresholds"]}
             log(f"mixed {label} {name}: {dt:.3f} s, x{t64b / dt:.2f}, rel err {leg[name]['rel_err_loglik']:.2e}")
+            if label == "theta_a":
+                leg[name]["class_util"] = class_utilisation(g, ctx, xd, yd, z, th, prec, args.tile)
         if label == "theta_b":
             # Why the adaptive rule keeps θ_b in binary64: forcing the
             # FP32-grade two-part binary16 class on the tiles with normalised

@@ -407,13 +407,15 @@ int gl_precision_stats(gl_context *ctx, int64_t *tiles_h, double *work_h, double
  * 3 = FP16 16x16x32. */
 int gl_selftest(gl_context *ctx, int32_t which, double *out_h, int64_t cap);
 
-/* Kernel timing of binary64 evaluations by phase of Alg. 2.  While enabled,
- * kernel launches of the direct calls are bracketed by HIP events on the
- * stream they run on: on = 1 the trailing updates only (the dominant kernel
- * family), on = 2 every phase below; 0 switches timing off.  Mixed-precision
- * evaluations are timed in no phase.  Phases run on three streams (critical
- * path, lookahead and forward solve), so summed durations may exceed the
- * wall time. */
+/* Kernel timing by phase of Alg. 2.  While enabled, kernel launches of the
+ * direct calls are bracketed by HIP events on the stream they run on: on = 1
+ * the trailing updates only (the dominant kernel family), on = 2 every phase
+ * below; 0 switches timing off.  In the mixed-precision modes only the
+ * trailing updates are timed, by precision class (the GL_PHASE_MIXED_*
+ * phases: one per class of gl_precision_stats, binary64 to one-part
+ * binary16; a mixed call whose tiles all stay binary64 runs, and is timed
+ * as, the binary64 schedule).  Phases run on three streams (critical path, lookahead and
+ * forward solve), so summed durations may exceed the wall time. */
 enum {
     GL_PHASE_GEN = 0,        /* Σ(θ) tile generation (Eq. 2) */
     GL_PHASE_POTRF = 1,      /* diagonal-tile factorisations (b³/3 flops each) */
@@ -424,16 +426,23 @@ enum {
     GL_PHASE_REDUCE = 6,     /* log|Σ|, ZᵀΣ⁻¹Z and l(θ) (Eq. 1) */
     GL_PHASE_TRAIL_PAIR = 7, /* trailing updates of the far columns by two panels in one pass
                                 (lookahead stream; see gl_opts.near_tiles) */
-    GL_NPHASE = 8
+    GL_PHASE_MIXED_FP64 = 8,   /* mixed modes: trailing updates of the binary64 class */
+    GL_PHASE_MIXED_FP32 = 9,   /* ... the FP32 class */
+    GL_PHASE_MIXED_BF16X6 = 10, /* ... three bfloat16 parts, six products */
+    GL_PHASE_MIXED_BF16X3 = 11, /* ... two bfloat16 parts, three products */
+    GL_PHASE_MIXED_BF16 = 12,   /* ... one bfloat16 part */
+    GL_PHASE_MIXED_FP16X3 = 13, /* ... two scaled binary16 parts, three products */
+    GL_PHASE_MIXED_FP16 = 14,   /* ... one scaled binary16 part */
+    GL_NPHASE = 15
 };
 int gl_profile_enable(gl_context *ctx, int32_t on);
 /* Synchronises the device and returns, per phase (GL_NPHASE values each; any
  * pointer may be NULL), the summed launch durations (ms), the algorithmic
  * flops of those launches (trailing: 2b³ per off-diagonal tile update, b²(b+1)
- * per diagonal tile update; generation and reduction: 0) and the launch count
- * since the last read, then resets them. */
+ * per diagonal tile update, whatever the precision class; generation and
+ * reduction: 0) and the launch count since the last read, then resets them. */
 int gl_profile_phases(gl_context *ctx, double *ms_h, double *flops_h, int64_t *launches_h);
-/* The same for the three trailing phases together (one value each). */
+/* The same for the three binary64 trailing phases together (one value each). */
 int gl_profile_read(gl_context *ctx, double *ms_h, double *flops_h, int64_t *launches_h);
 
 #ifdef __cplusplus

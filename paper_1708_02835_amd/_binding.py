@@ -465,7 +465,9 @@ def gl_selftest(ctx: Context, which: int):
     return np.frombuffer(out, dtype=np.float64).copy()
 
 
-PHASES = ("gen", "potrf", "trsm", "solve", "trail_crit", "trail_bulk", "reduce", "trail_pair")  # GL_PHASE_* order
+PHASES = ("gen", "potrf", "trsm", "solve", "trail_crit", "trail_bulk", "reduce", "trail_pair",
+          "mixed_fp64", "mixed_fp32", "mixed_bf16x6", "mixed_bf16x3", "mixed_bf16", "mixed_fp16x3",
+          "mixed_fp16")  # GL_PHASE_* order
 
 
 def gl_profile_enable(ctx: Context, on=True) -> None:

@@ -207,20 +207,6 @@ void Prof::end(hipStream_t s, Mark &m, int phase, double flops)
     pending.push_back(m);
 }
 
-// Runs launch() on s, bracketed by timing events when phase is profiled.
-template <class F>
-static void timed(Prof *prof, int phase, double flops, hipStream_t s, F &&launch)
-{
-    if (!prof || !prof->wants(phase)) {
-        launch();
-        return;
-    }
-    Prof::Mark m;
-    prof->begin(s, m);
-    launch();
-    prof->end(s, m, phase, flops);
-}
-
 // Algorithmic flops of the trailing update of step k over tile columns
 // jbeg..jend: 2b³ per off-diagonal tile, b²(b+1) per diagonal tile.
 static double trailing_flops(int64_t nt, int64_t jbeg, int64_t jend, int b)

@@ -79,12 +79,27 @@ struct Prof {
     bool all = false;           // every phase; otherwise the trailing updates only
     bool wants(int phase) const
     {
-        return all || phase == GL_PHASE_TRAIL_CRIT || phase == GL_PHASE_TRAIL_BULK || phase == GL_PHASE_TRAIL_PAIR;
+        return all || phase == GL_PHASE_TRAIL_CRIT || phase == GL_PHASE_TRAIL_BULK || phase == GL_PHASE_TRAIL_PAIR ||
+               phase >= GL_PHASE_MIXED_FP64;
     }
     hipEvent_t take();
     void begin(hipStream_t s, Mark &m);
     void end(hipStream_t s, Mark &m, int phase, double flops);
 };
+
+// Runs launch() on s, bracketed by timing events when phase is profiled.
+template <class F>
+void timed(Prof *prof, int phase, double flops, hipStream_t s, F &&launch)
+{
+    if (!prof || !prof->wants(phase)) {
+        launch();
+        return;
+    }
+    Prof::Mark m;
+    prof->begin(s, m);
+    launch();
+    prof->end(s, m, phase, flops);
+}
 
 // Side stream and events of one evaluation's step schedule (lookahead).
 struct Lanes {

@@ -842,16 +842,25 @@ static int build_lists(Work &w, const gl_opts &o, hipStream_t s, MixedPlan &plan
 // and the split-product classes with panels k-1 and k.
 enum { UPD_ALL = 0, UPD_STEP = 1, UPD_PAIR = 2 };
 
-static void class_updates(Work &w, int64_t k, int64_t j0, int64_t j1, const MixedPlan &plan, bool critical,
-                          int sel, hipStream_t s)
+// Timed (when profiling) in the class's phase with its algorithmic flops:
+// 2b³ per off-diagonal tile update and b²(b+1) per diagonal one (every
+// column's diagonal tile is in the band, so binary64), twice that with two
+// panels.
+static void class_updates(Lanes &ln, Work &w, int64_t k, int64_t j0, int64_t j1, const MixedPlan &plan,
+                          bool critical, int sel, hipStream_t s)
 {
+    const double b = (double)w.b, b3 = b * b * b;
     for (int c = 0; c < NCLASS; ++c) {
         if (sel == UPD_STEP && paired_class(c)) continue;
         const bool pair = sel == UPD_PAIR && paired_class(c);
         const int64_t a = plan.start[c][j0], e = plan.start[c][j1 + 1];
-        if (e > a)
+        if (e <= a) continue;
+        const double ndiag = c == C64 ? (double)(j1 - j0 + 1) : 0.0;
+        const double flops = (pair ? 2.0 : 1.0) * (2.0 * b3 * ((double)(e - a) - ndiag) + b * b * (b + 1.0) * ndiag);
+        timed(ln.prof, GL_PHASE_MIXED_FP64 + c, flops, s, [&] {
             launch_class_any(w.b, c, w.tiles, k, w.mv, w.mv.lists + plan.base[c] + a, e - a, w.info, critical, pair,
                              s);
+        });
     }
 }
 
@@ -922,15 +931,15 @@ int mixed_factorize(Lanes &ln, Work &w, gl_theta th, const gl_opts &o, hipStream
             launch_panel_convert(w, k, w.mv, s);
             GL_HIP_TRY(hipEventRecord(ln.panel, s));
             if (k > 0 && !even_wait) GL_HIP_TRY(hipStreamWaitEvent(s, ln.bulk, 0));
-            class_updates(w, k, k + 1, k + 1, plan, true, (odd && k + 1 >= js) ? UPD_PAIR : UPD_ALL, s);
+            class_updates(ln, w, k, k + 1, k + 1, plan, true, (odd && k + 1 >= js) ? UPD_PAIR : UPD_ALL, s);
             if (k + 2 < w.nt) {
                 GL_HIP_TRY(hipStreamWaitEvent(la, ln.panel, 0));
                 if (!pairs) {
-                    class_updates(w, k, k + 2, w.nt - 1, plan, false, UPD_ALL, la);
+                    class_updates(ln, w, k, k + 2, w.nt - 1, plan, false, UPD_ALL, la);
                 } else {
                     const int64_t split = std::max(js, k + 2);
-                    if (split > k + 2) class_updates(w, k, k + 2, split - 1, plan, false, UPD_ALL, la);
-                    if (split < w.nt) class_updates(w, k, split, w.nt - 1, plan, false, odd ? UPD_PAIR : UPD_STEP, la);
+                    if (split > k + 2) class_updates(ln, w, k, k + 2, split - 1, plan, false, UPD_ALL, la);
+                    if (split < w.nt) class_updates(ln, w, k, split, w.nt - 1, plan, false, odd ? UPD_PAIR : UPD_STEP, la);
                 }
                 GL_HIP_TRY(hipEventRecord(ln.bulk, la));
             }
