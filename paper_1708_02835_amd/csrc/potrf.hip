@@ -18,6 +18,11 @@
 // A non-positive (or NaN) pivot stores the 1-based global column in *info and
 // stops; every later kernel of the factorisation then returns immediately.
 // The tile's contribution 2 Σ log L_rr over rows r < n goes to logsum[k].
+// At b = 128 the whole tile stays in LDS between the steps (potrf_tile128).
+// The kernel runs beside the bulk trailing updates, so it starts only when a
+// CU has room for its registers and LDS: its footprint is kept at what the
+// general path needs (a fully unrolled block read raised the registers and
+// made some calls wait out a whole trailing launch).
 #include "batch.hpp"
 #include "common.hpp"
 #include "mfma.hpp"
