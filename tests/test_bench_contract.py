@@ -55,3 +55,39 @@ def test_fit_cubic_recovers_exact_coefficients():
     import bench
     a, b = bench.fit_cubic((100, 200, 300), [2e-9 * n ** 3 + 3e-7 * n ** 2 for n in (100, 200, 300)])
     assert abs(a - 2e-9) < 1e-15 and abs(b - 3e-7) < 1e-12
+
+
+def test_class_utilisation_arithmetic():
+    """The mixed legs' per-class rates from stand-in phase timings: TFLOP/s
+    from algorithmic flops and summed launch time, fractions of the class's
+    matrix peak with and without the split classes' extra products, classes
+    without launches left out, timing switched off afterwards."""
+    sys.path.insert(0, ROOT)
+    import bench
+
+    class FakeG:
+        PRECISION_CLASSES = ("fp64", "fp32", "bf16x6", "bf16x3", "bf16", "fp16x3", "fp16")
+        calls = []
+
+        def gl_profile_enable(self, ctx, on):
+            self.calls.append(on)
+
+        def gl_opts_default(self, **kw):
+            return kw
+
+        def loglik_eval(self, *a):
+            return {}
+
+        def gl_profile_phases(self, ctx):
+            ph = {"mixed_" + c: {"ms": 0.0, "flops": 0.0, "launches": 0} for c in self.PRECISION_CLASSES}
+            ph["mixed_fp64"] = {"ms": 10.0, "flops": 0.393e12, "launches": 4}   # 39.3 TFLOP/s
+            ph["mixed_fp16x3"] = {"ms": 100.0, "flops": 25e12, "launches": 7}  # 250 TFLOP/s
+            return ph
+
+    fg = FakeG()
+    out = bench.class_utilisation(fg, None, None, None, None, (1, 0.1, 0.5), 3, 512)
+    assert set(out) == {"fp64", "fp16x3"} and fg.calls == [1, 0]
+    assert abs(out["fp64"]["tflops"] - 39.3) < 1e-9 and abs(out["fp64"]["frac_of_peak"] - 0.5) < 1e-12
+    assert abs(out["fp16x3"]["tflops"] - 250.0) < 1e-9
+    assert abs(out["fp16x3"]["frac_of_peak"] - 0.1) < 1e-12
+    assert abs(out["fp16x3"]["frac_of_peak_counting_products"] - 0.3) < 1e-12
